@@ -1,0 +1,228 @@
+"""Oracle for the IDP-limited LGL-DGSEM on 2:1-balanced Cartesian quadtrees.
+
+TEST INFRASTRUCTURE ONLY.  A plain FP64 CPU implementation of the method, written
+from the paper (Bolm, Rueda-Ramirez, Kuzmin, Gassner: invariant-domain-preserving
+limiting with AMR for LGL-DGSEM).  Only the tests, the smoke check and the CPU
+baseline of the benchmark load it; the GPU library never does.  It shares no code
+with the GPU library.
+
+Parity status of each part is listed in the module docstrings of the C sources
+and in the pins under tests/.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libdgo.so")
+_lib = None
+
+RHS_HIGH, RHS_LOW = 0, 1
+DT_IDP, DT_LOWORDER = 0, 1
+LIM_NONE, LIM_POSITIVITY = 0, 1
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def _ptr(a, t=_D):
+    return a.ctypes.data_as(t)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_mesh_new.restype = ctypes.c_void_p
+        L.orc_mesh_new.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_char_p, ctypes.c_int]
+        L.orc_mesh_free.argtypes = [ctypes.c_void_p]
+        L.orc_mesh_num_mortars.restype = ctypes.c_int64
+        L.orc_mesh_num_mortars.argtypes = [ctypes.c_void_p]
+        L.orc_mesh_faces.argtypes = [ctypes.c_void_p, _I64]
+        L.orc_mesh_mortars.argtypes = [ctypes.c_void_p, _I64]
+        L.orc_mesh_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D]
+        L.orc_rhs.argtypes = [ctypes.c_void_p, _D, ctypes.c_int, ctypes.c_double, _D]
+        L.orc_max_dt.restype = ctypes.c_double
+        L.orc_max_dt.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_double]
+        L.orc_fe_step.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, _D, _D]
+        L.orc_ssprk3.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, _D]
+        L.orc_ssprk3_dt.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, _D]
+        L.orc_basis.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+        L.orc_mortar_ops.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_lagrange.restype = ctypes.c_double
+        L.orc_lagrange.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_legendre.restype = ctypes.c_double
+        L.orc_legendre.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_flux.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_double, _D]
+        L.orc_lnmean.restype = ctypes.c_double
+        L.orc_lnmean.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_overlap_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
+        L.orc_theta_pressure.restype = ctypes.c_double
+        L.orc_theta_pressure.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double]
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def set_threads(t):
+    """Set the OpenMP thread count of the oracle; returns the count in effect."""
+    return lib().orc_set_threads(int(t))
+
+
+def basis(N):
+    """LGL nodes, weights, derivative matrix D[a,k] = phi_k'(xi_a), Sbar (Sec. 2.1)."""
+    n = N + 1
+    xi, w = np.zeros(n), np.zeros(n)
+    D, S = np.zeros((n, n)), np.zeros((n, n))
+    if lib().orc_basis(N, _ptr(xi), _ptr(w), _ptr(D), _ptr(S)):
+        raise ValueError(N)
+    return xi, w, D, S
+
+
+def mortar_ops(N):
+    """Interpolation I[h,l,k], projection P[h,k,l], sparse weights Wt[k, h*n+l] (App. A)."""
+    n = N + 1
+    I, P, W = np.zeros((2, n, n)), np.zeros((2, n, n)), np.zeros((n, 2 * n))
+    lib().orc_mortar_ops(N, _ptr(I), _ptr(P), _ptr(W))
+    return I, P, W
+
+
+def overlap_weights(N, scale, shift):
+    """Overlap lengths of the reference face's LGL subcells with those of a face
+    scaled by `scale` and shifted by `shift` (eq. local_weights)."""
+    n = N + 1
+    out = np.zeros((n, n))
+    lib().orc_overlap_weights(N, scale, shift, _ptr(out))
+    return out
+
+
+def theta_pressure(u0, dc, pt, gamma):
+    """Largest theta in [0,1] with rho(u0 + theta dc) > 0 and p(u0 + theta dc) >= pt."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    dc = np.ascontiguousarray(dc, dtype=np.float64)
+    return lib().orc_theta_pressure(_ptr(u0), _ptr(dc), pt, gamma)
+
+
+def lagrange(N, k, s):
+    return lib().orc_lagrange(N, k, s)
+
+
+def legendre(m, s):
+    return lib().orc_legendre(m, s)
+
+
+def flux(kind, uL, uR, direction, gamma):
+    """kind: 'phys', 'llf', 'ranocha'."""
+    k = {"phys": 0, "llf": 1, "ranocha": 2}[kind]
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    f = np.zeros(4)
+    lib().orc_flux(k, _ptr(uL), _ptr(uR), direction, gamma, _ptr(f))
+    return f
+
+
+def lnmean(x, y):
+    return lib().orc_lnmean(x, y)
+
+
+STAT_KEYS = ("fv_inadmissible", "violations", "theta_vol_min", "theta_mort_min",
+             "alpha_vol_mean", "alpha_mort_mean", "dt")
+
+
+def _stats(a):
+    d = dict(zip(STAT_KEYS, a.tolist()))
+    d["fv_inadmissible"] = int(d["fv_inadmissible"])
+    d["violations"] = int(d["violations"])
+    return d
+
+
+class Mesh:
+    """A periodic quadtree mesh in the oracle, leaves given as (level, ix, iy)."""
+
+    def __init__(self, N, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0):
+        self.N, self.n = N, N + 1
+        self.level = np.ascontiguousarray(level, dtype=np.int8)
+        self.ix = np.ascontiguousarray(ix, dtype=np.int32)
+        self.iy = np.ascontiguousarray(iy, dtype=np.int32)
+        self.E = len(self.level)
+        self.box = (x0, y0, Lx, Ly, nx0, ny0)
+        err = ctypes.create_string_buffer(256)
+        self._h = lib().orc_mesh_new(N, self.E, self.level.ctypes.data, self.ix.ctypes.data,
+                                     self.iy.ctypes.data, x0, y0, Lx, Ly, nx0, ny0, err, 256)
+        if not self._h:
+            raise ValueError(err.value.decode())
+        self.M = lib().orc_mesh_num_mortars(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_mesh_free(self._h)
+            self._h = None
+
+    def faces(self):
+        out = np.zeros((self.E, 4, 4), dtype=np.int64)
+        lib().orc_mesh_faces(self._h, _ptr(out, _I64))
+        return out
+
+    def mortars(self):
+        out = np.zeros((max(self.M, 1), 4), dtype=np.int64)
+        lib().orc_mesh_mortars(self._h, _ptr(out, _I64))
+        return out[: self.M]
+
+    def geometry(self):
+        """Node coordinates x, y and masses m, each [E, n, n] indexed (e, b, a)."""
+        sh = (self.E, self.n, self.n)
+        x, y, m = np.zeros(sh), np.zeros(sh), np.zeros(sh)
+        lib().orc_mesh_geometry(self._h, _ptr(x), _ptr(y), _ptr(m))
+        return x, y, m
+
+    def state_shape(self):
+        return (self.E, 4, self.n, self.n)
+
+    def rhs(self, u, which=RHS_HIGH, gamma=1.4):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        du = np.zeros_like(u)
+        lib().orc_rhs(self._h, _ptr(u), which, gamma, _ptr(du))
+        return du
+
+    def max_dt(self, u, cfl, mode=DT_IDP, gamma=1.4):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        return lib().orc_max_dt(self._h, _ptr(u), cfl, mode, gamma)
+
+    def fe_step(self, u, dt, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        out = np.zeros_like(u)
+        st = np.zeros(len(STAT_KEYS))
+        rc = lib().orc_fe_step(self._h, _ptr(u), dt, gamma, beta, limiter, _ptr(out), _ptr(st))
+        d = _stats(st)
+        d["rc"] = rc
+        return out, d
+
+    def ssprk3(self, u, cfl, mode=DT_IDP, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
+        """One SSP-RK3 step; returns (new state, stats)."""
+        u = np.array(u, dtype=np.float64, order="C", copy=True)
+        st = np.zeros(len(STAT_KEYS))
+        rc = lib().orc_ssprk3(self._h, _ptr(u), cfl, mode, gamma, beta, limiter, _ptr(st))
+        d = _stats(st)
+        d["rc"] = rc
+        return u, d
+
+    def ssprk3_dt(self, u, dt, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
+        """One SSP-RK3 step with a given dt; returns (new state, stats)."""
+        u = np.array(u, dtype=np.float64, order="C", copy=True)
+        st = np.zeros(len(STAT_KEYS))
+        rc = lib().orc_ssprk3_dt(self._h, _ptr(u), dt, gamma, beta, limiter, _ptr(st))
+        d = _stats(st)
+        d["rc"] = rc
+        return u, d

@@ -1,0 +1,701 @@
+/*
+ * Oracle: semi-discretisation, time-step restriction, limited forward-Euler
+ * step and SSP-RK3.  TEST INFRASTRUCTURE ONLY (see dgo.h).
+ *
+ * All residuals here are R_i = m_i du_i/dt with the mass m_i = J omega_a omega_b,
+ * J = hx hy / 4 (eq. evolutionformula).
+ *
+ *  High order (eq. evolutionformula and the volume term F^Vol below it):
+ *    R_ab = omega_b ( -sum_k Sbar_ak (hy/2) f*_x(u_ab, u_kb) + boundary fluxes )
+ *         + omega_a ( -sum_k Sbar_bk (hx/2) f*_y(u_ab, u_ak) + boundary fluxes )
+ *    with LLF surface fluxes on conforming faces and Kopriva's L2 mortar
+ *    (interpolate, LLF on the mortar = small face, project back) on mortars.
+ *  Low order (eq. FVmethod, eq. interfaceflux_local):
+ *    LLF subcell fluxes between neighbouring nodes; on conforming faces the same
+ *    LLF as above; on mortars the sparsified IDP flux with weights tilde-omega.
+ *  Time step (eq. timestep_restriction; eq. CFLcondition_lowordermethod).
+ *  Limiting (Sec. 2.3): low-order update, then the volume correction with one
+ *  factor per subcell face, then the mortar correction with one factor per
+ *  mortar, against the positivity bounds of eq. Bounds_Positivity.
+ *  Time integration: three-stage SSP Runge-Kutta (Shu & Osher 1988, Sec. 3).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "dgo.h"
+
+#define IDX(e, v, b, a) ((((int64_t)(e)*4 + (v)) * n + (b)) * n + (a))
+
+/* node (a, b) of element face f at position k along the face */
+static void face_node(int f, int k, int N, int* a, int* b)
+{
+    if (f == 0) { *a = 0; *b = k; }
+    else if (f == 1) { *a = N; *b = k; }
+    else if (f == 2) { *a = k; *b = 0; }
+    else { *a = k; *b = N; }
+}
+
+static void get_node(const double* u, int n, int64_t e, int a, int b, double* q)
+{
+    for (int v = 0; v < 4; ++v) q[v] = u[IDX(e, v, b, a)];
+}
+
+static double face_len(const dgo_mesh* m, int64_t e, int f) { return f < 2 ? m->hy[e] : m->hx[e]; }
+
+/* ---------------------------------------------------------------------------
+ * Mortar contributions.  For mortar S, slot s in [0, 3n): s < n is large-face
+ * node k = s; s = n + h n + l is node l of small element h.  HO[S][s][v] and
+ * LO[S][s][v] are the mortar's contributions to R of that node.
+ * ------------------------------------------------------------------------- */
+static void mortar_contrib(const dgo_mesh* m, const double* u, double gamma, int64_t S, double* HO,
+                           double* LO)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    const dgo_mortar* M = &m->mort[S];
+    int f = M->face, dir = f / 2;
+    int large_lower = (f & 1); /* large element sits on the low-coordinate side */
+    double sgn_large = large_lower ? -1.0 : 1.0, sgn_small = -sgn_large;
+    double hL = face_len(m, M->large, f), hs = 0.5 * hL;
+    double uL[DGO_NMAX][4], us[2][DGO_NMAX][4];
+    for (int k = 0; k < n; ++k) {
+        int a, b;
+        face_node(f, k, N, &a, &b);
+        get_node(u, n, M->large, a, b, uL[k]);
+    }
+    for (int h = 0; h < 2; ++h)
+        for (int l = 0; l < n; ++l) {
+            int a, b;
+            face_node(f ^ 1, l, N, &a, &b);
+            get_node(u, n, M->small[h], a, b, us[h][l]);
+        }
+    for (int s = 0; s < 3 * n; ++s)
+        for (int v = 0; v < 4; ++v) HO[s * 4 + v] = LO[s * 4 + v] = 0.0;
+
+    /* high order: L2 mortar */
+    double Fm[2][DGO_NMAX][4];
+    for (int h = 0; h < 2; ++h)
+        for (int l = 0; l < n; ++l) {
+            double ui[4] = {0, 0, 0, 0};
+            for (int k = 0; k < n; ++k)
+                for (int v = 0; v < 4; ++v) ui[v] += B->I[h][l][k] * uL[k][v];
+            if (large_lower) dgo_flux_llf(ui, us[h][l], dir, gamma, Fm[h][l]);
+            else dgo_flux_llf(us[h][l], ui, dir, gamma, Fm[h][l]);
+            for (int v = 0; v < 4; ++v)
+                HO[(n + h * n + l) * 4 + v] = sgn_small * B->w[l] * hs / 2.0 * Fm[h][l][v];
+        }
+    for (int k = 0; k < n; ++k)
+        for (int v = 0; v < 4; ++v) {
+            double pk = 0.0;
+            for (int h = 0; h < 2; ++h)
+                for (int l = 0; l < n; ++l) pk += B->P[h][k][l] * Fm[h][l][v];
+            HO[k * 4 + v] = sgn_large * B->w[k] * hL / 2.0 * pk;
+        }
+
+    /* low order: sparse IDP mortar flux */
+    for (int k = 0; k < n; ++k)
+        for (int h = 0; h < 2; ++h)
+            for (int l = 0; l < n; ++l) {
+                double wt = B->Wt[k][h * n + l];
+                if (wt == 0.0) continue;
+                double W = wt * hL / 2.0, G[4];
+                if (large_lower) dgo_flux_llf(uL[k], us[h][l], dir, gamma, G);
+                else dgo_flux_llf(us[h][l], uL[k], dir, gamma, G);
+                for (int v = 0; v < 4; ++v) {
+                    LO[k * 4 + v] += sgn_large * W * G[v];
+                    LO[(n + h * n + l) * 4 + v] += sgn_small * W * G[v];
+                }
+            }
+}
+
+/* slot of node k along face f of element e, or -1 if that face is not a mortar */
+static int64_t face_slot(const dgo_mesh* m, int64_t e, int f, int k)
+{
+    const dgo_face* F = &m->face[e * 4 + f];
+    int n = m->B.n;
+    if (F->type == FACE_LARGE) return F->mortar * 3 * n + k;
+    if (F->type == FACE_SMALL) return F->mortar * 3 * n + n + F->half * n + k;
+    return -1;
+}
+
+/* conforming face contribution to R of node k of face f of element e */
+static void conf_face(const dgo_mesh* m, const double* u, double gamma, int64_t e, int f, int k,
+                      double* r)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    const dgo_face* F = &m->face[e * 4 + f];
+    int a, b, a2, b2;
+    face_node(f, k, N, &a, &b);
+    face_node(f ^ 1, k, N, &a2, &b2);
+    double ui[4], uo[4], Fl[4];
+    get_node(u, n, e, a, b, ui);
+    get_node(u, n, F->nbr, a2, b2, uo);
+    int dir = f / 2;
+    double W = B->w[k] * face_len(m, e, f) / 2.0;
+    if (f & 1) { /* element on the low side */
+        dgo_flux_llf(ui, uo, dir, gamma, Fl);
+        for (int v = 0; v < 4; ++v) r[v] = -W * Fl[v];
+    } else {
+        dgo_flux_llf(uo, ui, dir, gamma, Fl);
+        for (int v = 0; v < 4; ++v) r[v] = W * Fl[v];
+    }
+}
+
+/* surface contributions (conforming faces and mortar slots) for element e */
+static void add_surface(const dgo_mesh* m, const double* u, double gamma, const double* slots,
+                        int64_t e, double* R /* [4][n][n] */)
+{
+    int N = m->B.N, n = m->B.n;
+    for (int f = 0; f < 4; ++f) {
+        const dgo_face* F = &m->face[e * 4 + f];
+        for (int k = 0; k < n; ++k) {
+            int a, b;
+            face_node(f, k, N, &a, &b);
+            double r[4];
+            if (F->type == FACE_CONF) {
+                conf_face(m, u, gamma, e, f, k, r);
+            } else {
+                int64_t s = face_slot(m, e, f, k);
+                for (int v = 0; v < 4; ++v) r[v] = slots[s * 4 + v];
+            }
+            for (int v = 0; v < 4; ++v) R[(v * n + b) * n + a] += r[v];
+        }
+    }
+}
+
+static void compute_slots(const dgo_mesh* m, const double* u, double gamma, double* HO, double* LO)
+{
+    int n = m->B.n;
+#pragma omp parallel for schedule(static)
+    for (int64_t S = 0; S < m->M; ++S)
+        mortar_contrib(m, u, gamma, S, HO + S * 3 * n * 4, LO + S * 3 * n * 4);
+}
+
+/* high-order volume term, direct sum form */
+static void volume_high(const dgo_mesh* m, const double* u, double gamma, int64_t e, double* R)
+{
+    const dgo_basis* B = &m->B;
+    int n = B->n;
+    double hx = m->hx[e], hy = m->hy[e];
+    for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+            double ui[4], uk[4], fs[4], acc[4] = {0, 0, 0, 0};
+            get_node(u, n, e, a, b, ui);
+            for (int k = 0; k < n; ++k) {
+                get_node(u, n, e, k, b, uk);
+                dgo_flux_ranocha(ui, uk, 0, gamma, fs);
+                for (int v = 0; v < 4; ++v) acc[v] -= B->w[b] * B->S[a][k] * (hy / 2.0) * fs[v];
+                get_node(u, n, e, a, k, uk);
+                dgo_flux_ranocha(ui, uk, 1, gamma, fs);
+                for (int v = 0; v < 4; ++v) acc[v] -= B->w[a] * B->S[b][k] * (hx / 2.0) * fs[v];
+            }
+            for (int v = 0; v < 4; ++v) R[(v * n + b) * n + a] += acc[v];
+        }
+}
+
+/* low-order FV subcell fluxes, scaled subcell LLF flux on each interior subcell face */
+static void fv_face_flux(const dgo_mesh* m, const double* u, double gamma, int64_t e, int dir,
+                         int line, int a, double* F)
+{
+    int n = m->B.n;
+    double q0[4], q1[4];
+    if (dir == 0) {
+        get_node(u, n, e, a, line, q0);
+        get_node(u, n, e, a + 1, line, q1);
+    } else {
+        get_node(u, n, e, line, a, q0);
+        get_node(u, n, e, line, a + 1, q1);
+    }
+    dgo_flux_llf(q0, q1, dir, gamma, F);
+    double s = (dir == 0 ? m->hy[e] : m->hx[e]) / 2.0;
+    for (int v = 0; v < 4; ++v) F[v] *= s;
+}
+
+static void volume_low(const dgo_mesh* m, const double* u, double gamma, int64_t e, double* R)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    for (int line = 0; line < n; ++line)
+        for (int a = 0; a < N; ++a) {
+            double F[4];
+            fv_face_flux(m, u, gamma, e, 0, line, a, F); /* x-face (a,a+1) on row b=line */
+            for (int v = 0; v < 4; ++v) {
+                R[(v * n + line) * n + a] -= B->w[line] * F[v];
+                R[(v * n + line) * n + a + 1] += B->w[line] * F[v];
+            }
+            fv_face_flux(m, u, gamma, e, 1, line, a, F); /* y-face (a,a+1) on column a'=line */
+            for (int v = 0; v < 4; ++v) {
+                R[(v * n + a) * n + line] -= B->w[line] * F[v];
+                R[(v * n + a + 1) * n + line] += B->w[line] * F[v];
+            }
+        }
+}
+
+static double mass(const dgo_mesh* m, int64_t e, int a, int b)
+{
+    return m->hx[e] * m->hy[e] / 4.0 * m->B.w[a] * m->B.w[b];
+}
+
+static void residual(const dgo_mesh* m, const double* u, int which, double gamma, double* R)
+{
+    int n = m->B.n;
+    int64_t ns = m->M * 3 * n * 4;
+    double* HO = (double*)calloc(ns > 0 ? ns : 1, 8);
+    double* LO = (double*)calloc(ns > 0 ? ns : 1, 8);
+    compute_slots(m, u, gamma, HO, LO);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < m->E; ++e) {
+        double* Re = R + e * 4 * n * n;
+        memset(Re, 0, sizeof(double) * 4 * n * n);
+        if (which == RHS_HIGH) volume_high(m, u, gamma, e, Re);
+        else volume_low(m, u, gamma, e, Re);
+        add_surface(m, u, gamma, which == RHS_HIGH ? HO : LO, e, Re);
+    }
+    free(HO);
+    free(LO);
+}
+
+int dgo_rhs(const dgo_mesh* m, const double* u, int which, double gamma, double* du)
+{
+    int n = m->B.n;
+    residual(m, u, which, gamma, du);
+    for (int64_t e = 0; e < m->E; ++e)
+        for (int v = 0; v < 4; ++v)
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) du[IDX(e, v, b, a)] /= mass(m, e, a, b);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * time step
+ * ------------------------------------------------------------------------- */
+static double lam_pair(const double* p, const double* q, int dir, double gamma)
+{
+    double a = dgo_wavespeed(p, dir, gamma), b = dgo_wavespeed(q, dir, gamma);
+    return a > b ? a : b;
+}
+
+double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, double gamma)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    if (mode == DT_LOWORDER) {
+        double dt = INFINITY;
+        for (int64_t e = 0; e < m->E; ++e)
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    double q[4];
+                    get_node(u, n, e, a, b, q);
+                    /* the low-order stability bound of eq. CFLcondition_lowordermethod
+                       is only given up to a constant; the constant of the standard
+                       DGSEM estimate h / ((N+1) (lambda_1 + lambda_2)) is used */
+                    double t = 1.0 / ((N + 1) * (dgo_wavespeed(q, 0, gamma) / m->hx[e] +
+                                                 dgo_wavespeed(q, 1, gamma) / m->hy[e]));
+                    if (t < dt) dt = t;
+                }
+        return cfl * dt;
+    }
+    /* IDP: dt <= m_i / sum_j 2 d_ij, d_ij = |c_ij| lambda_ij */
+    double smax = 0.0;
+    double* sum = (double*)malloc(sizeof(double) * n * n);
+    for (int64_t e = 0; e < m->E; ++e) {
+        double hx = m->hx[e], hy = m->hy[e];
+        for (int i = 0; i < n * n; ++i) sum[i] = 0.0;
+        for (int line = 0; line < n; ++line)
+            for (int a = 0; a < N; ++a) {
+                double p[4], q[4];
+                get_node(u, n, e, a, line, p);
+                get_node(u, n, e, a + 1, line, q);
+                double d = B->w[line] * hy / 4.0 * lam_pair(p, q, 0, gamma);
+                sum[line * n + a] += 2 * d;
+                sum[line * n + a + 1] += 2 * d;
+                get_node(u, n, e, line, a, p);
+                get_node(u, n, e, line, a + 1, q);
+                d = B->w[line] * hx / 4.0 * lam_pair(p, q, 1, gamma);
+                sum[a * n + line] += 2 * d;
+                sum[(a + 1) * n + line] += 2 * d;
+            }
+        for (int f = 0; f < 4; ++f) {
+            const dgo_face* F = &m->face[e * 4 + f];
+            int dir = f / 2;
+            for (int k = 0; k < n; ++k) {
+                int a, b;
+                face_node(f, k, N, &a, &b);
+                double ui[4];
+                get_node(u, n, e, a, b, ui);
+                if (F->type == FACE_CONF) {
+                    int a2, b2;
+                    face_node(f ^ 1, k, N, &a2, &b2);
+                    double uo[4];
+                    get_node(u, n, F->nbr, a2, b2, uo);
+                    sum[b * n + a] += 2 * B->w[k] * face_len(m, e, f) / 4.0 * lam_pair(ui, uo, dir, gamma);
+                } else if (F->type == FACE_LARGE) {
+                    const dgo_mortar* M = &m->mort[F->mortar];
+                    for (int h = 0; h < 2; ++h)
+                        for (int l = 0; l < n; ++l) {
+                            double wt = B->Wt[k][h * n + l];
+                            if (wt == 0.0) continue;
+                            int a2, b2;
+                            face_node(f ^ 1, l, N, &a2, &b2);
+                            double uo[4];
+                            get_node(u, n, M->small[h], a2, b2, uo);
+                            sum[b * n + a] += 2 * (wt * face_len(m, e, f) / 4.0) * lam_pair(ui, uo, dir, gamma);
+                        }
+                } else {
+                    const dgo_mortar* M = &m->mort[F->mortar];
+                    for (int kk = 0; kk < n; ++kk) {
+                        double wt = B->Wt[kk][F->half * n + k];
+                        if (wt == 0.0) continue;
+                        int a2, b2;
+                        face_node(M->face, kk, N, &a2, &b2);
+                        double uo[4];
+                        get_node(u, n, M->large, a2, b2, uo);
+                        double hL = face_len(m, M->large, M->face);
+                        sum[b * n + a] += 2 * (wt * hL / 4.0) * lam_pair(ui, uo, dir, gamma);
+                    }
+                }
+            }
+        }
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double s = sum[b * n + a] / mass(m, e, a, b);
+                if (s > smax) smax = s;
+            }
+    }
+    free(sum);
+    return cfl / smax;
+}
+
+/* ---------------------------------------------------------------------------
+ * limiting
+ * ------------------------------------------------------------------------- */
+
+/* the limiter aims at the bounds raised by this relative margin, so that the
+   rounding of the final sums cannot cross the bounds themselves */
+#define BOUND_MARGIN (1.0 + 0x1p-40)
+
+/* largest theta in [0,1] with rho(u0 + theta dc) > 0 and p(u0 + theta dc) >= pt.
+   With rho > 0, p >= pt  <=>  g(theta) = (E - pt/(gamma-1)) rho - |m|^2/2 >= 0,
+   a quadratic in theta; the admissible set along the ray is [0, theta*]. */
+double dgo_theta_pressure(const double* u0, const double* dc, double pt, double gamma)
+{
+    double e0 = u0[3] - pt / (gamma - 1.0);
+    double g0 = u0[0] * e0 - 0.5 * (u0[1] * u0[1] + u0[2] * u0[2]);
+    if (!(g0 > 0.0) || !(u0[0] > 0.0)) return 0.0;
+    double g1 = dc[0] * e0 + u0[0] * dc[3] - (u0[1] * dc[1] + u0[2] * dc[2]);
+    double g2 = dc[0] * dc[3] - 0.5 * (dc[1] * dc[1] + dc[2] * dc[2]);
+    double root = INFINITY;
+    if (g2 == 0.0) {
+        if (g1 < 0.0) root = -g0 / g1;
+    } else {
+        double disc = g1 * g1 - 4.0 * g2 * g0;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double q = -0.5 * (g1 + (g1 >= 0.0 ? sq : -sq));
+            double r1 = q / g2, r2 = g0 / q;
+            if (r1 > 0.0 && r1 < root) root = r1;
+            if (r2 > 0.0 && r2 < root) root = r2;
+        }
+    }
+    if (dc[0] < 0.0) {
+        double rz = -u0[0] / dc[0];
+        if (rz < root) root = rz;
+    }
+    return root < 1.0 ? root : 1.0;
+}
+
+int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
+                int limiter, double* out, dgo_stats* st)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    int64_t E = m->E, nn = n * n;
+    memset(st, 0, sizeof(*st));
+    st->dt = dt;
+    st->theta_vol_min = 1.0;
+    st->theta_mort_min = 1.0;
+    int64_t ns = m->M * 3 * n * 4;
+    double* HO = (double*)calloc(ns > 0 ? ns : 1, 8);
+    double* LO = (double*)calloc(ns > 0 ? ns : 1, 8);
+    compute_slots(m, u, gamma, HO, LO);
+
+    if (limiter == LIM_NONE) {
+        double* R = (double*)malloc(sizeof(double) * E * 4 * nn);
+        residual(m, u, RHS_HIGH, gamma, R);
+        for (int64_t e = 0; e < E; ++e)
+            for (int v = 0; v < 4; ++v)
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a)
+                        out[IDX(e, v, b, a)] = u[IDX(e, v, b, a)] + dt / mass(m, e, a, b) * R[IDX(e, v, b, a)];
+        free(R);
+        free(HO);
+        free(LO);
+        return 0;
+    }
+
+    double* uFV = (double*)malloc(sizeof(double) * E * 4 * nn);
+    double* rmin = (double*)malloc(sizeof(double) * E * nn);
+    double* pmin = (double*)malloc(sizeof(double) * E * nn);
+    int64_t nfaces = 0;
+    double alpha_sum = 0.0;
+    int64_t inadm = 0, viol = 0;
+    double thmin = 1.0;
+
+#pragma omp parallel for schedule(static) reduction(+ : nfaces, alpha_sum, inadm) reduction(min : thmin)
+    for (int64_t e = 0; e < E; ++e) {
+        double R[4 * DGO_NMAX * DGO_NMAX];
+        memset(R, 0, sizeof(R));
+        volume_low(m, u, gamma, e, R);
+        add_surface(m, u, gamma, LO, e, R);
+        /* low-order update and bounds (eq. Bounds_Positivity) */
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double q[4];
+                for (int v = 0; v < 4; ++v) {
+                    q[v] = u[IDX(e, v, b, a)] + dt / mass(m, e, a, b) * R[(v * n + b) * n + a];
+                    uFV[IDX(e, v, b, a)] = q[v];
+                }
+                double p = dgo_pressure(q, gamma);
+                if (!(q[0] > 0.0) || !(p > 0.0)) inadm++;
+                rmin[e * nn + b * n + a] = beta * q[0];
+                pmin[e * nn + b * n + a] = beta * p;
+            }
+        /* antidiffusive fluxes on interior subcell faces: telescoped high-order
+           flux (eq. fluxdifferencingform) minus the low-order subcell flux */
+        double Ax[DGO_NMAX][DGO_NMAX][4], Ay[DGO_NMAX][DGO_NMAX][4]; /* [line][a] */
+        for (int line = 0; line < n; ++line)
+            for (int a = 0; a < N; ++a) {
+                for (int dir = 0; dir < 2; ++dir) {
+                    double fho[4] = {0, 0, 0, 0}, ffv[4];
+                    double s = (dir == 0 ? m->hy[e] : m->hx[e]) / 2.0;
+                    for (int l = 0; l <= a; ++l)
+                        for (int k = 0; k < n; ++k) {
+                            double ul[4], uk[4], fs[4];
+                            if (dir == 0) {
+                                get_node(u, n, e, l, line, ul);
+                                get_node(u, n, e, k, line, uk);
+                            } else {
+                                get_node(u, n, e, line, l, ul);
+                                get_node(u, n, e, line, k, uk);
+                            }
+                            dgo_flux_ranocha(ul, uk, dir, gamma, fs);
+                            for (int v = 0; v < 4; ++v) fho[v] += B->S[l][k] * s * fs[v];
+                        }
+                    fv_face_flux(m, u, gamma, e, dir, line, a, ffv);
+                    for (int v = 0; v < 4; ++v) {
+                        double A = B->w[line] * (fho[v] - ffv[v]);
+                        if (dir == 0) Ax[line][a][v] = A;
+                        else Ay[line][a][v] = A;
+                    }
+                }
+            }
+        /* per-node factors: Zalesak for rho, per-face pressure root with Gamma = 4 */
+        double th[DGO_NMAX][DGO_NMAX]; /* [b][a] */
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double mi = mass(m, e, a, b);
+                double q[4];
+                for (int v = 0; v < 4; ++v) q[v] = uFV[IDX(e, v, b, a)];
+                double cf[4][4];
+                int nf = 0;
+                if (a > 0) { for (int v = 0; v < 4; ++v) cf[nf][v] = dt / mi * Ax[b][a - 1][v]; nf++; }
+                if (a < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ax[b][a][v]; nf++; }
+                if (b > 0) { for (int v = 0; v < 4; ++v) cf[nf][v] = dt / mi * Ay[a][b - 1][v]; nf++; }
+                if (b < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ay[a][b][v]; nf++; }
+                double rt = rmin[e * nn + b * n + a] * BOUND_MARGIN;
+                double pt = pmin[e * nn + b * n + a] * BOUND_MARGIN;
+                double P = 0.0;
+                for (int j = 0; j < nf; ++j)
+                    if (cf[j][0] < 0.0) P += cf[j][0];
+                double t = 1.0;
+                if (P < 0.0) {
+                    double r = (rt - q[0]) / P;
+                    t = r < 1.0 ? r : 1.0;
+                    if (t < 0.0) t = 0.0;
+                }
+                for (int j = 0; j < nf; ++j) {
+                    double dc[4];
+                    for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
+                    double tp = dgo_theta_pressure(q, dc, pt, gamma);
+                    if (tp < t) t = tp;
+                }
+                th[b][a] = t;
+            }
+        /* per-face factor = min of its two nodes; limited volume update */
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double mi = mass(m, e, a, b);
+                double acc[4];
+                for (int v = 0; v < 4; ++v) acc[v] = uFV[IDX(e, v, b, a)];
+                if (a > 0) {
+                    double t = th[b][a - 1] < th[b][a] ? th[b][a - 1] : th[b][a];
+                    for (int v = 0; v < 4; ++v) acc[v] += t * dt / mi * Ax[b][a - 1][v];
+                }
+                if (a < N) {
+                    double t = th[b][a] < th[b][a + 1] ? th[b][a] : th[b][a + 1];
+                    for (int v = 0; v < 4; ++v) acc[v] -= t * dt / mi * Ax[b][a][v];
+                    nfaces++;
+                    alpha_sum += 1.0 - t;
+                    if (t < thmin) thmin = t;
+                }
+                if (b > 0) {
+                    double t = th[b - 1][a] < th[b][a] ? th[b - 1][a] : th[b][a];
+                    for (int v = 0; v < 4; ++v) acc[v] += t * dt / mi * Ay[a][b - 1][v];
+                }
+                if (b < N) {
+                    double t = th[b][a] < th[b + 1][a] ? th[b][a] : th[b + 1][a];
+                    for (int v = 0; v < 4; ++v) acc[v] -= t * dt / mi * Ay[a][b][v];
+                    nfaces++;
+                    alpha_sum += 1.0 - t;
+                    if (t < thmin) thmin = t;
+                }
+                for (int v = 0; v < 4; ++v) out[IDX(e, v, b, a)] = acc[v];
+            }
+    }
+    st->fv_inadmissible = inadm;
+    st->theta_vol_min = thmin;
+    st->alpha_vol_mean = nfaces ? alpha_sum / nfaces : 0.0;
+
+    /* mortar correction: one factor per mortar, antidiffusive flux scaled by
+       the number n_i of mortars at node i (Sec. 2.3, remark on mortar limiting) */
+    if (m->M > 0) {
+        double* theta = (double*)malloc(sizeof(double) * m->M);
+        double tmsum = 0.0, tmmin = 1.0;
+#pragma omp parallel for schedule(static) reduction(+ : tmsum) reduction(min : tmmin)
+        for (int64_t S = 0; S < m->M; ++S) {
+            const dgo_mortar* M = &m->mort[S];
+            double t = 1.0;
+            for (int s = 0; s < 3 * n; ++s) {
+                int64_t e;
+                int f, k;
+                if (s < n) { e = M->large; f = M->face; k = s; }
+                else { int h = (s - n) / n; e = M->small[h]; f = M->face ^ 1; k = (s - n) % n; }
+                int a, b;
+                face_node(f, k, N, &a, &b);
+                int ni = 0;
+                if (a == 0 && m->face[e * 4 + 0].type != FACE_CONF) ni++;
+                if (a == N && m->face[e * 4 + 1].type != FACE_CONF) ni++;
+                if (b == 0 && m->face[e * 4 + 2].type != FACE_CONF) ni++;
+                if (b == N && m->face[e * 4 + 3].type != FACE_CONF) ni++;
+                double mi = mass(m, e, a, b);
+                double q[4], dc[4];
+                const double* ho = HO + (S * 3 * n + s) * 4;
+                const double* lo = LO + (S * 3 * n + s) * 4;
+                for (int v = 0; v < 4; ++v) {
+                    q[v] = out[IDX(e, v, b, a)];
+                    dc[v] = ni * dt / mi * (ho[v] - lo[v]);
+                }
+                /* the high-order mortar flux interpolates the large face; near
+                   vacuum that state can leave the admissible set and the flux is
+                   not defined: the mortar then keeps the low-order flux (Sec. 3.2) */
+                if (!(isfinite(dc[0]) && isfinite(dc[1]) && isfinite(dc[2]) && isfinite(dc[3]))) {
+                    t = 0.0;
+                    continue;
+                }
+                double rt = rmin[e * nn + b * n + a] * BOUND_MARGIN;
+                double pt = pmin[e * nn + b * n + a] * BOUND_MARGIN;
+                if (dc[0] < 0.0) {
+                    double r = (rt - q[0]) / dc[0];
+                    if (r < 0.0) r = 0.0;
+                    if (r < t) t = r;
+                }
+                double tp = dgo_theta_pressure(q, dc, pt, gamma);
+                if (tp < t) t = tp;
+            }
+            theta[S] = t;
+            tmsum += 1.0 - t;
+            if (t < tmmin) tmmin = t;
+        }
+        st->alpha_mort_mean = tmsum / m->M;
+        st->theta_mort_min = tmmin;
+        /* apply: each node gathers its mortars in ascending mortar id */
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < E; ++e) {
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    int64_t slots[2];
+                    int64_t ids[2];
+                    int cnt = 0;
+                    for (int f = 0; f < 4; ++f) {
+                        int k = -1;
+                        if (f == 0 && a == 0) k = b;
+                        if (f == 1 && a == N) k = b;
+                        if (f == 2 && b == 0) k = a;
+                        if (f == 3 && b == N) k = a;
+                        if (k < 0) continue;
+                        int64_t s = face_slot(m, e, f, k);
+                        if (s < 0) continue;
+                        slots[cnt] = s;
+                        ids[cnt] = m->face[e * 4 + f].mortar;
+                        cnt++;
+                    }
+                    if (cnt == 2 && ids[1] < ids[0]) {
+                        int64_t t = slots[0]; slots[0] = slots[1]; slots[1] = t;
+                        t = ids[0]; ids[0] = ids[1]; ids[1] = t;
+                    }
+                    double mi = mass(m, e, a, b);
+                    for (int c = 0; c < cnt; ++c) {
+                        const double* ho = HO + slots[c] * 4;
+                        const double* lo = LO + slots[c] * 4;
+                        double t = theta[ids[c]];
+                        if (t == 0.0) continue;
+                        for (int v = 0; v < 4; ++v) out[IDX(e, v, b, a)] += t * dt / mi * (ho[v] - lo[v]);
+                    }
+                }
+        }
+        free(theta);
+    }
+    /* bound check of the final state against the bounds themselves */
+#pragma omp parallel for schedule(static) reduction(+ : viol)
+    for (int64_t e = 0; e < E; ++e)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double q[4];
+                get_node(out, n, e, a, b, q);
+                if (q[0] < rmin[e * nn + b * n + a] || dgo_pressure(q, gamma) < pmin[e * nn + b * n + a] ||
+                    q[0] != q[0])
+                    viol++;
+            }
+    st->violations = viol;
+    free(uFV);
+    free(rmin);
+    free(pmin);
+    free(HO);
+    free(LO);
+    return st->fv_inadmissible ? 1 : 0;
+}
+
+int dgo_ssprk3(const dgo_mesh* m, double* u, double cfl, int mode, double gamma, double beta,
+               int limiter, dgo_stats* st)
+{
+    return dgo_ssprk3_dt(m, u, dgo_max_dt(m, u, cfl, mode, gamma), gamma, beta, limiter, st);
+}
+
+int dgo_ssprk3_dt(const dgo_mesh* m, double* u, double dt, double gamma, double beta, int limiter,
+                  dgo_stats* st)
+{
+    int n = m->B.n;
+    int64_t sz = m->E * 4 * n * n;
+    double* u1 = (double*)malloc(sizeof(double) * sz);
+    double* w = (double*)malloc(sizeof(double) * sz);
+    dgo_stats s1, s2, s3;
+    int rc = 0;
+    rc |= dgo_fe_step(m, u, dt, gamma, beta, limiter, u1, &s1);
+    rc |= dgo_fe_step(m, u1, dt, gamma, beta, limiter, w, &s2);
+    for (int64_t i = 0; i < sz; ++i) u1[i] = 0.75 * u[i] + 0.25 * w[i];
+    rc |= dgo_fe_step(m, u1, dt, gamma, beta, limiter, w, &s3);
+    for (int64_t i = 0; i < sz; ++i) u[i] = u[i] / 3.0 + 2.0 / 3.0 * w[i];
+    memset(st, 0, sizeof(*st));
+    st->dt = dt;
+    st->fv_inadmissible = s1.fv_inadmissible + s2.fv_inadmissible + s3.fv_inadmissible;
+    st->violations = s1.violations + s2.violations + s3.violations;
+    st->theta_vol_min = fmin(s1.theta_vol_min, fmin(s2.theta_vol_min, s3.theta_vol_min));
+    st->theta_mort_min = fmin(s1.theta_mort_min, fmin(s2.theta_mort_min, s3.theta_mort_min));
+    st->alpha_vol_mean = (s1.alpha_vol_mean + s2.alpha_vol_mean + s3.alpha_vol_mean) / 3.0;
+    st->alpha_mort_mean = (s1.alpha_mort_mean + s2.alpha_mort_mean + s3.alpha_mort_mean) / 3.0;
+    free(u1);
+    free(w);
+    return rc;
+}
