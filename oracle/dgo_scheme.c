@@ -80,8 +80,16 @@ static void mortar_contrib(const dgo_mesh* m, const double* u, double gamma, int
             double ui[4] = {0, 0, 0, 0};
             for (int k = 0; k < n; ++k)
                 for (int v = 0; v < 4; ++v) ui[v] += B->I[h][l][k] * uL[k][v];
-            if (large_lower) dgo_flux_llf(ui, us[h][l], dir, gamma, Fm[h][l]);
-            else dgo_flux_llf(us[h][l], ui, dir, gamma, Fm[h][l]);
+            /* an interpolated state outside the admissible set leaves the
+               high-order mortar flux undefined (Sec. 3.2): mark it NaN, the
+               mortar limiter then keeps the low-order flux */
+            if (!(ui[0] > 0.0) || !(dgo_pressure(ui, gamma) > 0.0)) {
+                for (int v = 0; v < 4; ++v) Fm[h][l][v] = NAN;
+            } else if (large_lower) {
+                dgo_flux_llf(ui, us[h][l], dir, gamma, Fm[h][l]);
+            } else {
+                dgo_flux_llf(us[h][l], ui, dir, gamma, Fm[h][l]);
+            }
             for (int v = 0; v < 4; ++v)
                 HO[(n + h * n + l) * 4 + v] = sgn_small * B->w[l] * hs / 2.0 * Fm[h][l][v];
         }
