@@ -1,0 +1,157 @@
+/*
+ * dgidp: MI355X (gfx950) library for the invariant-domain-preserving (IDP)
+ * limited LGL-DGSEM of the 2D compressible Euler equations on 2:1-balanced
+ * periodic Cartesian quadtrees (Bolm, Rueda-Ramirez, Kuzmin, Gassner:
+ * "Invariant-domain-preserving limiting with Adaptive Mesh Refinement for
+ * Legendre-Gauss-Lobatto Discontinuous Galerkin Spectral Element Methods").
+ *
+ * Conventions shared by every entry point
+ *  - Return value: 0 on success, a negative DGIDP_E_* code on failure.  No
+ *    entry point aborts the process.  After an error the context stays usable,
+ *    except after DGIDP_E_DEVICE.  dgidp_last_error() gives a message.
+ *  - Nodal state layout (external order): u[e][v][j][i], e = leaf index in the
+ *    caller's leaf order, v = (rho, rho v1, rho v2, rho e), j = LGL node index
+ *    along y, i = LGL node index along x, N+1 nodes per direction.
+ *  - Pointers flagged `on_device` are device pointers used on the context's
+ *    stream; otherwise they are host pointers.  The caller owns every pointer
+ *    it passes; the library copies what it keeps.  The context owns all device
+ *    buffers it allocates.
+ *  - Asynchrony: entry points that take no host output pointer only enqueue
+ *    work on the context's stream; those that return host values synchronise.
+ */
+#ifndef DGIDP_H
+#define DGIDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DGIDP_OK = 0,
+    DGIDP_E_INVALID_ARG = -1,
+    DGIDP_E_UNSUPPORTED_N = -2,
+    DGIDP_E_DEVICE = -3,
+    DGIDP_E_MESH_GAP_OR_OVERLAP = -4,
+    DGIDP_E_MESH_NOT_BALANCED = -5,
+    DGIDP_E_STATE_INADMISSIBLE = -6,
+    DGIDP_E_NO_MESH = -7,
+    DGIDP_E_NO_STATE = -8,
+    DGIDP_E_DT = -9
+};
+
+enum { DGIDP_FP64 = 0, DGIDP_MIXED = 1 };           /* precision of the high-order fluxes */
+enum { DGIDP_DT_IDP = 0, DGIDP_DT_LOWORDER = 1 };   /* time-step rule */
+enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1 };
+enum { DGIDP_RHS_HIGH = 0, DGIDP_RHS_LOW = 1 };
+
+typedef struct dgidp_ctx dgidp_ctx;
+
+/* Parameters of the scheme.
+ *  N          polynomial degree (GPU kernels exist for N = 3 and N = 4)
+ *  gamma      ratio of specific heats (Sec. 3: 1.4; 3 in Sec. 3.2)
+ *  beta       positivity bound factor: rho >= beta rho^FV, p >= beta p^FV
+ *             (eq. Bounds_Positivity, beta = 0.1)
+ *  precision  DGIDP_FP64, or DGIDP_MIXED: FP32 volume flux differencing and
+ *             mortar interpolation/projection, FP64 everything else
+ *  dt_mode    DGIDP_DT_IDP (eq. timestep_restriction) or DGIDP_DT_LOWORDER
+ *             (eq. CFLcondition_lowordermethod, constant of the standard
+ *             DGSEM estimate: dt = CFL / max_i (N+1)(lambda_1/hx + lambda_2/hy))
+ *  limiter    DGIDP_LIMIT_NONE (pure high order) or DGIDP_LIMIT_POSITIVITY
+ *             (Sec. 2.3: volume then mortar convex limiting)
+ *  strict_dt  if nonzero, dgidp_limit() rejects a dt above the IDP bound */
+typedef struct {
+    int N;
+    double gamma;
+    double beta;
+    int precision;
+    int dt_mode;
+    int limiter;
+    int strict_dt;
+} dgidp_params;
+
+/* Statistics of one limited forward-Euler step or one SSP-RK3 step (summed or
+ * reduced over its stages).  alpha = 1 - theta is the low-order fraction
+ * (Sec. 3 intro: alpha = 1 pure low order). */
+typedef struct {
+    int64_t fv_inadmissible; /* nodes whose low-order update left rho > 0, p > 0 */
+    int64_t violations;      /* nodes below the rho / p bounds after limiting (tolerance 0) */
+    double theta_vol_min;    /* smallest volume blending factor */
+    double theta_mort_min;   /* smallest mortar blending factor */
+    double alpha_vol_mean;   /* mean of 1 - theta over interior subcell faces */
+    double alpha_mort_mean;  /* mean of 1 - theta over mortars */
+    double dt;               /* time step used */
+} dgidp_stats;
+
+/* Create a context.  `stream` is a hipStream_t (may be NULL for the null
+ * stream), borrowed, e.g. torch.cuda.current_stream().cuda_stream.
+ * Errors: DGIDP_E_INVALID_ARG, DGIDP_E_UNSUPPORTED_N, DGIDP_E_DEVICE. */
+int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out);
+void dgidp_destroy(dgidp_ctx* ctx);
+const char* dgidp_last_error(dgidp_ctx* ctx);
+int dgidp_set_stream(dgidp_ctx* ctx, void* stream);
+int dgidp_synchronize(dgidp_ctx* ctx);
+
+/* Upload a quadtree mesh (Sec. 3.1: leaves are the elements).  The root grid
+ * is nx0 x ny0 on [x0, x0+Lx] x [y0, y0+Ly], periodic in both directions; leaf
+ * e covers cell (ix[e], iy[e]) of the (nx0 2^level[e]) x (ny0 2^level[e]) grid.
+ * Neighbours across a face may differ by one level (Sec. 2.2: 2-to-1
+ * nonconforming interfaces).  Host arrays, copied.  Replaces any previous mesh
+ * and state.  Errors: DGIDP_E_MESH_GAP_OR_OVERLAP (leaves do not tile the
+ * domain), DGIDP_E_MESH_NOT_BALANCED, DGIDP_E_INVALID_ARG. */
+int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t n_leaves, const int8_t* level, const int32_t* ix,
+                      const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
+                      int ny0);
+/* Host-only: validate a leaf list like dgidp_mesh_upload (same errors, message
+ * in msg) without a context or GPU; returns the number of mortars and of nodes
+ * that lie on two mortars.  Output pointers may be NULL. */
+int dgidp_mesh_validate(int N, int64_t n_leaves, const int8_t* level, const int32_t* ix,
+                        const int32_t* iy, int nx0, int ny0, int64_t* n_mortars,
+                        int64_t* n_two_mortar_nodes, char* msg, int msglen);
+/* Number of elements and of mortars (nonconforming faces) of the mesh. */
+int dgidp_mesh_info(dgidp_ctx* ctx, int64_t* n_elements, int64_t* n_mortars);
+/* Physical node coordinates, host arrays [E][N+1][N+1] (external order). */
+int dgidp_node_coords(dgidp_ctx* ctx, double* x, double* y);
+
+/* Upload / download the nodal state (layout above).  Upload checks that every
+ * value is finite and rho > 0, p > 0 (DGIDP_E_STATE_INADMISSIBLE, first bad
+ * node in the message). */
+int dgidp_state_upload(dgidp_ctx* ctx, const double* u, int on_device);
+int dgidp_state_download(dgidp_ctx* ctx, double* u, int on_device);
+
+/* Semi-discrete time derivative du/dt of the current state (eq. evolutionformula
+ * with Kopriva's L2 mortars for DGIDP_RHS_HIGH; eq. FVmethod with the sparse IDP
+ * mortar flux of eq. interfaceflux_local for DGIDP_RHS_LOW); no limiting.
+ * Same layout as the state. */
+int dgidp_rhs(dgidp_ctx* ctx, int which, double* du, int on_device);
+
+/* Largest stable time step times cfl (dt_mode of the context; eq.
+ * timestep_restriction for DGIDP_DT_IDP).  Synchronises. */
+int dgidp_max_dt(dgidp_ctx* ctx, double cfl, double* dt);
+
+/* One limited forward-Euler step of size dt, in place (Sec. 2.3: low-order
+ * update, volume correction, mortar correction).  `s` may be NULL (then the
+ * call only enqueues work).  Errors: DGIDP_E_DT in strict mode. */
+int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s);
+
+/* One SSP-RK3 step in place (Shu-Osher form, each stage a limited forward-Euler
+ * step), dt = cfl times the bound of the context's dt_mode, evaluated once at
+ * the start of the step.  dt_used and s may be NULL (then nothing is copied to
+ * the host and the call only enqueues work). */
+int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s);
+/* Same with a given dt (used to land exactly on an end time). */
+int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s);
+
+/* Host-only: the operator tables the library uploads for degree N, flat
+ * doubles: w[n] (LGL weights, Sec. 2.1), Sbar[n][n] (Sec. 2.1), mortar
+ * interpolation I[2][n][n] and L2 projection P[2][n][n] (Sec. 2.2, Kopriva's
+ * mortar), sparse mortar weights Wt[n][2n] (eq. local_weights, App. A); n = N+1.
+ * `out` holds at least n + 5 n^2 + 2 n^2 doubles.  Needs no GPU. */
+int dgidp_host_tables(int N, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

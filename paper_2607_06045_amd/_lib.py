@@ -1,0 +1,226 @@
+"""ctypes binding of libdgidp.so (include/dgidp.h): argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels.  PyTorch provides
+device memory and the stream.  There is no CPU fallback: if the library is not
+built, importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library shares)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgidp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "or python paper_2607_06045_amd/build.py")
+
+FP64, MIXED = 0, 1
+DT_IDP, DT_LOWORDER = 0, 1
+LIMIT_NONE, LIMIT_POSITIVITY = 0, 1
+RHS_HIGH, RHS_LOW = 0, 1
+
+ERRORS = {
+    -1: "DGIDP_E_INVALID_ARG", -2: "DGIDP_E_UNSUPPORTED_N", -3: "DGIDP_E_DEVICE",
+    -4: "DGIDP_E_MESH_GAP_OR_OVERLAP", -5: "DGIDP_E_MESH_NOT_BALANCED",
+    -6: "DGIDP_E_STATE_INADMISSIBLE", -7: "DGIDP_E_NO_MESH", -8: "DGIDP_E_NO_STATE",
+    -9: "DGIDP_E_DT",
+}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("precision", ctypes.c_int), ("dt_mode", ctypes.c_int),
+                ("limiter", ctypes.c_int), ("strict_dt", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("fv_inadmissible", ctypes.c_int64), ("violations", ctypes.c_int64),
+                ("theta_vol_min", ctypes.c_double), ("theta_mort_min", ctypes.c_double),
+                ("alpha_vol_mean", ctypes.c_double), ("alpha_mort_mean", ctypes.c_double),
+                ("dt", ctypes.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp, _d, _i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+_lib = ctypes.CDLL(LIB_PATH)
+_SIGS = {
+    "dgidp_create": (_i, [ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
+    "dgidp_destroy": (None, [_vp]),
+    "dgidp_last_error": (ctypes.c_char_p, [_vp]),
+    "dgidp_set_stream": (_i, [_vp, _vp]),
+    "dgidp_synchronize": (_i, [_vp]),
+    "dgidp_mesh_upload": (_i, [_vp, ctypes.c_int64, _vp, _vp, _vp, _d, _d, _d, _d, _i, _i]),
+    "dgidp_mesh_info": (_i, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "dgidp_node_coords": (_i, [_vp, _vp, _vp]),
+    "dgidp_state_upload": (_i, [_vp, _vp, _i]),
+    "dgidp_state_download": (_i, [_vp, _vp, _i]),
+    "dgidp_rhs": (_i, [_vp, _i, _vp, _i]),
+    "dgidp_max_dt": (_i, [_vp, _d, ctypes.POINTER(_d)]),
+    "dgidp_limit": (_i, [_vp, _d, ctypes.POINTER(Stats)]),
+    "dgidp_step": (_i, [_vp, _d, ctypes.POINTER(_d), ctypes.POINTER(Stats)]),
+    "dgidp_step_dt": (_i, [_vp, _d, ctypes.POINTER(Stats)]),
+    "dgidp_host_tables": (_i, [_i, _vp]),
+    "dgidp_mesh_validate": (_i, [_i, ctypes.c_int64, _vp, _vp, _vp, _i, _i,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.c_char_p, _i]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+class DgidpError(RuntimeError):
+    pass
+
+
+def host_tables(N):
+    """The library's operator tables for degree N: dict of w, S, I, P, Wt."""
+    n = N + 1
+    out = np.zeros(n + 7 * n * n)
+    rc = _lib.dgidp_host_tables(N, out.ctypes.data)
+    if rc:
+        raise DgidpError(ERRORS.get(rc, rc))
+    o = 0
+    res = {}
+    for key, shape in (("w", (n,)), ("S", (n, n)), ("I", (2, n, n)), ("P", (2, n, n)),
+                       ("Wt", (n, 2 * n))):
+        size = int(np.prod(shape))
+        res[key] = out[o:o + size].reshape(shape)
+        o += size
+    return res
+
+
+def validate_mesh(N, level, ix, iy, nx0, ny0):
+    """Host-only mesh check: returns (n_mortars, n_two_mortar_nodes) or raises."""
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    M, T2 = ctypes.c_int64(), ctypes.c_int64()
+    msg = ctypes.create_string_buffer(256)
+    rc = _lib.dgidp_mesh_validate(N, len(level), level.ctypes.data, ix.ctypes.data,
+                                  iy.ctypes.data, nx0, ny0, ctypes.byref(M), ctypes.byref(T2),
+                                  msg, 256)
+    if rc:
+        raise DgidpError(f"dgidp_mesh_validate: {ERRORS.get(rc, rc)}: {msg.value.decode()}")
+    return M.value, T2.value
+
+
+class Solver:
+    """One dgidp context: a mesh, a state on the GPU and the stepping entry points."""
+
+    def __init__(self, N=3, gamma=1.4, beta=0.1, precision=FP64, dt_mode=DT_IDP,
+                 limiter=LIMIT_POSITIVITY, strict_dt=False, stream=None):
+        if not torch.cuda.is_available():
+            raise DgidpError("dgidp needs a ROCm GPU; none is visible")
+        self.N, self.n = N, N + 1
+        self.gamma = gamma
+        self.params = Params(N, gamma, beta, precision, dt_mode, limiter, int(strict_dt))
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _vp()
+        rc = _lib.dgidp_create(ctypes.byref(self.params), _vp(self.stream.cuda_stream),
+                               ctypes.byref(h))
+        if rc:
+            raise DgidpError(f"dgidp_create: {ERRORS.get(rc, rc)}")
+        self._h = h
+        self.E = self.M = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dgidp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc:
+            msg = _lib.dgidp_last_error(self._h).decode()
+            raise DgidpError(f"{what}: {ERRORS.get(rc, rc)}: {msg}")
+
+    # mesh ------------------------------------------------------------------
+    def set_mesh(self, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0):
+        level = np.ascontiguousarray(level, dtype=np.int8)
+        ix = np.ascontiguousarray(ix, dtype=np.int32)
+        iy = np.ascontiguousarray(iy, dtype=np.int32)
+        self._check(_lib.dgidp_mesh_upload(self._h, len(level), level.ctypes.data,
+                                           ix.ctypes.data, iy.ctypes.data, x0, y0, Lx, Ly,
+                                           nx0, ny0), "dgidp_mesh_upload")
+        E, M = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.dgidp_mesh_info(self._h, ctypes.byref(E), ctypes.byref(M)),
+                    "dgidp_mesh_info")
+        self.E, self.M = E.value, M.value
+
+    def node_coords(self):
+        sh = (self.E, self.n, self.n)
+        x, y = np.zeros(sh), np.zeros(sh)
+        self._check(_lib.dgidp_node_coords(self._h, x.ctypes.data, y.ctypes.data),
+                    "dgidp_node_coords")
+        return x, y
+
+    @property
+    def shape(self):
+        return (self.E, 4, self.n, self.n)
+
+    # state -----------------------------------------------------------------
+    def upload(self, u):
+        """u: numpy array (host) or torch float64 CUDA tensor, shape [E, 4, n, n]."""
+        if isinstance(u, torch.Tensor) and u.is_cuda:
+            assert u.dtype == torch.float64 and tuple(u.shape) == self.shape and u.is_contiguous()
+            self._check(_lib.dgidp_state_upload(self._h, u.data_ptr(), 1), "dgidp_state_upload")
+        else:
+            u = np.ascontiguousarray(u, dtype=np.float64)
+            assert u.shape == self.shape
+            self._check(_lib.dgidp_state_upload(self._h, u.ctypes.data, 0), "dgidp_state_upload")
+
+    def download(self, device=False):
+        if device:
+            out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+            self._check(_lib.dgidp_state_download(self._h, out.data_ptr(), 1),
+                        "dgidp_state_download")
+            return out
+        out = np.zeros(self.shape)
+        self._check(_lib.dgidp_state_download(self._h, out.ctypes.data, 0), "dgidp_state_download")
+        return out
+
+    def rhs(self, which=RHS_HIGH):
+        out = np.zeros(self.shape)
+        self._check(_lib.dgidp_rhs(self._h, which, out.ctypes.data, 0), "dgidp_rhs")
+        return out
+
+    # time stepping -----------------------------------------------------------
+    def max_dt(self, cfl):
+        dt = _d()
+        self._check(_lib.dgidp_max_dt(self._h, cfl, ctypes.byref(dt)), "dgidp_max_dt")
+        return dt.value
+
+    def limit(self, dt, stats=True):
+        st = Stats()
+        self._check(_lib.dgidp_limit(self._h, dt, ctypes.byref(st) if stats else None),
+                    "dgidp_limit")
+        return st.to_dict() if stats else None
+
+    def step(self, cfl, stats=True):
+        st = Stats()
+        dt = _d()
+        self._check(_lib.dgidp_step(self._h, cfl, ctypes.byref(dt) if stats else None,
+                                    ctypes.byref(st) if stats else None), "dgidp_step")
+        return st.to_dict() if stats else None
+
+    def step_dt(self, dt, stats=True):
+        st = Stats()
+        self._check(_lib.dgidp_step_dt(self._h, dt, ctypes.byref(st) if stats else None),
+                    "dgidp_step_dt")
+        return st.to_dict() if stats else None
+
+    def synchronize(self):
+        self._check(_lib.dgidp_synchronize(self._h), "dgidp_synchronize")

@@ -1,0 +1,647 @@
+// Host side of dgidp: context, quadtree mesh and connectivity, state transfer,
+// and the C-ABI entry points declared in include/dgidp.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "dgidp_internal.h"
+
+namespace dgidp {
+int build_and_upload_tables(int N, std::vector<double>* nodes);
+int host_tables(int N, double* out);
+}  // namespace dgidp
+
+using namespace dgidp;
+
+struct dgidp_ctx {
+    dgidp_params p{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<double> xi;  // LGL nodes
+    // mesh (host)
+    int64_t E = 0, M = 0;
+    std::vector<int8_t> level;
+    std::vector<int32_t> ix, iy;
+    std::vector<int> perm;  // internal -> external
+    double x0 = 0, y0 = 0, Lx = 1, Ly = 1;
+    int nx0 = 1, ny0 = 1;
+    std::vector<double> hh;  // internal [E*2]
+    // device
+    DevMesh dm;
+    double *U = nullptr, *W1 = nullptr, *W2 = nullptr;
+    double* dt_dev = nullptr;
+    double* partial = nullptr;
+    unsigned int* counter = nullptr;
+    DevStats* stats = nullptr;
+    unsigned long long* bad = nullptr;
+    int dtb = 0;
+    bool has_state = false;
+};
+
+namespace {
+
+int fail(dgidp_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return fail(ctx, DGIDP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_mesh(dgidp_ctx* c)
+{
+    dfree(c->dm.fnbr);
+    dfree(c->dm.fmort);
+    dfree(c->dm.mort);
+    dfree(c->dm.h);
+    dfree(c->dm.slot_node);
+    dfree(c->dm.slot_partner);
+    dfree(c->dm.slot);
+    dfree(c->dm.perm);
+    dfree(c->U);
+    dfree(c->W1);
+    dfree(c->W2);
+    dfree(c->partial);
+    c->dm = DevMesh();
+    c->E = c->M = 0;
+    c->has_state = false;
+}
+
+template <typename T>
+int upload(dgidp_ctx* ctx, T*& dst, const std::vector<T>& src)
+{
+    const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+    HIPCHK(hipMalloc((void**)&dst, bytes));
+    if (!src.empty()) HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return 0;
+}
+
+inline uint64_t key_of(int l, int64_t i, int64_t j)
+{
+    return ((uint64_t)l << 56) | ((uint64_t)i << 28) | (uint64_t)j;
+}
+
+inline uint64_t morton(uint64_t x, uint64_t y)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < 31; ++b) {
+        k |= ((x >> b) & 1ull) << (2 * b);
+        k |= ((y >> b) & 1ull) << (2 * b + 1);
+    }
+    return k;
+}
+
+double host_pressure(const double* u, double g)
+{
+    return (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+}
+
+int sync_stats(dgidp_ctx* ctx, dgidp_stats* s, int nstages)
+{
+    DevStats h;
+    HIPCHK(hipMemcpyAsync(&h, ctx->stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    s->fv_inadmissible = (int64_t)h.fv_inadmissible;
+    s->violations = (int64_t)h.violations;
+    double tv, tm;
+    std::memcpy(&tv, &h.theta_vol_min_bits, 8);
+    std::memcpy(&tm, &h.theta_mort_min_bits, 8);
+    s->theta_vol_min = tv;
+    s->theta_mort_min = tm;
+    s->alpha_vol_mean = h.nfaces ? h.alpha_vol_sum / (double)h.nfaces : 0.0;
+    s->alpha_mort_mean = h.nmortars ? h.alpha_mort_sum / (double)h.nmortars : 0.0;
+    s->dt = h.dt;
+    (void)nstages;
+    return 0;
+}
+
+// Connectivity of a periodic quadtree mesh, in internal (Morton) element order.
+struct HostMesh {
+    int M = 0;
+    std::vector<int> perm;          // internal -> external
+    std::vector<int> fnbr, fmort;   // [E*4]
+    std::vector<int> mort;          // [M*4] large, face, small0, small1
+    std::vector<int> snode, spart;  // [M*3n]
+};
+
+int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, const int32_t* iy,
+                    int nx0, int ny0, HostMesh& hm, std::string& err)
+{
+    if (N != 3 && N != 4) {
+        err = "unsupported N";
+        return DGIDP_E_UNSUPPORTED_N;
+    }
+    const int n = N + 1, NN = n * n;
+    if (E <= 0 || !level || !ix || !iy || nx0 <= 0 || ny0 <= 0 || E > (int64_t)(1 << 30) / (NN * 4)) {
+        err = "invalid mesh arguments";
+        return DGIDP_E_INVALID_ARG;
+    }
+    std::unordered_map<uint64_t, int> find;
+    find.reserve((size_t)E * 2);
+    double area = 0.0;
+    int lmax = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int l = level[e];
+        if (l < 0 || l > 20 || ix[e] < 0 || iy[e] < 0 || ix[e] >= ((int64_t)nx0 << l) ||
+            iy[e] >= ((int64_t)ny0 << l)) {
+            err = "leaf " + std::to_string(e) + " outside the root grid";
+            return DGIDP_E_MESH_GAP_OR_OVERLAP;
+        }
+        if (!find.emplace(key_of(l, ix[e], iy[e]), (int)e).second) {
+            err = "duplicate leaf " + std::to_string(e);
+            return DGIDP_E_MESH_GAP_OR_OVERLAP;
+        }
+        area += std::ldexp(1.0, -2 * l);
+        lmax = std::max(lmax, l);
+    }
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t cx = ix[e], cy = iy[e];
+        for (int l = level[e] - 1; l >= 0; --l) {
+            cx >>= 1;
+            cy >>= 1;
+            if (find.count(key_of(l, cx, cy))) {
+                err = "leaf " + std::to_string(e) + " overlaps a coarser leaf";
+                return DGIDP_E_MESH_GAP_OR_OVERLAP;
+            }
+        }
+    }
+    if (std::fabs(area - (double)nx0 * ny0) > 1e-9 * nx0 * ny0) {
+        err = "leaves do not tile the domain";
+        return DGIDP_E_MESH_GAP_OR_OVERLAP;
+    }
+    auto lookup = [&](int l, int64_t i, int64_t j) -> int {
+        if (l < 0 || l > 20) return -1;
+        const int64_t nx = (int64_t)nx0 << l, ny = (int64_t)ny0 << l;
+        i = ((i % nx) + nx) % nx;
+        j = ((j % ny) + ny) % ny;
+        auto it = find.find(key_of(l, i, j));
+        return it == find.end() ? -1 : it->second;
+    };
+    // internal order: Morton order of the leaves on the finest grid
+    std::vector<std::pair<uint64_t, int>> ord((size_t)E);
+    for (int64_t e = 0; e < E; ++e) {
+        const int s = lmax - level[e];
+        ord[e] = {morton((uint64_t)ix[e] << s, (uint64_t)iy[e] << s), (int)e};
+    }
+    std::sort(ord.begin(), ord.end());
+    std::vector<int> inv(E);
+    hm.perm.assign(E, 0);
+    for (int64_t i = 0; i < E; ++i) {
+        hm.perm[i] = ord[i].second;
+        inv[ord[i].second] = (int)i;
+    }
+    hm.fnbr.assign(E * 4, -1);
+    hm.fmort.assign(E * 4, -1);
+    hm.mort.clear();
+    int M = 0;
+    // pass 1: conforming faces and large sides (mortars numbered by internal large element)
+    for (int64_t i = 0; i < E; ++i) {
+        const int e = hm.perm[i], l = level[e];
+        for (int f = 0; f < 4; ++f) {
+            const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
+            const int64_t cx = ix[e] + dx, cy = iy[e] + dy;
+            const int g = lookup(l, cx, cy);
+            if (g >= 0) {
+                hm.fnbr[i * 4 + f] = inv[g];
+                continue;
+            }
+            const int64_t nx = (int64_t)nx0 << l, ny = (int64_t)ny0 << l;
+            const int64_t wx = ((cx % nx) + nx) % nx, wy = ((cy % ny) + ny) % ny;
+            if (lookup(l - 1, wx >> 1, wy >> 1) >= 0) continue;  // small side: pass 2
+            int s0, s1;
+            if (f < 2) {
+                const int64_t sx = 2 * wx + (f == 0 ? 1 : 0);
+                s0 = lookup(l + 1, sx, 2 * wy);
+                s1 = lookup(l + 1, sx, 2 * wy + 1);
+            } else {
+                const int64_t sy = 2 * wy + (f == 2 ? 1 : 0);
+                s0 = lookup(l + 1, 2 * wx, sy);
+                s1 = lookup(l + 1, 2 * wx + 1, sy);
+            }
+            if (s0 < 0 || s1 < 0) {
+                err = "leaf " + std::to_string(e) + " face " + std::to_string(f) + " is not 2:1 balanced";
+                return DGIDP_E_MESH_NOT_BALANCED;
+            }
+            hm.fnbr[i * 4 + f] = inv[s0];
+            hm.fmort[i * 4 + f] = (M << 2);
+            hm.mort.push_back((int)i);
+            hm.mort.push_back(f);
+            hm.mort.push_back(inv[s0]);
+            hm.mort.push_back(inv[s1]);
+            ++M;
+        }
+    }
+    // pass 2: small sides point at the large element and carry their half
+    for (int S = 0; S < M; ++S) {
+        const int L = hm.mort[S * 4], f = hm.mort[S * 4 + 1];
+        for (int h = 0; h < 2; ++h) {
+            const int s = hm.mort[S * 4 + 2 + h];
+            hm.fnbr[s * 4 + (f ^ 1)] = L;
+            hm.fmort[s * 4 + (f ^ 1)] = (S << 2) | 2 | h;
+        }
+    }
+    for (int64_t i = 0; i < E * 4; ++i)
+        if (hm.fnbr[i] < 0) {
+            err = "face " + std::to_string(i % 4) + " of leaf " + std::to_string(hm.perm[i / 4]) +
+                  " has no 2:1 partner";
+            return DGIDP_E_MESH_NOT_BALANCED;
+        }
+    // mortar slots: node ids, and partners of nodes that lie on two mortars
+    const int NS = 3 * n;
+    hm.snode.assign((size_t)M * NS, 0);
+    hm.spart.assign((size_t)M * NS, -1);
+    auto fq = [&](int f, int k) { return f == 0 ? k * n : (f == 1 ? k * n + N : (f == 2 ? k : N * n + k)); };
+    std::unordered_map<int, int> first;
+    for (int S = 0; S < M; ++S) {
+        const int L = hm.mort[S * 4], f = hm.mort[S * 4 + 1];
+        for (int j = 0; j < NS; ++j) {
+            int e, ff, k;
+            if (j < n) {
+                e = L;
+                ff = f;
+                k = j;
+            } else {
+                e = hm.mort[S * 4 + 2 + (j - n) / n];
+                ff = f ^ 1;
+                k = (j - n) % n;
+            }
+            const int node = e * NN + fq(ff, k);
+            const int sid = S * NS + j;
+            hm.snode[sid] = node;
+            auto it = first.find(node);
+            if (it == first.end()) {
+                first[node] = sid;
+            } else {
+                hm.spart[sid] = it->second;
+                hm.spart[it->second] = sid;
+            }
+        }
+    }
+    hm.M = M;
+    return 0;
+}
+
+KernelParams kparams(const dgidp_ctx* c)
+{
+    KernelParams k;
+    k.gamma = c->p.gamma;
+    k.beta = c->p.beta;
+    k.limiter = c->p.limiter;
+    k.precision = c->p.precision;
+    return k;
+}
+
+// one limited forward-Euler stage: uout = a un + b FE(uin)
+int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, double a, double b,
+          DevStats* st)
+{
+    const KernelParams kp = kparams(ctx);
+    if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, ctx->dt_dev, st, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
+    if (launch_mortar(ctx->p.N, ctx->dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
+        return fail(ctx, DGIDP_E_DEVICE, "mortar kernel launch failed");
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dgidp_last_error(dgidp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
+{
+    if (!p || !out) return DGIDP_E_INVALID_ARG;
+    *out = nullptr;
+    if (p->N != 3 && p->N != 4) return DGIDP_E_UNSUPPORTED_N;
+    if (!(p->gamma > 1.0) || !(p->beta >= 0.0 && p->beta < 1.0) ||
+        (p->precision != DGIDP_FP64 && p->precision != DGIDP_MIXED) ||
+        (p->dt_mode != DGIDP_DT_IDP && p->dt_mode != DGIDP_DT_LOWORDER) ||
+        (p->limiter != DGIDP_LIMIT_NONE && p->limiter != DGIDP_LIMIT_POSITIVITY))
+        return DGIDP_E_INVALID_ARG;
+    dgidp_ctx* ctx = new dgidp_ctx();
+    ctx->p = *p;
+    ctx->stream = (hipStream_t)stream;
+    if (build_and_upload_tables(p->N, &ctx->xi)) {
+        delete ctx;
+        return DGIDP_E_DEVICE;
+    }
+    if (hipMalloc((void**)&ctx->dt_dev, sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&ctx->counter, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&ctx->stats, sizeof(DevStats)) != hipSuccess ||
+        hipMalloc((void**)&ctx->bad, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(ctx->counter, 0, sizeof(unsigned int)) != hipSuccess ||
+        hipMemset(ctx->stats, 0, sizeof(DevStats)) != hipSuccess) {
+        dgidp_destroy(ctx);
+        return DGIDP_E_DEVICE;
+    }
+    *out = ctx;
+    return 0;
+}
+
+void dgidp_destroy(dgidp_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    free_mesh(ctx);
+    dfree(ctx->dt_dev);
+    dfree(ctx->counter);
+    dfree(ctx->stats);
+    dfree(ctx->bad);
+    delete ctx;
+}
+
+int dgidp_set_stream(dgidp_ctx* ctx, void* stream)
+{
+    if (!ctx) return DGIDP_E_INVALID_ARG;
+    ctx->stream = (hipStream_t)stream;
+    return 0;
+}
+
+int dgidp_synchronize(dgidp_ctx* ctx)
+{
+    if (!ctx) return DGIDP_E_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int32_t* ix,
+                      const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
+                      int ny0)
+{
+    if (!ctx) return DGIDP_E_INVALID_ARG;
+    if (!(Lx > 0) || !(Ly > 0)) return fail(ctx, DGIDP_E_INVALID_ARG, "invalid domain size");
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_mesh(ctx);
+    const int N = ctx->p.N, n = N + 1, NN = n * n;
+    HostMesh hm;
+    std::string err;
+    const int code = build_host_mesh(N, E, level, ix, iy, nx0, ny0, hm, err);
+    if (code) return fail(ctx, code, err);
+    const int M = hm.M;
+    std::vector<double> hh(E * 2);
+    for (int64_t i = 0; i < E; ++i) {
+        const int e = hm.perm[i], l = level[e];
+        hh[2 * i] = Lx / (double)((int64_t)nx0 << l);
+        hh[2 * i + 1] = Ly / (double)((int64_t)ny0 << l);
+    }
+    ctx->E = E;
+    ctx->M = M;
+    ctx->level.assign(level, level + E);
+    ctx->ix.assign(ix, ix + E);
+    ctx->iy.assign(iy, iy + E);
+    ctx->perm = hm.perm;
+    ctx->hh = hh;
+    ctx->x0 = x0;
+    ctx->y0 = y0;
+    ctx->Lx = Lx;
+    ctx->Ly = Ly;
+    ctx->nx0 = nx0;
+    ctx->ny0 = ny0;
+    int rc = 0;
+    if ((rc = upload(ctx, ctx->dm.fnbr, hm.fnbr)) || (rc = upload(ctx, ctx->dm.fmort, hm.fmort)) ||
+        (rc = upload(ctx, ctx->dm.mort, hm.mort)) || (rc = upload(ctx, ctx->dm.h, hh)) ||
+        (rc = upload(ctx, ctx->dm.slot_node, hm.snode)) ||
+        (rc = upload(ctx, ctx->dm.slot_partner, hm.spart)) || (rc = upload(ctx, ctx->dm.perm, hm.perm)))
+        return rc;
+    const size_t sz = (size_t)E * 4 * NN * sizeof(double);
+    HIPCHK(hipMalloc((void**)&ctx->dm.slot, std::max<size_t>(1, (size_t)M * 3 * n) * kSlotW * sizeof(double)));
+    HIPCHK(hipMalloc((void**)&ctx->U, sz));
+    HIPCHK(hipMalloc((void**)&ctx->W1, sz));
+    HIPCHK(hipMalloc((void**)&ctx->W2, sz));
+    ctx->dtb = dt_blocks(N, (int)E);
+    HIPCHK(hipMalloc((void**)&ctx->partial, ctx->dtb * sizeof(double)));
+    ctx->dm.E = (int)E;
+    ctx->dm.M = M;
+    return 0;
+}
+
+int dgidp_mesh_validate(int N, int64_t n_leaves, const int8_t* level, const int32_t* ix,
+                        const int32_t* iy, int nx0, int ny0, int64_t* n_mortars,
+                        int64_t* n_two_mortar_nodes, char* msg, int msglen)
+{
+    HostMesh hm;
+    std::string err;
+    const int code = build_host_mesh(N, n_leaves, level, ix, iy, nx0, ny0, hm, err);
+    if (msg && msglen > 0) {
+        std::snprintf(msg, (size_t)msglen, "%s", err.c_str());
+    }
+    if (code) return code;
+    if (n_mortars) *n_mortars = hm.M;
+    if (n_two_mortar_nodes) {
+        int64_t c = 0;
+        for (int p : hm.spart) c += p >= 0;
+        *n_two_mortar_nodes = c / 2;
+    }
+    return 0;
+}
+
+int dgidp_mesh_info(dgidp_ctx* ctx, int64_t* n_elements, int64_t* n_mortars)
+{
+    if (!ctx) return DGIDP_E_INVALID_ARG;
+    if (n_elements) *n_elements = ctx->E;
+    if (n_mortars) *n_mortars = ctx->M;
+    return 0;
+}
+
+int dgidp_node_coords(dgidp_ctx* ctx, double* x, double* y)
+{
+    if (!ctx || !x || !y) return DGIDP_E_INVALID_ARG;
+    if (!ctx->E) return fail(ctx, DGIDP_E_NO_MESH, "no mesh");
+    const int n = ctx->p.N + 1;
+    for (int64_t e = 0; e < ctx->E; ++e) {
+        const int l = ctx->level[e];
+        const double hx = ctx->Lx / (double)((int64_t)ctx->nx0 << l);
+        const double hy = ctx->Ly / (double)((int64_t)ctx->ny0 << l);
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                const size_t i = ((size_t)e * n + b) * n + a;
+                x[i] = ctx->x0 + (ctx->ix[e] + 0.5 * (ctx->xi[a] + 1.0)) * hx;
+                y[i] = ctx->y0 + (ctx->iy[e] + 0.5 * (ctx->xi[b] + 1.0)) * hy;
+            }
+    }
+    return 0;
+}
+
+int dgidp_state_upload(dgidp_ctx* ctx, const double* u, int on_device)
+{
+    if (!ctx || !u) return DGIDP_E_INVALID_ARG;
+    if (!ctx->E) return fail(ctx, DGIDP_E_NO_MESH, "no mesh");
+    const int N = ctx->p.N, NN = (N + 1) * (N + 1);
+    const size_t sz = (size_t)ctx->E * 4 * NN * sizeof(double);
+    if (on_device) {
+        HIPCHK(hipMemsetAsync(ctx->bad, 0xff, sizeof(unsigned long long), ctx->stream));
+        if (launch_check_state(N, (int)ctx->E, ctx->p.gamma, u, ctx->bad, ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "check kernel launch failed");
+        unsigned long long bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, ctx->bad, sizeof(bad), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (bad != ~0ull)
+            return fail(ctx, DGIDP_E_STATE_INADMISSIBLE,
+                        "inadmissible state at element " + std::to_string(bad / NN) + " node " + std::to_string(bad % NN));
+        if (launch_permute(N, (int)ctx->E, ctx->dm.perm, u, ctx->U, 1, ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "permute kernel launch failed");
+    } else {
+        for (int64_t e = 0; e < ctx->E; ++e)
+            for (int q = 0; q < NN; ++q) {
+                double w[4];
+                for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
+                const double p = host_pressure(w, ctx->p.gamma);
+                if (!(std::isfinite(w[0]) && std::isfinite(w[1]) && std::isfinite(w[2]) &&
+                      std::isfinite(w[3]) && w[0] > 0.0 && p > 0.0))
+                    return fail(ctx, DGIDP_E_STATE_INADMISSIBLE,
+                                "inadmissible state at element " + std::to_string(e) + " node " + std::to_string(q));
+            }
+        HIPCHK(hipMemcpyAsync(ctx->W1, u, sz, hipMemcpyHostToDevice, ctx->stream));
+        if (launch_permute(N, (int)ctx->E, ctx->dm.perm, ctx->W1, ctx->U, 1, ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "permute kernel launch failed");
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->has_state = true;
+    return 0;
+}
+
+static int to_external(dgidp_ctx* ctx, const double* src_int, double* dst, int on_device)
+{
+    const int N = ctx->p.N, NN = (N + 1) * (N + 1);
+    const size_t sz = (size_t)ctx->E * 4 * NN * sizeof(double);
+    if (on_device) {
+        if (launch_permute(N, (int)ctx->E, ctx->dm.perm, src_int, dst, 0, ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "permute kernel launch failed");
+        return 0;
+    }
+    double* tmp = src_int == ctx->W2 ? ctx->W1 : ctx->W2;
+    if (launch_permute(N, (int)ctx->E, ctx->dm.perm, src_int, tmp, 0, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "permute kernel launch failed");
+    HIPCHK(hipMemcpyAsync(dst, tmp, sz, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int dgidp_state_download(dgidp_ctx* ctx, double* u, int on_device)
+{
+    if (!ctx || !u) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    return to_external(ctx, ctx->U, u, on_device);
+}
+
+int dgidp_rhs(dgidp_ctx* ctx, int which, double* du, int on_device)
+{
+    if (!ctx || !du || (which != DGIDP_RHS_HIGH && which != DGIDP_RHS_LOW)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    if (launch_rhs(ctx->p.N, ctx->dm, kparams(ctx), ctx->U, which, ctx->W1, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "rhs kernel launch failed");
+    return to_external(ctx, ctx->W1, du, on_device);
+}
+
+static int enqueue_dt(dgidp_ctx* ctx, double cfl, int mode, DevStats* st)
+{
+    if (launch_dt(ctx->p.N, ctx->dm, kparams(ctx), ctx->U, cfl, mode, ctx->partial, ctx->counter,
+                  ctx->dtb, ctx->dt_dev, st, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "dt kernel launch failed");
+    return 0;
+}
+
+int dgidp_max_dt(dgidp_ctx* ctx, double cfl, double* dt)
+{
+    if (!ctx || !dt || !(cfl > 0)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    int rc = enqueue_dt(ctx, cfl, ctx->p.dt_mode, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(dt, ctx->dt_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s)
+{
+    if (!ctx || !(dt > 0)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    if (ctx->p.strict_dt) {
+        double bound = 0;
+        int rc = enqueue_dt(ctx, 1.0, DGIDP_DT_IDP, nullptr);
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(&bound, ctx->dt_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (dt > bound)
+            return fail(ctx, DGIDP_E_DT, "dt above the IDP bound " + std::to_string(bound));
+    }
+    if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
+    DevStats* st = s ? ctx->stats : nullptr;
+    if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
+    int rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st);
+    if (rc) return rc;
+    std::swap(ctx->U, ctx->W1);
+    if (s) {
+        rc = sync_stats(ctx, s, 1);
+        s->dt = dt;
+        return rc;
+    }
+    return 0;
+}
+
+static int ssprk3(dgidp_ctx* ctx, dgidp_stats* s)
+{
+    DevStats* st = s ? ctx->stats : nullptr;
+    int rc;
+    if ((rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st))) return rc;
+    if ((rc = stage(ctx, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, st))) return rc;
+    if ((rc = stage(ctx, ctx->W2, ctx->U, ctx->U, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
+    return 0;
+}
+
+int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s)
+{
+    if (!ctx || !(cfl > 0)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    DevStats* st = s ? ctx->stats : nullptr;
+    if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
+    int rc = enqueue_dt(ctx, cfl, ctx->p.dt_mode, st);
+    if (rc) return rc;
+    if ((rc = ssprk3(ctx, s))) return rc;
+    if (dt_used) {
+        HIPCHK(hipMemcpyAsync(dt_used, ctx->dt_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    if (s) return sync_stats(ctx, s, 3);
+    return 0;
+}
+
+int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s)
+{
+    if (!ctx || !(dt > 0)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
+    DevStats* st = s ? ctx->stats : nullptr;
+    if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
+    int rc = ssprk3(ctx, s);
+    if (rc) return rc;
+    if (s) {
+        rc = sync_stats(ctx, s, 3);
+        s->dt = dt;
+        return rc;
+    }
+    return 0;
+}
+
+// host copy of the operator tables (flat layout, see host_tables)
+int dgidp_host_tables(int N, double* out) { return host_tables(N, out); }
+
+}  // extern "C"

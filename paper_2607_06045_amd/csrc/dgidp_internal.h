@@ -1,0 +1,86 @@
+// Internal declarations shared by the host code and the HIP kernels of dgidp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dgidp.h"
+
+namespace dgidp {
+
+constexpr int kMaxN = 4;
+constexpr int kSlotW = 12;  // doubles per mortar slot record
+
+// Face codes: fmort[e*4+f] = -1 for a conforming face, otherwise
+// (mortar << 2) | (small << 1) | half, small = 1 if e is a small side.
+inline __host__ __device__ int fm_mortar(int c) { return c >> 2; }
+inline __host__ __device__ int fm_small(int c) { return (c >> 1) & 1; }
+inline __host__ __device__ int fm_half(int c) { return c & 1; }
+
+// Operator tables of degree N, in constant memory.
+template <int N>
+struct Tab {
+    static constexpr int n = N + 1;
+    double w[n];                  // LGL quadrature weights
+    double S[n][n];               // Sbar = 2 Qbar - Bbar
+    double I[2][n][n];            // mortar interpolation: half h, small node l, large node k
+    double P[2][n][n];            // L2 projection: half h, large node k, small node l
+    double Wt[n][2 * n];          // sparse mortar weights, reference measure on [-1, 1]
+    float wf[n], Sf[n][n], If[2][n][n], Pf[2][n][n];  // FP32 copies for the mixed mode
+};
+
+// Device-side statistics accumulator.
+struct DevStats {
+    unsigned long long fv_inadmissible;
+    unsigned long long violations;
+    unsigned long long theta_vol_min_bits;   // min over positive doubles as bit patterns
+    unsigned long long theta_mort_min_bits;
+    double alpha_vol_sum;
+    double alpha_mort_sum;
+    unsigned long long nfaces;
+    unsigned long long nmortars;
+    double dt;
+};
+
+struct DevMesh {
+    int E = 0, M = 0;
+    int* fnbr = nullptr;        // [E*4] neighbour element across the face (large element for small sides)
+    int* fmort = nullptr;       // [E*4] face codes
+    int* mort = nullptr;        // [M*4] large element, large face, small 0, small 1
+    double* h = nullptr;        // [E*2] hx, hy
+    int* slot_node = nullptr;   // [M*3n] element * n^2 + node
+    int* slot_partner = nullptr;  // [M*3n] slot of the other mortar of a node on two mortars, or -1
+    double* slot = nullptr;     // [M*3n*kSlotW]
+    int* perm = nullptr;        // [E] external index of internal element e
+};
+
+struct KernelParams {
+    double gamma, beta;
+    int limiter;
+    int precision;
+};
+
+// launchers (dgidp_kernels.hip)
+int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
+                 const double* un, double* uout, double a, double b, const double* dt,
+                 DevStats* st, hipStream_t s);
+int launch_rhs(int N, const DevMesh& m, const KernelParams& kp, const double* u, int which,
+               double* du, hipStream_t s);
+int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st, hipStream_t s,
+                  double gamma, int limiter);
+int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, double cfl,
+              int mode, double* partial, unsigned int* counter, int nblocks, double* dt_out,
+              DevStats* st, hipStream_t s);
+int dt_blocks(int N, int E);
+int launch_permute(int N, int E, const int* perm, const double* src, double* dst, int to_internal,
+                   hipStream_t s);
+int launch_stats_reset(DevStats* st, hipStream_t s);
+int launch_set_double(double* p, double v, hipStream_t s);
+int launch_check_state(int N, int E, double gamma, const double* u, unsigned long long* bad,
+                       hipStream_t s);
+int upload_tables(int N, const void* host_tab, size_t bytes);
+
+}  // namespace dgidp

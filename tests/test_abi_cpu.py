@@ -1,0 +1,96 @@
+"""The C-ABI library: loads without a GPU, exports every entry point the header
+declares; its host-side operator tables agree with the oracle's independent ones."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2607_06045_amd", "libdgidp.so")
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "dgidp.h")).read()
+    return sorted(set(re.findall(r"\b(dgidp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (dgidp_\w+)", out))
+    missing = [s for s in declared() if s not in exported]
+    assert not missing, missing
+    import paper_2607_06045_amd as P
+    assert sorted(P.exported_symbols()) == declared()
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_library_tables_match_oracle(oracle, N):
+    import paper_2607_06045_amd as P
+    t = P.host_tables(N)
+    xi, w, D, S = oracle.basis(N)
+    I, Pm, W = oracle.mortar_ops(N)
+    assert np.abs(t["w"] - w).max() < 1e-15
+    assert np.abs(t["S"] - S).max() < 1e-14
+    assert np.abs(t["I"] - I).max() < 1e-14
+    assert np.abs(t["P"] - Pm).max() < 1e-14
+    assert np.abs(t["Wt"] - W).max() < 1e-15
+    assert np.array_equal(t["Wt"] > 0, W > 0)
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    import paper_2607_06045_amd as P
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(P.DgidpError):
+        P.Solver(3)
+
+
+def _two_mortar_nodes(M):
+    """Nodes on two mortar faces, counted from the oracle's face table."""
+    faces = M.faces()
+    cnt = 0
+    for e in range(M.E):
+        t = faces[e, :, 0] != 0
+        # corners: (a=0,b=0): faces 0,2; (N,0): 1,2; (0,N): 0,3; (N,N): 1,3
+        cnt += int(t[0] and t[2]) + int(t[1] and t[2]) + int(t[0] and t[3]) + int(t[1] and t[3])
+    return cnt
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_mesh_validate_matches_oracle(oracle, seed):
+    import paper_2607_06045_amd as P
+    from workloads.meshes import random_mesh
+    spec = random_mesh(seed, 4, 3, 0.4)
+    M = oracle.Mesh(3, *spec.args())
+    nm, n2 = P.validate_mesh(3, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
+    assert nm == M.M
+    assert n2 == _two_mortar_nodes(M)
+
+
+def test_mesh_validate_config_counts():
+    import paper_2607_06045_amd as P
+    from workloads.meshes import config_mesh
+    for k, mortars in ((1, 16), (2, 552), (3, 3584)):
+        spec = config_mesh(k)
+        nm, _ = P.validate_mesh(3, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
+        assert nm == mortars
+
+
+def test_mesh_validate_errors():
+    import paper_2607_06045_amd as P
+    lv = np.array([0, 0, 0, 1, 1, 1, 2, 2, 2, 2], dtype=np.int8)
+    ix = np.array([0, 0, 1, 2, 3, 3, 4, 5, 4, 5], dtype=np.int32)
+    iy = np.array([0, 1, 1, 0, 0, 1, 2, 2, 3, 3], dtype=np.int32)
+    with pytest.raises(P.DgidpError, match="NOT_BALANCED"):
+        P.validate_mesh(3, lv, ix, iy, 2, 2)
+    with pytest.raises(P.DgidpError, match="GAP_OR_OVERLAP"):
+        P.validate_mesh(3, lv[:-1], ix[:-1], iy[:-1], 2, 2)
+    with pytest.raises(P.DgidpError, match="GAP_OR_OVERLAP"):
+        P.validate_mesh(3, np.r_[lv, 1], np.r_[ix, 0], np.r_[iy, 0], 2, 2)
+    with pytest.raises(P.DgidpError, match="UNSUPPORTED_N"):
+        P.validate_mesh(7, lv, ix, iy, 2, 2)
