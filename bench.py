@@ -1,0 +1,147 @@
+"""Throughput of the IDP-limited LGL-DGSEM hot path on one MI355X.
+
+One step = one SSP-RK3 step of the whole path: the IDP time step, then three
+stages of (high-order and low-order fluxes, volume limiter, mortar limiter, SSP
+combination).  Workload: the Sedov-type blast of the configuration list (2D
+Euler, gamma = 1.4, [-1,1]^2 periodic, 64^2 base mesh refined by three levels
+inside r <= 0.3 and 2:1 balanced: 22,156 leaves, 552 mortars, N = 3,
+rho = 1, v = 0, p = 1e-5 plus a Gaussian energy bump of width 0.06, positivity
+limiting, CFL 0.5 on the IDP time step).  Inputs are synthetic and generated
+on the host from the library's node coordinates, then resident in HBM.
+
+Prints one JSON line.  value = DOF-updates/s = (elements (N+1)^2) x 3 stages x
+steps / seconds.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s (RHS+IDP limiter+RK stage), FP64 vs mixed; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes of the element stage kernel per node and launch: the
+# first stage reads u and writes u^(1) (64 B); the other two also read u^n
+# (96 B); averaged over the three launches of a step
+STAGE_BYTES_PER_NODE = (64.0 + 96.0 + 96.0) / 3.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2607_06045_amd", "csrc", "dgidp_kernels.hip")
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of the stage kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, N, seconds=12.0):
+    """The oracle as it stands, timed on this host's cores on a bounded sample
+    of the same workload (whole SSP-RK3 steps of the same mesh and state)."""
+    import numpy as np
+    import oracle as O
+    from workloads import states
+    cores = len(os.sched_getaffinity(0))
+    threads = O.set_threads(cores)
+    M = O.Mesh(N, *spec.args())
+    x, y, m = M.geometry()
+    u = states.config_state(2, x, y)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        u, st = M.ssprk3(u, 0.5)
+        steps += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    dofs = M.E * (N + 1) ** 2
+    return {"value": dofs * 3 * steps / dt, "unit": "DOF-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of the same 22,156-leaf blast workload, "
+                      f"{dt:.1f} s, OpenMP over elements"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2607_06045_amd as P
+    from workloads import states
+    from workloads.meshes import config_mesh
+
+    N = 3
+    spec = config_mesh(2)
+    s = P.Solver(N, gamma=1.4, beta=0.1, precision=P.FP64, dt_mode=P.DT_IDP,
+                 limiter=P.LIMIT_POSITIVITY)
+    s.set_mesh(*spec.args())
+    x, y = s.node_coords()
+    u0 = states.config_state(2, x, y)
+    s.upload(u0)
+    dofs = s.E * (N + 1) ** 2
+
+    for _ in range(args.warmup):
+        s.step(0.5, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step(0.5, stats=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = dofs * 3 * args.steps / elapsed
+
+    # one more step with statistics: bounds and limiter activity of the run
+    st = s.step(0.5, stats=True)
+    km = s.time_kernels(reps=50)
+    stage_bytes = STAGE_BYTES_PER_NODE * dofs
+    achieved = stage_bytes / (km["stage"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("traffic_k_stage_blast22k.json"),
+            "kernel": "k_stage<3>", "kernel_ms": km["stage"], "bytes_per_launch": stage_bytes,
+            "other_kernels_ms": {"k_mortar": km["mortar"], "k_dt": km["dt"]}}
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sedov-gaussian blast, 22156 leaves (64^2 base +3 levels, r<=0.3), "
+                               "552 mortars, N=3, positivity limiting, IDP dt CFL 0.5",
+                   "elements": s.E, "mortars": s.M, "dofs": dofs, "N": N},
+        "roofline": roof,
+        "run_stats": {"violations": st["violations"], "theta_vol_min": st["theta_vol_min"],
+                      "theta_mort_min": st["theta_mort_min"], "dt": st["dt"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,6 +65,7 @@ _SIGS = {
     "dgidp_step": (_i, [_vp, _d, ctypes.POINTER(_d), ctypes.POINTER(Stats)]),
     "dgidp_step_dt": (_i, [_vp, _d, ctypes.POINTER(Stats)]),
     "dgidp_host_tables": (_i, [_i, _vp]),
+    "dgidp_time_kernels": (_i, [_vp, _i, _vp]),
     "dgidp_mesh_validate": (_i, [_i, ctypes.c_int64, _vp, _vp, _vp, _i, _i,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.c_char_p, _i]),
@@ -221,6 +222,12 @@ class Solver:
         self._check(_lib.dgidp_step_dt(self._h, dt, ctypes.byref(st) if stats else None),
                     "dgidp_step_dt")
         return st.to_dict() if stats else None
+
+    def time_kernels(self, reps=50):
+        """Mean ms per launch of (stage kernel, mortar kernel, dt kernel), HIP events."""
+        ms = np.zeros(3)
+        self._check(_lib.dgidp_time_kernels(self._h, reps, ms.ctypes.data), "dgidp_time_kernels")
+        return {"stage": ms[0], "mortar": ms[1], "dt": ms[2]}
 
     def synchronize(self):
         self._check(_lib.dgidp_synchronize(self._h), "dgidp_synchronize")

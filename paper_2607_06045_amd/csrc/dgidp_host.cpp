@@ -641,6 +641,43 @@ int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s)
     return 0;
 }
 
+int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
+{
+    if (!ctx || !ms || reps <= 0) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    const KernelParams kp = kparams(ctx);
+    hipEvent_t ev[6];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    // stage operands as in the second SSP-RK3 stage: W1 -> W2 with u^n = U
+    HIPCHK(hipMemcpyAsync(ctx->W1, ctx->U, (size_t)ctx->E * 4 * (ctx->p.N + 1) * (ctx->p.N + 1) * sizeof(double),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    int rc = enqueue_dt(ctx, 0.5, ctx->p.dt_mode, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ev[0], ctx->stream));
+    for (int r = 0; r < reps; ++r)
+        if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, ctx->dt_dev, nullptr,
+                         ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
+    HIPCHK(hipEventRecord(ev[1], ctx->stream));
+    HIPCHK(hipEventRecord(ev[2], ctx->stream));
+    for (int r = 0; r < reps; ++r)
+        if (launch_mortar(ctx->p.N, ctx->dm, ctx->W2, 0.25, nullptr, ctx->stream, kp.gamma, kp.limiter))
+            return fail(ctx, DGIDP_E_DEVICE, "mortar kernel launch failed");
+    HIPCHK(hipEventRecord(ev[3], ctx->stream));
+    HIPCHK(hipEventRecord(ev[4], ctx->stream));
+    for (int r = 0; r < reps; ++r)
+        if ((rc = enqueue_dt(ctx, 0.5, ctx->p.dt_mode, nullptr))) return rc;
+    HIPCHK(hipEventRecord(ev[5], ctx->stream));
+    HIPCHK(hipEventSynchronize(ev[5]));
+    for (int k = 0; k < 3; ++k) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+        ms[k] = (double)t / reps;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return 0;
+}
+
 // host copy of the operator tables (flat layout, see host_tables)
 int dgidp_host_tables(int N, double* out) { return host_tables(N, out); }
 
