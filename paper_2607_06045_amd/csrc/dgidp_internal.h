@@ -25,6 +25,7 @@ template <int N>
 struct Tab {
     static constexpr int n = N + 1;
     double w[n];                  // LGL quadrature weights
+    double winv[n];               // 1 / w
     double S[n][n];               // Sbar = 2 Qbar - Bbar
     double I[2][n][n];            // mortar interpolation: half h, small node l, large node k
     double P[2][n][n];            // L2 projection: half h, large node k, small node l

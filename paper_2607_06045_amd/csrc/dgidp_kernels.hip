@@ -1,22 +1,23 @@
 // HIP kernels of dgidp for gfx950 (MI355X).
 //
 // One SSP-RK3 stage (Sec. 2.3 and Sec. 3 intro of the paper) is two kernels:
-//   k_stage   one thread per LGL node, a block holds 256 / (N+1)^2 elements.
-//             Loads the element into LDS, evaluates the Ranocha two-point
-//             fluxes once per node pair of every line, telescopes them into
-//             high-order subcell fluxes (eq. fluxdifferencingform), evaluates the
-//             LLF subcell fluxes (eq. FVmethod), the conforming surface fluxes and
-//             this element's side of every mortar (Kopriva's L2 mortar and the
-//             sparse IDP mortar flux of eq. interfaceflux_local), forms the
-//             low-order update and the positivity bounds (eq. Bounds_Positivity),
-//             limits the volume antidiffusive fluxes per subcell face and writes
-//             a u^n + b u^vol.  Nodes on mortars also leave a slot record with
-//             their mortar antidiffusive increment and their own admissible
-//             fraction of it.
+//   k_stage   one thread per LGL node; a block of 128 threads holds 8 elements
+//             (N = 3) or 5 elements (N = 4).  It stages the element in LDS,
+//             evaluates the surface fluxes with one lane per face node
+//             (conforming LLF, Kopriva's L2 mortar, the sparse IDP mortar flux
+//             of eq. interfaceflux_local), the Ranocha two-point fluxes once per
+//             node pair of every line, telescopes them into high-order subcell
+//             fluxes (eq. fluxdifferencingform), evaluates the LLF subcell
+//             fluxes (eq. FVmethod), forms the low-order update and the
+//             positivity bounds (eq. Bounds_Positivity), limits the volume
+//             antidiffusive fluxes per subcell face and writes a u^n + b u^vol.
+//             Nodes on mortars also leave a slot record with their mortar
+//             antidiffusive increment and their own admissible fraction of it.
 //   k_mortar  one thread per mortar slot: the mortar's factor is the minimum
 //             over its slots (one factor per mortar keeps the flux conservative,
-//             Sec. 2.3); the corrections are added in ascending mortar order.
-// The time step (eq. timestep_restriction) is a grid max-reduction, k_dt.
+//             Sec. 2.3); corrections are added in ascending mortar order.
+// The time step (eq. timestep_restriction) is a per-block max (k_dt) and a
+// one-block final reduction (k_dt_final).
 #include <hip/hip_runtime.h>
 
 #include "dgidp_internal.h"
@@ -50,9 +51,33 @@ __device__ __forceinline__ int xcd_batch(int bid, int nb)
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
 }
 
+// launch geometry per degree: 128-thread blocks (two waves)
+template <int N>
+struct Geo {
+    static constexpr int n = N + 1, NN = n * n;
+    static constexpr int EPB = 128 / NN;           // 8 for N = 3, 5 for N = 4
+    static constexpr int NT = EPB * NN;            // active threads
+    static constexpr int BS = 128;                 // block size
+    static constexpr int NFN = 4 * n;              // face nodes per element
+    static constexpr int NPL = n * (n - 1) / 2;    // node pairs per line
+    static constexpr int NP = 2 * n * NPL;         // node pairs per element
+    static constexpr int NF = 2 * N * n;           // interior subcell faces per element
+};
+
 // ---------------------------------------------------------------------------
-// Euler helpers
+// arithmetic helpers
 // ---------------------------------------------------------------------------
+// 1/y from the hardware estimate and two Newton steps (about 1 ulp); used on
+// the paths every node takes, where y > 0
+__device__ __forceinline__ double frcp(double y)
+{
+    double r = __builtin_amdgcn_rcp(y);
+    double e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-y, r, 1.0);
+    return fma(r, e, r);
+}
+
 struct NodeP {
     double u[4];
     double r, v1, v2, p, c;
@@ -60,7 +85,7 @@ struct NodeP {
 
 __device__ __forceinline__ void make_node(NodeP& s, double g)
 {
-    const double ir = 1.0 / s.u[0];
+    const double ir = frcp(s.u[0]);
     s.r = s.u[0];
     s.v1 = s.u[1] * ir;
     s.v2 = s.u[2] * ir;
@@ -70,10 +95,10 @@ __device__ __forceinline__ void make_node(NodeP& s, double g)
 
 __device__ __forceinline__ double pressure(const double* u, double g)
 {
-    return (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+    return (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) * frcp(u[0]));
 }
 
-// local Lax-Friedrichs flux in direction d between the low-side state L and the
+// local Lax-Friedrichs flux in direction D between the low-side state L and the
 // high-side state R
 template <int D>
 __device__ __forceinline__ void llf(const NodeP& L, const NodeP& R, double* F)
@@ -115,26 +140,51 @@ __device__ __forceinline__ void mortar_flux(int d, bool large_low, const NodeP& 
     else llf_dir(d, us, ui, F);
 }
 
-// logarithmic mean (x - y) / (ln x - ln y) from precomputed logarithms; for
-// ((x-y)/(x+y))^2 < 1e-4 the truncated series of 2 atanh (Ismail & Roe 2009)
+// logarithmic mean (x - y) / (ln x - ln y) and its reciprocal from precomputed
+// logarithms; for ((x-y)/(x+y))^2 < 1e-4 the series of 2 atanh truncated after
+// f^6 (Ismail & Roe 2009)
 __device__ __forceinline__ double lnmean(double x, double y, double lx, double ly)
 {
     const double s = x + y, d = x - y;
     if (d * d < 1e-4 * (s * s)) {
-        const double f2 = (d * d) / (s * s);
-        return s / (2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0))));
+        const double is = frcp(s);
+        const double f2 = d * d * is * is;
+        return s * frcp(2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0))));
     }
-    return d / (lx - ly);
+    return d * frcp(lx - ly);
+}
+
+__device__ __forceinline__ double inv_lnmean(double x, double y, double lx, double ly)
+{
+    const double s = x + y, d = x - y;
+    if (d * d < 1e-4 * (s * s)) {
+        const double is = frcp(s);
+        const double f2 = d * d * is * is;
+        return (2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0)))) * is;
+    }
+    return (lx - ly) * frcp(d);
 }
 
 __device__ __forceinline__ float lnmeanf(float x, float y, float lx, float ly)
 {
     const float s = x + y, d = x - y;
     if (d * d < 1e-2f * (s * s)) {
-        const float f2 = (d * d) / (s * s);
-        return s / (2.0f + f2 * (2.0f / 3.0f + f2 * (2.0f / 5.0f + f2 * (2.0f / 7.0f))));
+        const float is = __builtin_amdgcn_rcpf(s);
+        const float f2 = d * d * is * is;
+        return s * __builtin_amdgcn_rcpf(2.0f + f2 * (2.0f / 3.0f + f2 * (2.0f / 5.0f + f2 * (2.0f / 7.0f))));
     }
-    return d / (lx - ly);
+    return d * __builtin_amdgcn_rcpf(lx - ly);
+}
+
+__device__ __forceinline__ float inv_lnmeanf(float x, float y, float lx, float ly)
+{
+    const float s = x + y, d = x - y;
+    if (d * d < 1e-2f * (s * s)) {
+        const float is = __builtin_amdgcn_rcpf(s);
+        const float f2 = d * d * is * is;
+        return (2.0f + f2 * (2.0f / 3.0f + f2 * (2.0f / 5.0f + f2 * (2.0f / 7.0f)))) * is;
+    }
+    return (lx - ly) * __builtin_amdgcn_rcpf(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -143,16 +193,16 @@ __device__ __forceinline__ float lnmeanf(float x, float y, float lx, float ly)
 // g(theta) = (E - pt/(gamma-1)) rho - |m|^2 / 2 >= 0, a quadratic in theta whose
 // admissible set along the ray is an interval [0, theta*] (p is concave).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double theta_p(const double* u0, const double* dc, double pt, double g)
+__device__ __forceinline__ double theta_p(const double* u0, const double* dc, double pt, double ig1)
 {
-    const double e0 = u0[3] - pt / (g - 1.0);
+    const double e0 = u0[3] - pt * ig1;
     const double g0 = u0[0] * e0 - 0.5 * (u0[1] * u0[1] + u0[2] * u0[2]);
     if (!(g0 > 0.0) || !(u0[0] > 0.0)) return 0.0;
     // full step admissible: the interval contains [0, 1]
     const double r1 = u0[0] + dc[0];
     if (r1 > 0.0) {
         const double m1 = u0[1] + dc[1], m2 = u0[2] + dc[2];
-        const double g1v = (u0[3] + dc[3] - pt / (g - 1.0)) * r1 - 0.5 * (m1 * m1 + m2 * m2);
+        const double g1v = (u0[3] + dc[3] - pt * ig1) * r1 - 0.5 * (m1 * m1 + m2 * m2);
         if (g1v >= 0.0) return 1.0;
     }
     const double g1 = dc[0] * e0 + u0[0] * dc[3] - (u0[1] * dc[1] + u0[2] * dc[2]);
@@ -203,7 +253,8 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// block-wide accumulation of per-thread statistics, one atomic per wave
+// accumulation of per-thread statistics, one atomic per wave; every lane of
+// the wave must call it
 __device__ __forceinline__ void push_stats(DevStats* st, unsigned long long inad,
                                            unsigned long long viol, double thmin, double asum,
                                            unsigned long long nf, bool mortar)
@@ -263,11 +314,17 @@ __device__ __forceinline__ int face_q(int f, int k)
 }
 
 template <int N>
-__device__ __forceinline__ void load_node(const double* u, int e, int q, NodeP& s, double g)
+__device__ __forceinline__ void load_u(const double* u, int e, int q, double* w)
 {
     constexpr int NN = (N + 1) * (N + 1);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) s.u[v] = u[((size_t)e * 4 + v) * NN + q];
+    for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
+}
+
+template <int N>
+__device__ __forceinline__ void load_node(const double* u, int e, int q, NodeP& s, double g)
+{
+    load_u<N>(u, e, q, s.u);
     make_node(s, g);
 }
 
@@ -285,182 +342,208 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
     k = l + 1 + r;
 }
 
+// node qq of the block's element le from its LDS copies
+#define LDS_NODE(X, qq)                                   \
+    do {                                                  \
+        for (int v_ = 0; v_ < 4; ++v_) X.u[v_] = sU[le][v_][qq]; \
+        X.r = sR[le][qq][0];                              \
+        X.v1 = sR[le][qq][1];                             \
+        X.v2 = sR[le][qq][2];                             \
+        X.p = sR[le][qq][3];                              \
+        X.c = sR[le][qq][4];                              \
+    } while (0)
+
 template <int N, int MODE, bool MIXED>
-__global__ __launch_bounds__(256) void k_stage(StageArgs A)
+__global__ __launch_bounds__(128) void k_stage(StageArgs A)
 {
-    constexpr int n = N + 1, NN = n * n, EPB = 256 / NN, NT = EPB * NN;
-    constexpr int NPL = n * (n - 1) / 2;   // node pairs per line
-    constexpr int NP = 2 * n * NPL;        // node pairs per element
-    constexpr int NF = 2 * N * n;          // interior subcell faces per element
-    constexpr int PPT = NP / NN;           // pairs per thread (3 for N=3, 4 for N=4)
+    using G = Geo<N>;
+    constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
+    constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN;
     static_assert(NP % NN == 0, "pair split");
-    static_assert(NP >= 2 * NF, "face buffers reuse the pair buffer");
-    static_assert(NP * 4 >= 4 * 2 * n * 4, "mortar node fluxes reuse the pair buffer");
+    static_assert(NP >= 2 * NF, "subcell face buffers reuse the pair buffer");
+    static_assert(NP * 4 >= 48 * n, "mortar buffers reuse the pair buffer");
+    constexpr int MB = 16 * n;  // offset of the mortar-node fluxes in the pair buffer
 
     __shared__ double sU[EPB][4][NN];
-    __shared__ double sR[EPB][7][NN];  // rho, v1, v2, p, c, ln rho, ln(rho/p)
+    __shared__ double sR[EPB][NN][8];  // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
     __shared__ double sPair[EPB][NP * 4];
+    __shared__ double sFace[EPB][NFN][8];  // per face node: low-order surface term, HO - LO
     __shared__ double sTh[EPB][NN];
 
     const Tab<N>& tb = T<N>();
-    const double g = A.gamma;
+    const double g = A.gamma, ig1 = 1.0 / (g - 1.0);
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
     const int e = xcd_batch(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = tid < NT && e < A.E;
 
-    NodeP me;
+    // ---- phase 1: own node into LDS; face-node role and its remote loads ----
     double hx = 1.0, hy = 1.0;
-    int fcode[4] = {-1, -1, -1, -1}, fn[4] = {0, 0, 0, 0};
+    int fcode[4] = {-1, -1, -1, -1};
+    const bool fnode = act && q < NFN;       // this lane also evaluates one face node
+    const int ff = q / n, fk = q - (q / n) * n;  // its face and position
+    int fcode_f = -1, fnb = 0;
+    double onb[4];  // conforming neighbour state across face ff at position fk
+    bool blk_mortar = false;
     if (act) {
+        NodeP me;
         load_node<N>(A.uin, e, q, me, g);
         hx = A.h[2 * e];
         hy = A.h[2 * e + 1];
 #pragma unroll
         for (int v = 0; v < 4; ++v) sU[le][v][q] = me.u[v];
-        sR[le][0][q] = me.r;
-        sR[le][1][q] = me.v1;
-        sR[le][2][q] = me.v2;
-        sR[le][3][q] = me.p;
-        sR[le][4][q] = me.c;
-        sR[le][5][q] = log(me.r);
-        sR[le][6][q] = log(me.r / me.p);
+        const double lr = log(me.r);
+        const double z = me.r * frcp(me.p);
+        sR[le][q][0] = me.r;
+        sR[le][q][1] = me.v1;
+        sR[le][q][2] = me.v2;
+        sR[le][q][3] = me.p;
+        sR[le][q][4] = me.c;
+        sR[le][q][5] = lr;
+        sR[le][q][6] = z;
+        sR[le][q][7] = log(z);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            fcode[f] = A.fmort[e * 4 + f];
-            fn[f] = A.fnbr[e * 4 + f];
-        }
-    }
-    // faces this node lies on: position along the face
-    const int kpos[4] = {b, b, a, a};
-    const bool onf[4] = {a == 0, a == N, b == 0, b == N};
-    __syncthreads();
-
-    // ---- phase 2: mortar-node fluxes of large faces (Kopriva's L2 mortar) ----
-    if (act) {
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (!onf[f] || fcode[f] < 0 || fm_small(fcode[f])) continue;
-            const int S = fm_mortar(fcode[f]), k = kpos[f], d = f >> 1;
-            const bool large_low = f & 1;
-            for (int hh = 0; hh < 2; ++hh) {
-                const int s = A.mort[S * 4 + 2 + hh];
-                NodeP ui, us;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int j = 0; j < n; ++j) acc += tb.I[hh][k][j] * sU[le][v][face_q<N>(f, j)];
-                    ui.u[v] = acc;
-                }
-                make_node(ui, g);
-                load_node<N>(A.uin, s, face_q<N>(f ^ 1, k), us, g);
-                double F[4];
-                mortar_flux(d, large_low, ui, us, F);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sPair[le][((f * 2 + hh) * n + k) * 4 + v] = F[v];
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- phase 3: surface contributions of this node ----
-    double RsLO[4] = {0, 0, 0, 0};
-    double dS[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // HO - LO of up to two mortar faces
-    int slotid[2] = {-1, -1};
-    int nmf = 0;
-    if (act) {
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (!onf[f]) continue;
-            const int k = kpos[f], d = f >> 1;
-            const double hf = f < 2 ? hy : hx;
-            const bool low = f & 1;  // this element lies on the low side of the face
-            const double sg = low ? -1.0 : 1.0;
-            const int code = fcode[f];
-            if (code < 0) {
-                NodeP o;
-                load_node<N>(A.uin, fn[f], face_q<N>(f ^ 1, k), o, g);
-                double F[4];
-                if (low) llf_dir(d, me, o, F);
-                else llf_dir(d, o, me, F);
-                const double W = sg * tb.w[k] * hf * 0.5;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) RsLO[v] += W * F[v];
-                continue;
-            }
-            const int S = fm_mortar(code);
-            double ho[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
-            if (!fm_small(code)) {
-                // large side: project the mortar fluxes, sparse low-order pairs
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-                        for (int l = 0; l < n; ++l)
-                            acc += tb.P[hh][k][l] * sPair[le][((f * 2 + hh) * n + l) * 4 + v];
-                    ho[v] = sg * tb.w[k] * hf * 0.5 * acc;
-                }
-                for (int hh = 0; hh < 2; ++hh) {
-                    const int s = A.mort[S * 4 + 2 + hh];
-                    for (int l = 0; l < n; ++l) {
-                        const double wt = tb.Wt[k][hh * n + l];
-                        if (wt == 0.0) continue;
-                        NodeP us;
-                        load_node<N>(A.uin, s, face_q<N>(f ^ 1, l), us, g);
-                        double G[4];
-                        if (low) llf_dir(d, me, us, G);
-                        else llf_dir(d, us, me, G);
-                        const double W = sg * wt * hf * 0.5;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) lo[v] += W * G[v];
-                    }
-                }
-                slotid[nmf] = S * 3 * n + k;
+        for (int f = 0; f < 4; ++f) fcode[f] = A.fmort[e * 4 + f];
+        if (fnode) {
+            fcode_f = fcode[ff];
+            fnb = A.fnbr[e * 4 + ff];
+            if (fcode_f < 0) {
+                load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
+            } else if (!fm_small(fcode_f)) {
+                blk_mortar = true;
             } else {
-                // small side: interpolate the large face, LLF on the mortar = this face
-                const int hh = fm_half(code), L = fn[f], fl = f ^ 1;
-                const double hL = 2.0 * hf;
-                NodeP uL[n];
+                // small side: stage the large face trace for the interpolation
+                double w[4];
+                load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), w);
 #pragma unroll
-                for (int j = 0; j < n; ++j) load_node<N>(A.uin, L, face_q<N>(fl, j), uL[j], g);
-                NodeP ui;
+                for (int v = 0; v < 4; ++v) sPair[le][(ff * n + fk) * 4 + v] = w[v];
+                blk_mortar = true;
+            }
+        }
+    }
+    const bool any_mortar = __syncthreads_or(blk_mortar);
+
+    // ---- phase 2: one surface flux per face node ----
+    const int dff = ff >> 1;
+    const bool lowf = ff & 1;                    // element on the low side of face ff
+    const double sgf = lowf ? -1.0 : 1.0;
+    const double hff = ff < 2 ? hy : hx;
+    if (fnode) {
+        NodeP own;  // the face node's state
+        LDS_NODE(own, face_q<N>(ff, fk));
+        double* F8 = sFace[le][q];
+        if (fcode_f < 0) {
+            NodeP o;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o.u[v] = onb[v];
+            make_node(o, g);
+            double F[4];
+            if (lowf) llf_dir(dff, own, o, F);
+            else llf_dir(dff, o, own, F);
+            const double W = sgf * tb.w[fk] * hff * 0.5;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                F8[v] = W * F[v];
+                F8[4 + v] = 0.0;
+            }
+        } else if (!fm_small(fcode_f)) {
+            // large side: mortar-node fluxes at position fk of both halves
+            const int S = fm_mortar(fcode_f);
+            for (int hh = 0; hh < 2; ++hh) {
+                NodeP ui, us;
+                load_node<N>(A.uin, A.mort[S * 4 + 2 + hh], face_q<N>(ff ^ 1, fk), us, g);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     double acc = 0.0;
 #pragma unroll
-                    for (int j = 0; j < n; ++j) acc += tb.I[hh][k][j] * uL[j].u[v];
+                    for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sU[le][v][face_q<N>(ff, j)];
                     ui.u[v] = acc;
                 }
                 make_node(ui, g);
                 double F[4];
-                mortar_flux(d, !low, ui, me, F);
+                mortar_flux(dff, lowf, ui, us, F);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ho[v] = sg * tb.w[k] * hf * 0.5 * F[v];
+                for (int v = 0; v < 4; ++v) sPair[le][MB + ((ff * 2 + hh) * n + fk) * 4 + v] = F[v];
+            }
+        } else {
+            // small side: interpolate the large face, LLF on the mortar = this face
+            const int hh = fm_half(fcode_f);
+            NodeP ui;
 #pragma unroll
-                for (int j = 0; j < n; ++j) {
-                    const double wt = tb.Wt[j][hh * n + k];
-                    if (wt == 0.0) continue;
-                    double G[4];
-                    if (low) llf_dir(d, me, uL[j], G);
-                    else llf_dir(d, uL[j], me, G);
-                    const double W = sg * wt * hL * 0.5;
+            for (int v = 0; v < 4; ++v) {
+                double acc = 0.0;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) lo[v] += W * G[v];
-                }
-                slotid[nmf] = S * 3 * n + n + hh * n + k;
+                for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sPair[le][(ff * n + j) * 4 + v];
+                ui.u[v] = acc;
+            }
+            make_node(ui, g);
+            double F[4], ho[4], lo[4] = {0, 0, 0, 0};
+            mortar_flux(dff, !lowf, ui, own, F);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ho[v] = sgf * tb.w[fk] * hff * 0.5 * F[v];
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+                const double wt = tb.Wt[j][hh * n + fk];
+                if (wt == 0.0) continue;
+                NodeP uj;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) uj.u[v] = sPair[le][(ff * n + j) * 4 + v];
+                make_node(uj, g);
+                double Gf[4];
+                if (lowf) llf_dir(dff, own, uj, Gf);
+                else llf_dir(dff, uj, own, Gf);
+                const double W = sgf * wt * hff;  // wt * h_L / 2 with h_L = 2 h
+#pragma unroll
+                for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                RsLO[v] += lo[v];
-                dS[nmf][v] = ho[v] - lo[v];
+                F8[v] = lo[v];
+                F8[4 + v] = ho[v] - lo[v];
             }
-            ++nmf;
         }
     }
-    __syncthreads();
+    if (any_mortar) {
+        __syncthreads();
+        // ---- phase 3: large sides project the mortar fluxes; sparse low order ----
+        if (fnode && fcode_f >= 0 && !fm_small(fcode_f)) {
+            const int S = fm_mortar(fcode_f);
+            NodeP own;
+            LDS_NODE(own, face_q<N>(ff, fk));
+            double ho[4], lo[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                    for (int l = 0; l < n; ++l)
+                        acc += tb.P[hh][fk][l] * sPair[le][MB + ((ff * 2 + hh) * n + l) * 4 + v];
+                ho[v] = sgf * tb.w[fk] * hff * 0.5 * acc;
+            }
+            for (int hh = 0; hh < 2; ++hh) {
+                const int sm = A.mort[S * 4 + 2 + hh];
+                for (int l = 0; l < n; ++l) {
+                    const double wt = tb.Wt[fk][hh * n + l];
+                    if (wt == 0.0) continue;
+                    NodeP us;
+                    load_node<N>(A.uin, sm, face_q<N>(ff ^ 1, l), us, g);
+                    double Gf[4];
+                    if (lowf) llf_dir(dff, own, us, Gf);
+                    else llf_dir(dff, us, own, Gf);
+                    const double W = sgf * wt * hff * 0.5;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sFace[le][q][v] = lo[v];
+                sFace[le][q][4 + v] = ho[v] - lo[v];
+            }
+        }
+        __syncthreads();
+    }
 
     // ---- phase 4: two-point volume fluxes, once per node pair of each line ----
     if (act) {
@@ -474,38 +557,32 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
             const int ql = d == 0 ? line * n + l : l * n + line;
             const int qk = d == 0 ? line * n + k : k * n + line;
             const double scale = tb.S[l][k] * 0.5 * (d == 0 ? hy : hx);
+            const double* L = sR[le][ql];
+            const double* R = sR[le][qk];
             double f[4];
             if (!MIXED) {
-                const double rL = sR[le][0][ql], rR = sR[le][0][qk];
-                const double v1L = sR[le][1][ql], v1R = sR[le][1][qk];
-                const double v2L = sR[le][2][ql], v2R = sR[le][2][qk];
-                const double pL = sR[le][3][ql], pR = sR[le][3][qk];
-                const double rho_ln = lnmean(rL, rR, sR[le][5][ql], sR[le][5][qk]);
-                const double zL = rL / pL, zR = rR / pR;
-                const double z_ln = lnmean(zL, zR, sR[le][6][ql], sR[le][6][qk]);
-                const double vnL = d == 0 ? v1L : v2L, vnR = d == 0 ? v1R : v2R;
+                const double rho_ln = lnmean(L[0], R[0], L[5], R[5]);
+                const double iz_ln = inv_lnmean(L[6], R[6], L[7], R[7]);
+                const double vnL = d == 0 ? L[1] : L[2], vnR = d == 0 ? R[1] : R[2];
                 const double fr = rho_ln * 0.5 * (vnL + vnR);
-                const double pa = 0.5 * (pL + pR);
+                const double pa = 0.5 * (L[3] + R[3]);
                 f[0] = fr;
-                f[1] = fr * 0.5 * (v1L + v1R) + (d == 0 ? pa : 0.0);
-                f[2] = fr * 0.5 * (v2L + v2R) + (d == 1 ? pa : 0.0);
-                f[3] = fr * (0.5 * (v1L * v1R + v2L * v2R) + 1.0 / ((g - 1.0) * z_ln)) +
-                       0.5 * (pL * vnR + pR * vnL);
+                f[1] = fr * 0.5 * (L[1] + R[1]) + (d == 0 ? pa : 0.0);
+                f[2] = fr * 0.5 * (L[2] + R[2]) + (d == 1 ? pa : 0.0);
+                f[3] = fr * (0.5 * (L[1] * R[1] + L[2] * R[2]) + ig1 * iz_ln) +
+                       0.5 * (L[3] * vnR + R[3] * vnL);
             } else {
-                const float rL = (float)sR[le][0][ql], rR = (float)sR[le][0][qk];
-                const float v1L = (float)sR[le][1][ql], v1R = (float)sR[le][1][qk];
-                const float v2L = (float)sR[le][2][ql], v2R = (float)sR[le][2][qk];
-                const float pL = (float)sR[le][3][ql], pR = (float)sR[le][3][qk];
-                const float rho_ln = lnmeanf(rL, rR, (float)sR[le][5][ql], (float)sR[le][5][qk]);
-                const float zL = rL / pL, zR = rR / pR;
-                const float z_ln = lnmeanf(zL, zR, (float)sR[le][6][ql], (float)sR[le][6][qk]);
+                const float rho_ln = lnmeanf((float)L[0], (float)R[0], (float)L[5], (float)R[5]);
+                const float iz_ln = inv_lnmeanf((float)L[6], (float)R[6], (float)L[7], (float)R[7]);
+                const float v1L = (float)L[1], v1R = (float)R[1], v2L = (float)L[2], v2R = (float)R[2];
+                const float pL = (float)L[3], pR = (float)R[3];
                 const float vnL = d == 0 ? v1L : v2L, vnR = d == 0 ? v1R : v2R;
                 const float fr = rho_ln * 0.5f * (vnL + vnR);
                 const float pa = 0.5f * (pL + pR);
                 f[0] = fr;
                 f[1] = fr * 0.5f * (v1L + v1R) + (d == 0 ? pa : 0.0f);
                 f[2] = fr * 0.5f * (v2L + v2R) + (d == 1 ? pa : 0.0f);
-                f[3] = fr * (0.5f * (v1L * v1R + v2L * v2R) + 1.0f / ((float)(g - 1.0) * z_ln)) +
+                f[3] = fr * (0.5f * (v1L * v1R + v2L * v2R) + (float)ig1 * iz_ln) +
                        0.5f * (pL * vnR + pR * vnL);
             }
 #pragma unroll
@@ -533,14 +610,9 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
                     for (int v = 0; v < 4; ++v) ho[v] += sPair[le][p * 4 + v];
                 }
             const int qn = d == 0 ? q + 1 : q + n;
-            NodeP o;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o.u[v] = sU[le][v][qn];
-            o.r = sR[le][0][qn];
-            o.v1 = sR[le][1][qn];
-            o.v2 = sR[le][2][qn];
-            o.p = sR[le][3][qn];
-            o.c = sR[le][4][qn];
+            NodeP o, me;
+            LDS_NODE(o, qn);
+            LDS_NODE(me, q);
             double F[4];
             llf_dir(d, me, o, F);
             const double hs = 0.5 * (d == 0 ? hy : hx), wl = tb.w[line];
@@ -575,20 +647,45 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     __syncthreads();
 
     // ---- phase 6: low-order residual, bounds, node factors ----
-    const int fxl = b * N + a - 1, fxr = b * N + a;          // x faces left / right of the node
+    const int fxl = b * N + a - 1, fxr = b * N + a;                  // x faces left / right
     const int fyb = N * n + a * N + b - 1, fyt = N * n + a * N + b;  // y faces below / above
-    double RLO[4];
-    double mi = 1.0;
+    const bool onf[4] = {a == 0, a == N, b == 0, b == N};
+    const int fnq[4] = {0 * n + b, 1 * n + b, 2 * n + a, 3 * n + a};  // face-node index per face
+    double RLO[4], dS0[4] = {0, 0, 0, 0}, dS1[4] = {0, 0, 0, 0};
+    int slot0 = -1, slot1 = -1, nmf = 0;
+    double im = 1.0;  // 1 / m_i
     if (act) {
-        mi = 0.25 * hx * hy * tb.w[a] * tb.w[b];
+        im = 4.0 / (hx * hy) * tb.winv[a] * tb.winv[b];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            double r = RsLO[v];
+            double r = 0.0;
             if (a > 0) r += tb.w[b] * sFV[fxl * 4 + v];
             if (a < N) r -= tb.w[b] * sFV[fxr * 4 + v];
             if (b > 0) r += tb.w[a] * sFV[fyb * 4 + v];
             if (b < N) r -= tb.w[a] * sFV[fyt * 4 + v];
             RLO[v] = r;
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (!onf[f]) continue;
+            const double* F8 = sFace[le][fnq[f]];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) RLO[v] += F8[v];
+            const int code = fcode[f];
+            if (code >= 0) {
+                const int S = fm_mortar(code), k = f < 2 ? b : a;
+                const int sid = fm_small(code) ? S * 3 * n + n + fm_half(code) * n + k : S * 3 * n + k;
+                if (nmf == 0) {
+                    slot0 = sid;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) dS0[v] = F8[4 + v];
+                } else {
+                    slot1 = sid;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) dS1[v] = F8[4 + v];
+                }
+                ++nmf;
+            }
         }
     }
     if (MODE == MODE_RHS_LOW || MODE == MODE_RHS_HIGH) {
@@ -601,22 +698,22 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
                     if (a < N) r -= sA[fxr * 4 + v];
                     if (b > 0) r += sA[fyb * 4 + v];
                     if (b < N) r -= sA[fyt * 4 + v];
-                    r += dS[0][v] + dS[1][v];
+                    r += dS0[v] + dS1[v];
                 }
-                A.uout[((size_t)e * 4 + v) * NN + q] = r / mi;
+                A.uout[((size_t)e * 4 + v) * NN + q] = r * im;
             }
         }
         return;
     }
 
     const double dt = *A.dt;
-    const double dtm = dt / mi;
+    const double dtm = dt * im;
     double uFV[4], cf[4][4];
     double rmin = 0.0, pmin = 0.0, th = 1.0;
     unsigned long long inad = 0;
     if (act) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) uFV[v] = me.u[v] + dtm * RLO[v];
+        for (int v = 0; v < 4; ++v) uFV[v] = sU[le][v][q] + dtm * RLO[v];
         const double pFV = pressure(uFV, g);
         if (!(uFV[0] > 0.0) || !(pFV > 0.0)) inad = 1;
         rmin = A.beta * uFV[0];
@@ -640,7 +737,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
             for (int j = 0; j < 4; ++j) {
                 const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
                 if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
-                th = fmin(th, theta_p(uFV, dc, pt, g));
+                th = fmin(th, theta_p(uFV, dc, pt, ig1));
             }
         }
         sTh[le][q] = th;
@@ -648,10 +745,10 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     __syncthreads();
 
     // ---- phase 7: limited volume update, SSP combination, mortar slots ----
-    double uvol[4];
     double asum = 0.0, thmin = 1.0;
     unsigned long long nf = 0, viol = 0;
     if (act) {
+        double uvol[4];
         double tf[4];
         tf[0] = a > 0 ? fmin(th, sTh[le][q - 1]) : 0.0;
         tf[1] = a < N ? fmin(th, sTh[le][q + 1]) : 0.0;
@@ -671,48 +768,51 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
             ++nf;
         }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const size_t idx = ((size_t)e * 4 + v) * NN + q;
-        double r = A.b * uvol[v];
-        if (A.a != 0.0) r += A.a * A.un[idx];
-        A.uout[idx] = r;
-    }
-    if (nmf == 0) {
-        if (A.limiter != DGIDP_LIMIT_NONE && (uvol[0] < rmin || pressure(uvol, g) < pmin || uvol[0] != uvol[0]))
-            viol = 1;
-    } else {
-        const double rt = rmin * kMargin, pt = pmin * kMargin;
-        for (int j = 0; j < nmf; ++j) {
-            double c[4], dc[4];
-            bool fin = true;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                c[v] = dtm * dS[j][v];
-                dc[v] = nmf * c[v];
-                fin = fin && isfinite(dc[v]);
-            }
-            double ts = 1.0;
-            if (A.limiter != DGIDP_LIMIT_NONE) {
-                // the high-order mortar flux is undefined when the interpolated
-                // state leaves the admissible set: the mortar keeps the low-order flux
-                if (!fin) {
-                    ts = 0.0;
-                } else {
-                    if (dc[0] < 0.0) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
-                    ts = fmin(ts, theta_p(uvol, dc, pt, g));
-                }
-            }
-            double* S = A.slot + (size_t)slotid[j] * kSlotW;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                S[v] = uvol[v];
-                S[4 + v] = c[v];
-            }
-            S[8] = ts;
-            S[9] = rmin;
-            S[10] = pmin;
+        for (int v = 0; v < 4; ++v) {
+            const size_t idx = ((size_t)e * 4 + v) * NN + q;
+            double r = A.b * uvol[v];
+            if (A.a != 0.0) r += A.a * A.un[idx];
+            A.uout[idx] = r;
         }
-    }
+        if (nmf == 0) {
+            if (A.limiter != DGIDP_LIMIT_NONE &&
+                (uvol[0] < rmin || pressure(uvol, g) < pmin || uvol[0] != uvol[0]))
+                viol = 1;
+        } else {
+            const double rt = rmin * kMargin, pt = pmin * kMargin;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (j >= nmf) break;
+                const double* dS = j == 0 ? dS0 : dS1;
+                double c[4], dc[4];
+                bool fin = true;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    c[v] = dtm * dS[v];
+                    dc[v] = nmf * c[v];
+                    fin = fin && isfinite(dc[v]);
+                }
+                double ts = 1.0;
+                if (A.limiter != DGIDP_LIMIT_NONE) {
+                    // an undefined high-order mortar flux keeps the low-order flux
+                    if (!fin) {
+                        ts = 0.0;
+                    } else {
+                        if (dc[0] < 0.0) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
+                        ts = fmin(ts, theta_p(uvol, dc, pt, ig1));
+                    }
+                }
+                double* S = A.slot + (size_t)(j == 0 ? slot0 : slot1) * kSlotW;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    S[v] = uvol[v];
+                    S[4 + v] = c[v];
+                }
+                S[8] = ts;
+                S[9] = rmin;
+                S[10] = pmin;
+            }
+        }
     }
     if (A.st) push_stats(A.st, inad, viol, thmin, asum, nf, false);
 }
@@ -777,7 +877,7 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
 }
 
 // ---------------------------------------------------------------------------
-// time step: per node sum_j 2 d_ij / m_i (or the low-order estimate), grid max
+// time step: per node sum_j 2 d_ij / m_i (or the low-order estimate), block max
 // ---------------------------------------------------------------------------
 struct DtArgs {
     const double* u;
@@ -786,116 +886,125 @@ struct DtArgs {
     const int* mort;
     const double* h;
     int E;
-    double gamma, cfl;
+    double gamma;
     int mode;
     double* partial;
-    unsigned int* counter;
-    double* dt_out;
-    DevStats* st;
 };
 
-template <int N>
 __device__ __forceinline__ double wave_speed(const NodeP& s, int d)
 {
     return fabs(d == 0 ? s.v1 : s.v2) + s.c;
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void k_dt(DtArgs A)
+__global__ __launch_bounds__(128) void k_dt(DtArgs A)
 {
-    constexpr int n = N + 1, NN = n * n, EPB = 256 / NN, NT = EPB * NN;
+    using G = Geo<N>;
+    constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     __shared__ double sL[EPB][2][NN];
-    __shared__ double sRed[4];
-    __shared__ bool sLast;
+    __shared__ double sF[EPB][NFN];
+    __shared__ double sRed[2];
     const Tab<N>& tb = T<N>();
     const double g = A.gamma;
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
     const int e = blockIdx.x * EPB + le;
     const bool act = tid < NT && e < A.E;
-    NodeP me;
-    double hx = 1.0, hy = 1.0;
+    const bool idp = A.mode != DGIDP_DT_LOWORDER;
+    const bool fnode = act && idp && q < NFN;
+    const int ff = q / n, fk = q - (q / n) * n, dff = ff >> 1;
+    double hx = 1.0, hy = 1.0, lo_nb = 0.0;
+    int code = -1, nb = 0;
     if (act) {
+        NodeP me;
         load_node<N>(A.u, e, q, me, g);
         hx = A.h[2 * e];
         hy = A.h[2 * e + 1];
-        sL[le][0][q] = wave_speed<N>(me, 0);
-        sL[le][1][q] = wave_speed<N>(me, 1);
+        sL[le][0][q] = wave_speed(me, 0);
+        sL[le][1][q] = wave_speed(me, 1);
+        if (fnode) {
+            code = A.fmort[e * 4 + ff];
+            nb = A.fnbr[e * 4 + ff];
+            if (code < 0) {
+                NodeP o;
+                load_node<N>(A.u, nb, face_q<N>(ff ^ 1, fk), o, g);
+                lo_nb = wave_speed(o, dff);
+            }
+        }
+    }
+    __syncthreads();
+    if (fnode) {
+        // edges across face ff at position fk: 2 |c_ij| lambda_ij
+        const double hf = ff < 2 ? hy : hx;
+        const double lm = sL[le][dff][face_q<N>(ff, fk)];
+        double sum = 0.0;
+        if (code < 0) {
+            sum = 2.0 * tb.w[fk] * hf * 0.25 * fmax(lm, lo_nb);
+        } else if (!fm_small(code)) {
+            const int S = fm_mortar(code);
+            for (int hh = 0; hh < 2; ++hh) {
+                const int sm = A.mort[S * 4 + 2 + hh];
+                for (int l = 0; l < n; ++l) {
+                    const double wt = tb.Wt[fk][hh * n + l];
+                    if (wt == 0.0) continue;
+                    NodeP o;
+                    load_node<N>(A.u, sm, face_q<N>(ff ^ 1, l), o, g);
+                    sum += 2.0 * wt * hf * 0.25 * fmax(lm, wave_speed(o, dff));
+                }
+            }
+        } else {
+            const int hh = fm_half(code);
+            for (int j = 0; j < n; ++j) {
+                const double wt = tb.Wt[j][hh * n + fk];
+                if (wt == 0.0) continue;
+                NodeP o;
+                load_node<N>(A.u, nb, face_q<N>(ff ^ 1, j), o, g);
+                sum += 2.0 * wt * (2.0 * hf) * 0.25 * fmax(lm, wave_speed(o, dff));
+            }
+        }
+        sF[le][q] = sum;
     }
     __syncthreads();
     double s = 0.0;
     if (act) {
-        if (A.mode == DGIDP_DT_LOWORDER) {
-            s = (N + 1) * (sL[le][0][q] / hx + sL[le][1][q] / hy);
+        const double lx = sL[le][0][q], ly = sL[le][1][q];
+        if (!idp) {
+            s = (N + 1) * (lx / hx + ly / hy);
         } else {
-            const double lx = sL[le][0][q], ly = sL[le][1][q];
             double sum = 0.0;
             if (a > 0) sum += 2.0 * tb.w[b] * hy * 0.25 * fmax(lx, sL[le][0][q - 1]);
             if (a < N) sum += 2.0 * tb.w[b] * hy * 0.25 * fmax(lx, sL[le][0][q + 1]);
             if (b > 0) sum += 2.0 * tb.w[a] * hx * 0.25 * fmax(ly, sL[le][1][q - n]);
             if (b < N) sum += 2.0 * tb.w[a] * hx * 0.25 * fmax(ly, sL[le][1][q + n]);
-            const int kpos[4] = {b, b, a, a};
-            const bool onf[4] = {a == 0, a == N, b == 0, b == N};
-            for (int f = 0; f < 4; ++f) {
-                if (!onf[f]) continue;
-                const int k = kpos[f], d = f >> 1, code = A.fmort[e * 4 + f];
-                const double hf = f < 2 ? hy : hx, lm = d == 0 ? lx : ly;
-                if (code < 0) {
-                    NodeP o;
-                    load_node<N>(A.u, A.fnbr[e * 4 + f], face_q<N>(f ^ 1, k), o, g);
-                    sum += 2.0 * tb.w[k] * hf * 0.25 * fmax(lm, wave_speed<N>(o, d));
-                } else if (!fm_small(code)) {
-                    const int S = fm_mortar(code);
-                    for (int hh = 0; hh < 2; ++hh) {
-                        const int sm = A.mort[S * 4 + 2 + hh];
-                        for (int l = 0; l < n; ++l) {
-                            const double wt = tb.Wt[k][hh * n + l];
-                            if (wt == 0.0) continue;
-                            NodeP o;
-                            load_node<N>(A.u, sm, face_q<N>(f ^ 1, l), o, g);
-                            sum += 2.0 * wt * hf * 0.25 * fmax(lm, wave_speed<N>(o, d));
-                        }
-                    }
-                } else {
-                    const int hh = fm_half(code), L = A.fnbr[e * 4 + f];
-                    for (int j = 0; j < n; ++j) {
-                        const double wt = tb.Wt[j][hh * n + k];
-                        if (wt == 0.0) continue;
-                        NodeP o;
-                        load_node<N>(A.u, L, face_q<N>(f ^ 1, j), o, g);
-                        sum += 2.0 * wt * (2.0 * hf) * 0.25 * fmax(lm, wave_speed<N>(o, d));
-                    }
-                }
-            }
-            s = sum / (0.25 * hx * hy * tb.w[a] * tb.w[b]);
+            if (a == 0) sum += sF[le][0 * n + b];
+            if (a == N) sum += sF[le][1 * n + b];
+            if (b == 0) sum += sF[le][2 * n + a];
+            if (b == N) sum += sF[le][3 * n + a];
+            s = sum * 4.0 / (hx * hy) * tb.winv[a] * tb.winv[b];
         }
     }
     s = wave_max(s);
     if ((tid & 63) == 0) sRed[tid >> 6] = s;
     __syncthreads();
-    if (tid == 0) {
-        double m = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
-        A.partial[blockIdx.x] = m;
-        __threadfence();
-        const unsigned int done = atomicAdd(A.counter, 1u);
-        sLast = (done == gridDim.x - 1);
-    }
+    if (tid == 0) A.partial[blockIdx.x] = fmax(sRed[0], sRed[1]);
+}
+
+// one block: max of the per-block maxima, dt = cfl / max
+__global__ __launch_bounds__(256) void k_dt_final(const double* partial, int nb, double cfl,
+                                                  double* dt_out, DevStats* st)
+{
+    __shared__ double sRed[4];
+    const int tid = threadIdx.x;
+    double m = 0.0;
+    for (int i = tid; i < nb; i += 256) m = fmax(m, partial[i]);
+    m = wave_max(m);
+    if ((tid & 63) == 0) sRed[tid >> 6] = m;
     __syncthreads();
-    if (sLast) {
-        // last block: reduce the per-block maxima, publish dt, re-arm the counter
-        __threadfence();
-        double m = 0.0;
-        for (int i = tid; i < (int)gridDim.x; i += 256) m = fmax(m, __builtin_nontemporal_load(&A.partial[i]));
-        m = wave_max(m);
-        if ((tid & 63) == 0) sRed[tid >> 6] = m;
-        __syncthreads();
-        if (tid == 0) {
-            m = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
-            const double dt = A.cfl / m;
-            *A.dt_out = dt;
-            if (A.st) A.st->dt = dt;
-            *A.counter = 0u;
-        }
+    if (tid == 0) {
+        m = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+        const double dt = cfl / m;
+        *dt_out = dt;
+        if (st) st->dt = dt;
     }
 }
 
@@ -941,7 +1050,7 @@ __global__ void k_check_state(int total_nodes, int NN, double g, const double* u
     const int e = i / NN, q = i - e * NN;
     double w[4];
     for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
-    const double p = pressure(w, g);
+    const double p = (g - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
     const bool ok = isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2]) && isfinite(w[3]) &&
                     w[0] > 0.0 && p > 0.0;
     if (!ok) atomicMin(bad, (unsigned long long)i);
@@ -955,7 +1064,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
                    double* uout, double a, double b, const double* dt, DevStats* st, int mode,
                    hipStream_t s)
 {
-    constexpr int NN = (N + 1) * (N + 1), EPB = 256 / NN;
+    using G = Geo<N>;
     StageArgs A;
     A.uin = uin;
     A.un = un;
@@ -973,16 +1082,17 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.beta = kp.beta;
     A.limiter = kp.limiter;
     A.st = st;
-    const int grid = (m.E + EPB - 1) / EPB;
+    const int grid = (m.E + G::EPB - 1) / G::EPB;
     const bool mixed = kp.precision == DGIDP_MIXED;
+    const dim3 blk(G::BS);
     if (mode == MODE_STAGE) {
-        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true>), dim3(grid), dim3(256), 0, s, A);
-        else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false>), dim3(grid), dim3(256), 0, s, A);
+        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true>), dim3(grid), blk, 0, s, A);
+        else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false>), dim3(grid), blk, 0, s, A);
     } else if (mode == MODE_RHS_HIGH) {
-        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true>), dim3(grid), dim3(256), 0, s, A);
-        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false>), dim3(grid), dim3(256), 0, s, A);
+        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true>), dim3(grid), blk, 0, s, A);
+        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false>), dim3(grid), blk, 0, s, A);
     } else {
-        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false>), dim3(grid), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false>), dim3(grid), blk, 0, s, A);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1027,7 +1137,7 @@ int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st,
 
 int dt_blocks(int N, int E)
 {
-    const int EPB = 256 / ((N + 1) * (N + 1));
+    const int EPB = 128 / ((N + 1) * (N + 1));
     return (E + EPB - 1) / EPB;
 }
 
@@ -1035,6 +1145,7 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
               int mode, double* partial, unsigned int* counter, int nblocks, double* dt_out,
               DevStats* st, hipStream_t s)
 {
+    (void)counter;
     DtArgs A;
     A.u = u;
     A.fnbr = m.fnbr;
@@ -1043,15 +1154,12 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
     A.h = m.h;
     A.E = m.E;
     A.gamma = kp.gamma;
-    A.cfl = cfl;
     A.mode = mode;
     A.partial = partial;
-    A.counter = counter;
-    A.dt_out = dt_out;
-    A.st = st;
-    if (N == 3) hipLaunchKernelGGL(k_dt<3>, dim3(nblocks), dim3(256), 0, s, A);
-    else if (N == 4) hipLaunchKernelGGL(k_dt<4>, dim3(nblocks), dim3(256), 0, s, A);
+    if (N == 3) hipLaunchKernelGGL(k_dt<3>, dim3(nblocks), dim3(128), 0, s, A);
+    else if (N == 4) hipLaunchKernelGGL(k_dt<4>, dim3(nblocks), dim3(128), 0, s, A);
     else return -1;
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, partial, nblocks, cfl, dt_out, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -202,6 +202,7 @@ void build(Tab<N>& t)
         }
     for (int i = 0; i < n; ++i) {
         t.w[i] = (double)w[i];
+        t.winv[i] = (double)(1 / w[i]);
         for (int j = 0; j < n; ++j) {
             ld s = 2 * w[i] * D[i][j];
             if (i == j && i == 0) s += 1;
