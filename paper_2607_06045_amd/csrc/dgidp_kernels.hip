@@ -62,7 +62,28 @@ struct Geo {
     static constexpr int NPL = n * (n - 1) / 2;    // node pairs per line
     static constexpr int NP = 2 * n * NPL;         // node pairs per element
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
+    // padded LDS strides: a half wave covers two N = 3 elements; an element's
+    // stride of 16 (mod 32) doubles puts the second one on the other 32 banks
+    static constexpr int PU = N == 3 ? NN + 4 : NN + 1;    // sU variable stride
+    static constexpr int PR = N == 3 ? NN + 2 : NN + 1;    // sR variable stride
+    static constexpr int PP = N == 3 ? NP + 4 : NP;        // sPair variable stride
+    static constexpr int PFN = NFN + 2;                    // sFace variable stride
+    static constexpr int PT = N == 3 ? NN : NN + 1;        // sTh element stride
 };
+
+// (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
+template <int N>
+constexpr unsigned long long pair_code()
+{
+    unsigned long long c = 0;
+    int i = 0;
+    for (int l = 0; l <= N; ++l)
+        for (int k = l + 1; k <= N; ++k) {
+            c |= (unsigned long long)(l | (k << 3)) << (6 * i);
+            ++i;
+        }
+    return c;
+}
 
 // ---------------------------------------------------------------------------
 // arithmetic helpers
@@ -346,11 +367,11 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
 #define LDS_NODE(X, qq)                                   \
     do {                                                  \
         for (int v_ = 0; v_ < 4; ++v_) X.u[v_] = sU[le][v_][qq]; \
-        X.r = sR[le][qq][0];                              \
-        X.v1 = sR[le][qq][1];                             \
-        X.v2 = sR[le][qq][2];                             \
-        X.p = sR[le][qq][3];                              \
-        X.c = sR[le][qq][4];                              \
+        X.r = sR[le][0][qq];                              \
+        X.v1 = sR[le][1][qq];                             \
+        X.v2 = sR[le][2][qq];                             \
+        X.p = sR[le][3][qq];                              \
+        X.c = sR[le][4][qq];                              \
     } while (0)
 
 template <int N, int MODE, bool MIXED>
@@ -360,15 +381,17 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN;
     static_assert(NP % NN == 0, "pair split");
-    static_assert(NP >= 2 * NF, "subcell face buffers reuse the pair buffer");
-    static_assert(NP * 4 >= 48 * n, "mortar buffers reuse the pair buffer");
-    constexpr int MB = 16 * n;  // offset of the mortar-node fluxes in the pair buffer
+    static_assert(G::PP >= 2 * NF, "subcell face buffers reuse the pair buffer");
+    static_assert(G::PP >= 12 * n, "mortar buffers reuse the pair buffer");
+    constexpr int MB = 4 * n;  // offset of the mortar-node fluxes in the pair buffer
+    constexpr unsigned long long PCODE = pair_code<N>();
 
-    __shared__ double sU[EPB][4][NN];
-    __shared__ double sR[EPB][NN][8];  // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
-    __shared__ double sPair[EPB][NP * 4];
-    __shared__ double sFace[EPB][NFN][8];  // per face node: low-order surface term, HO - LO
-    __shared__ double sTh[EPB][NN];
+    // variable-major, padded (see Geo)
+    __shared__ double sU[EPB][4][G::PU];
+    __shared__ double sR[EPB][8][G::PR];     // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
+    __shared__ double sPair[EPB][4][G::PP];  // pair fluxes; later FV and A of the subcell faces
+    __shared__ double sFace[EPB][8][G::PFN]; // per face node: low-order surface term, HO - LO
+    __shared__ double sTh[EPB][G::PT];
 
     const Tab<N>& tb = T<N>();
     const double g = A.gamma, ig1 = 1.0 / (g - 1.0);
@@ -394,14 +417,14 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         for (int v = 0; v < 4; ++v) sU[le][v][q] = me.u[v];
         const double lr = log(me.r);
         const double z = me.r * frcp(me.p);
-        sR[le][q][0] = me.r;
-        sR[le][q][1] = me.v1;
-        sR[le][q][2] = me.v2;
-        sR[le][q][3] = me.p;
-        sR[le][q][4] = me.c;
-        sR[le][q][5] = lr;
-        sR[le][q][6] = z;
-        sR[le][q][7] = log(z);
+        sR[le][0][q] = me.r;
+        sR[le][1][q] = me.v1;
+        sR[le][2][q] = me.v2;
+        sR[le][3][q] = me.p;
+        sR[le][4][q] = me.c;
+        sR[le][5][q] = lr;
+        sR[le][6][q] = z;
+        sR[le][7][q] = log(z);
 #pragma unroll
         for (int f = 0; f < 4; ++f) fcode[f] = A.fmort[e * 4 + f];
         if (fnode) {
@@ -416,7 +439,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 double w[4];
                 load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), w);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) sPair[le][(ff * n + fk) * 4 + v] = w[v];
+                for (int v = 0; v < 4; ++v) sPair[le][v][ff * n + fk] = w[v];
                 blk_mortar = true;
             }
         }
@@ -431,7 +454,6 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     if (fnode) {
         NodeP own;  // the face node's state
         LDS_NODE(own, face_q<N>(ff, fk));
-        double* F8 = sFace[le][q];
         if (fcode_f < 0) {
             NodeP o;
 #pragma unroll
@@ -443,8 +465,8 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             const double W = sgf * tb.w[fk] * hff * 0.5;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                F8[v] = W * F[v];
-                F8[4 + v] = 0.0;
+                sFace[le][v][q] = W * F[v];
+                sFace[le][4 + v][q] = 0.0;
             }
         } else if (!fm_small(fcode_f)) {
             // large side: mortar-node fluxes at position fk of both halves
@@ -463,7 +485,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 double F[4];
                 mortar_flux(dff, lowf, ui, us, F);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) sPair[le][MB + ((ff * 2 + hh) * n + fk) * 4 + v] = F[v];
+                for (int v = 0; v < 4; ++v) sPair[le][v][MB + (ff * 2 + hh) * n + fk] = F[v];
             }
         } else {
             // small side: interpolate the large face, LLF on the mortar = this face
@@ -473,7 +495,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             for (int v = 0; v < 4; ++v) {
                 double acc = 0.0;
 #pragma unroll
-                for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sPair[le][(ff * n + j) * 4 + v];
+                for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sPair[le][v][ff * n + j];
                 ui.u[v] = acc;
             }
             make_node(ui, g);
@@ -487,7 +509,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 if (wt == 0.0) continue;
                 NodeP uj;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) uj.u[v] = sPair[le][(ff * n + j) * 4 + v];
+                for (int v = 0; v < 4; ++v) uj.u[v] = sPair[le][v][ff * n + j];
                 make_node(uj, g);
                 double Gf[4];
                 if (lowf) llf_dir(dff, own, uj, Gf);
@@ -498,8 +520,8 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                F8[v] = lo[v];
-                F8[4 + v] = ho[v] - lo[v];
+                sFace[le][v][q] = lo[v];
+                sFace[le][4 + v][q] = ho[v] - lo[v];
             }
         }
     }
@@ -518,7 +540,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
                     for (int l = 0; l < n; ++l)
-                        acc += tb.P[hh][fk][l] * sPair[le][MB + ((ff * 2 + hh) * n + l) * 4 + v];
+                        acc += tb.P[hh][fk][l] * sPair[le][v][MB + (ff * 2 + hh) * n + l];
                 ho[v] = sgf * tb.w[fk] * hff * 0.5 * acc;
             }
             for (int hh = 0; hh < 2; ++hh) {
@@ -538,8 +560,8 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                sFace[le][q][v] = lo[v];
-                sFace[le][q][4 + v] = ho[v] - lo[v];
+                sFace[le][v][q] = lo[v];
+                sFace[le][4 + v][q] = ho[v] - lo[v];
             }
         }
         __syncthreads();
@@ -552,13 +574,17 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             const int p = q + i * NN;
             const int d = p / (n * NPL), rem = p - d * (n * NPL);
             const int line = rem / NPL, pi = rem - line * NPL;
-            int l, k;
-            pair_lk<N>(pi, l, k);
+            const int lk = (int)((PCODE >> (6 * pi)) & 63ull);
+            const int l = lk & 7, k = lk >> 3;
             const int ql = d == 0 ? line * n + l : l * n + line;
             const int qk = d == 0 ? line * n + k : k * n + line;
             const double scale = tb.S[l][k] * 0.5 * (d == 0 ? hy : hx);
-            const double* L = sR[le][ql];
-            const double* R = sR[le][qk];
+            double L[8], R[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                L[j] = sR[le][j][ql];
+                R[j] = sR[le][j][qk];
+            }
             double f[4];
             if (!MIXED) {
                 const double rho_ln = lnmean(L[0], R[0], L[5], R[5]);
@@ -586,7 +612,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                        0.5f * (pL * vnR + pR * vnL);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sPair[le][p * 4 + v] = scale * f[v];
+            for (int v = 0; v < 4; ++v) sPair[le][v][p] = scale * f[v];
         }
     }
     __syncthreads();
@@ -607,7 +633,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                     const int pi = l * (2 * n - l - 1) / 2 + (k - l - 1);
                     const int p = d * n * NPL + line * NPL + pi;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) ho[v] += sPair[le][p * 4 + v];
+                    for (int v = 0; v < 4; ++v) ho[v] += sPair[le][v][p];
                 }
             const int qn = d == 0 ? q + 1 : q + n;
             NodeP o, me;
@@ -624,23 +650,21 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         }
     }
     __syncthreads();
-    double* sFV = sPair[le];
-    double* sA = sPair[le] + NF * 4;
     if (act) {
         if (a < N) {
             const int fi = b * N + a;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                sFV[fi * 4 + v] = FVo[0][v];
-                sA[fi * 4 + v] = Ao[0][v];
+                sPair[le][v][fi] = FVo[0][v];
+                sPair[le][v][NF + fi] = Ao[0][v];
             }
         }
         if (b < N) {
             const int fi = N * n + a * N + b;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                sFV[fi * 4 + v] = FVo[1][v];
-                sA[fi * 4 + v] = Ao[1][v];
+                sPair[le][v][fi] = FVo[1][v];
+                sPair[le][v][NF + fi] = Ao[1][v];
             }
         }
     }
@@ -659,18 +683,18 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double r = 0.0;
-            if (a > 0) r += tb.w[b] * sFV[fxl * 4 + v];
-            if (a < N) r -= tb.w[b] * sFV[fxr * 4 + v];
-            if (b > 0) r += tb.w[a] * sFV[fyb * 4 + v];
-            if (b < N) r -= tb.w[a] * sFV[fyt * 4 + v];
+            if (a > 0) r += tb.w[b] * sPair[le][v][fxl];
+            if (a < N) r -= tb.w[b] * sPair[le][v][fxr];
+            if (b > 0) r += tb.w[a] * sPair[le][v][fyb];
+            if (b < N) r -= tb.w[a] * sPair[le][v][fyt];
             RLO[v] = r;
         }
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             if (!onf[f]) continue;
-            const double* F8 = sFace[le][fnq[f]];
+            const int fq = fnq[f];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) RLO[v] += F8[v];
+            for (int v = 0; v < 4; ++v) RLO[v] += sFace[le][v][fq];
             const int code = fcode[f];
             if (code >= 0) {
                 const int S = fm_mortar(code), k = f < 2 ? b : a;
@@ -678,11 +702,11 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 if (nmf == 0) {
                     slot0 = sid;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) dS0[v] = F8[4 + v];
+                    for (int v = 0; v < 4; ++v) dS0[v] = sFace[le][4 + v][fq];
                 } else {
                     slot1 = sid;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) dS1[v] = F8[4 + v];
+                    for (int v = 0; v < 4; ++v) dS1[v] = sFace[le][4 + v][fq];
                 }
                 ++nmf;
             }
@@ -694,10 +718,10 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             for (int v = 0; v < 4; ++v) {
                 double r = RLO[v];
                 if (MODE == MODE_RHS_HIGH) {
-                    if (a > 0) r += sA[fxl * 4 + v];
-                    if (a < N) r -= sA[fxr * 4 + v];
-                    if (b > 0) r += sA[fyb * 4 + v];
-                    if (b < N) r -= sA[fyt * 4 + v];
+                    if (a > 0) r += sPair[le][v][NF + fxl];
+                    if (a < N) r -= sPair[le][v][NF + fxr];
+                    if (b > 0) r += sPair[le][v][NF + fyb];
+                    if (b < N) r -= sPair[le][v][NF + fyt];
                     r += dS0[v] + dS1[v];
                 }
                 A.uout[((size_t)e * 4 + v) * NN + q] = r * im;
@@ -720,10 +744,10 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         pmin = A.beta * pFV;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            cf[0][v] = a > 0 ? dtm * sA[fxl * 4 + v] : 0.0;
-            cf[1][v] = a < N ? -dtm * sA[fxr * 4 + v] : 0.0;
-            cf[2][v] = b > 0 ? dtm * sA[fyb * 4 + v] : 0.0;
-            cf[3][v] = b < N ? -dtm * sA[fyt * 4 + v] : 0.0;
+            cf[0][v] = a > 0 ? dtm * sPair[le][v][NF + fxl] : 0.0;
+            cf[1][v] = a < N ? -dtm * sPair[le][v][NF + fxr] : 0.0;
+            cf[2][v] = b > 0 ? dtm * sPair[le][v][NF + fyb] : 0.0;
+            cf[3][v] = b < N ? -dtm * sPair[le][v][NF + fyt] : 0.0;
         }
         if (A.limiter != DGIDP_LIMIT_NONE) {
             // Zalesak-type factor for the density: sum of the negative increments
