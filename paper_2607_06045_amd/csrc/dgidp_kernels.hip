@@ -64,11 +64,10 @@ struct Geo {
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
     // padded LDS strides: a half wave covers two N = 3 elements; an element's
     // stride of 16 (mod 32) doubles puts the second one on the other 32 banks
-    static constexpr int PU = N == 3 ? NN + 4 : NN + 1;    // sU variable stride
+    static constexpr int PU = N == 3 ? NN + 2 : NN + 1;    // sU variable stride
     static constexpr int PR = N == 3 ? NN + 2 : NN + 1;    // sR variable stride
     static constexpr int PP = N == 3 ? NP + 4 : NP;        // sPair variable stride
-    static constexpr int PFN = NFN + 2;                    // sFace variable stride
-    static constexpr int PT = N == 3 ? NN : NN + 1;        // sTh element stride
+    static constexpr int PFN = N == 3 ? NFN + 4 : NFN + 2;  // sFace variable stride
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
@@ -390,8 +389,9 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     __shared__ double sU[EPB][4][G::PU];
     __shared__ double sR[EPB][8][G::PR];     // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
     __shared__ double sPair[EPB][4][G::PP];  // pair fluxes; later FV and A of the subcell faces
-    __shared__ double sFace[EPB][8][G::PFN]; // per face node: low-order surface term, HO - LO
-    __shared__ double sTh[EPB][G::PT];
+    __shared__ double sFace[EPB][4][G::PFN]; // per face node: low-order surface term
+    // node factors of the volume limiter reuse the first row of sR (free after phase 5)
+#define sTh(qq) sR[le][0][qq]
 
     const Tab<N>& tb = T<N>();
     const double g = A.gamma, ig1 = 1.0 / (g - 1.0);
@@ -407,8 +407,14 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     const int ff = q / n, fk = q - (q / n) * n;  // its face and position
     int fcode_f = -1, fnb = 0;
     double onb[4];  // conforming neighbour state across face ff at position fk
+    double un4[4] = {0, 0, 0, 0};  // u^n of this node for the SSP combination
     bool blk_mortar = false;
     if (act) {
+        // issue the independent global loads first
+#pragma unroll
+        for (int f = 0; f < 4; ++f) fcode[f] = A.fmort[e * 4 + f];
+        if (fnode) fnb = A.fnbr[e * 4 + ff];
+        if (MODE == MODE_STAGE && A.a != 0.0) load_u<N>(A.un, e, q, un4);
         NodeP me;
         load_node<N>(A.uin, e, q, me, g);
         hx = A.h[2 * e];
@@ -425,11 +431,8 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         sR[le][5][q] = lr;
         sR[le][6][q] = z;
         sR[le][7][q] = log(z);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) fcode[f] = A.fmort[e * 4 + f];
         if (fnode) {
             fcode_f = fcode[ff];
-            fnb = A.fnbr[e * 4 + ff];
             if (fcode_f < 0) {
                 load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
             } else if (!fm_small(fcode_f)) {
@@ -464,10 +467,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             else llf_dir(dff, o, own, F);
             const double W = sgf * tb.w[fk] * hff * 0.5;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                sFace[le][v][q] = W * F[v];
-                sFace[le][4 + v][q] = 0.0;
-            }
+            for (int v = 0; v < 4; ++v) sFace[le][v][q] = W * F[v];
         } else if (!fm_small(fcode_f)) {
             // large side: mortar-node fluxes at position fk of both halves
             const int S = fm_mortar(fcode_f);
@@ -519,9 +519,12 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                sFace[le][v][q] = lo[v];
-                sFace[le][4 + v][q] = ho[v] - lo[v];
+            for (int v = 0; v < 4; ++v) sFace[le][v][q] = lo[v];
+            {
+                const int S = fm_mortar(fcode_f);
+                double* R = A.slot + (size_t)(S * 3 * n + n + fm_half(fcode_f) * n + fk) * kSlotW;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R[4 + v] = ho[v] - lo[v];
             }
         }
     }
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             NodeP own;
             LDS_NODE(own, face_q<N>(ff, fk));
             double ho[4], lo[4] = {0, 0, 0, 0};
-#pragma unroll
+#pragma unroll 1
             for (int v = 0; v < 4; ++v) {
                 double acc = 0.0;
 #pragma unroll
@@ -559,9 +562,11 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 }
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                sFace[le][v][q] = lo[v];
-                sFace[le][4 + v][q] = ho[v] - lo[v];
+            for (int v = 0; v < 4; ++v) sFace[le][v][q] = lo[v];
+            {
+                double* R = A.slot + (size_t)(S * 3 * n + fk) * kSlotW;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R[4 + v] = ho[v] - lo[v];
             }
         }
         __syncthreads();
@@ -702,11 +707,11 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 if (nmf == 0) {
                     slot0 = sid;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) dS0[v] = sFace[le][4 + v][fq];
+                    for (int v = 0; v < 4; ++v) dS0[v] = A.slot[(size_t)sid * kSlotW + 4 + v];
                 } else {
                     slot1 = sid;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) dS1[v] = sFace[le][4 + v][fq];
+                    for (int v = 0; v < 4; ++v) dS1[v] = A.slot[(size_t)sid * kSlotW + 4 + v];
                 }
                 ++nmf;
             }
@@ -764,7 +769,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 th = fmin(th, theta_p(uFV, dc, pt, ig1));
             }
         }
-        sTh[le][q] = th;
+        sTh(q) = th;
     }
     __syncthreads();
 
@@ -774,10 +779,10 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     if (act) {
         double uvol[4];
         double tf[4];
-        tf[0] = a > 0 ? fmin(th, sTh[le][q - 1]) : 0.0;
-        tf[1] = a < N ? fmin(th, sTh[le][q + 1]) : 0.0;
-        tf[2] = b > 0 ? fmin(th, sTh[le][q - n]) : 0.0;
-        tf[3] = b < N ? fmin(th, sTh[le][q + n]) : 0.0;
+        tf[0] = a > 0 ? fmin(th, sTh(q - 1)) : 0.0;
+        tf[1] = a < N ? fmin(th, sTh(q + 1)) : 0.0;
+        tf[2] = b > 0 ? fmin(th, sTh(q - n)) : 0.0;
+        tf[3] = b < N ? fmin(th, sTh(q + n)) : 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             uvol[v] = uFV[v] + tf[0] * cf[0][v] + tf[1] * cf[1][v] + tf[2] * cf[2][v] + tf[3] * cf[3][v];
@@ -795,7 +800,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         for (int v = 0; v < 4; ++v) {
             const size_t idx = ((size_t)e * 4 + v) * NN + q;
             double r = A.b * uvol[v];
-            if (A.a != 0.0) r += A.a * A.un[idx];
+            if (A.a != 0.0) r += A.a * un4[v];
             A.uout[idx] = r;
         }
         if (nmf == 0) {
