@@ -34,11 +34,11 @@ struct dgidp_ctx {
     DevMesh dm;
     double *U = nullptr, *W1 = nullptr, *W2 = nullptr;
     double* dt_dev = nullptr;
-    double* partial = nullptr;
-    unsigned int* counter = nullptr;
+    // two dt accumulators used in turn: the dt kernel fills one and clears the other
+    unsigned long long* acc = nullptr;
+    int acc_slot = 0;
     DevStats* stats = nullptr;
     unsigned long long* bad = nullptr;
-    int dtb = 0;
     bool has_state = false;
 };
 
@@ -77,7 +77,6 @@ void free_mesh(dgidp_ctx* c)
     dfree(c->U);
     dfree(c->W1);
     dfree(c->W2);
-    dfree(c->partial);
     c->dm = DevMesh();
     c->E = c->M = 0;
     c->has_state = false;
@@ -307,12 +306,19 @@ KernelParams kparams(const dgidp_ctx* c)
     return k;
 }
 
+DtSource stored_dt(const dgidp_ctx* c)
+{
+    DtSource d;
+    d.dt = c->dt_dev;
+    return d;
+}
+
 // one limited forward-Euler stage: uout = a un + b FE(uin)
 int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, double a, double b,
-          DevStats* st)
+          DevStats* st, const DtSource& dt)
 {
     const KernelParams kp = kparams(ctx);
-    if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, ctx->dt_dev, st, ctx->stream))
+    if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
     if (launch_mortar(ctx->p.N, ctx->dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
         return fail(ctx, DGIDP_E_DEVICE, "mortar kernel launch failed");
@@ -343,10 +349,10 @@ int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
         return DGIDP_E_DEVICE;
     }
     if (hipMalloc((void**)&ctx->dt_dev, sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&ctx->counter, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&ctx->acc, 2 * kDtWords * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&ctx->stats, sizeof(DevStats)) != hipSuccess ||
         hipMalloc((void**)&ctx->bad, sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(ctx->counter, 0, sizeof(unsigned int)) != hipSuccess ||
+        hipMemset(ctx->acc, 0, 2 * kDtWords * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(ctx->stats, 0, sizeof(DevStats)) != hipSuccess) {
         dgidp_destroy(ctx);
         return DGIDP_E_DEVICE;
@@ -362,7 +368,7 @@ void dgidp_destroy(dgidp_ctx* ctx)
     else (void)hipDeviceSynchronize();
     free_mesh(ctx);
     dfree(ctx->dt_dev);
-    dfree(ctx->counter);
+    dfree(ctx->acc);
     dfree(ctx->stats);
     dfree(ctx->bad);
     delete ctx;
@@ -426,8 +432,6 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     HIPCHK(hipMalloc((void**)&ctx->U, sz));
     HIPCHK(hipMalloc((void**)&ctx->W1, sz));
     HIPCHK(hipMalloc((void**)&ctx->W2, sz));
-    ctx->dtb = dt_blocks(N, (int)E);
-    HIPCHK(hipMalloc((void**)&ctx->partial, ctx->dtb * sizeof(double)));
     ctx->dm.E = (int)E;
     ctx->dm.M = M;
     return 0;
@@ -551,11 +555,39 @@ int dgidp_rhs(dgidp_ctx* ctx, int which, double* du, int on_device)
     return to_external(ctx, ctx->W1, du, on_device);
 }
 
-static int enqueue_dt(dgidp_ctx* ctx, double cfl, int mode, DevStats* st)
+// enqueue the dt kernel on the current state; *src tells the next stage kernel
+// to take dt = cfl / max from the accumulator it fills
+static int enqueue_dt(dgidp_ctx* ctx, double cfl, int mode, DtSource* src)
 {
-    if (launch_dt(ctx->p.N, ctx->dm, kparams(ctx), ctx->U, cfl, mode, ctx->partial, ctx->counter,
-                  ctx->dtb, ctx->dt_dev, st, ctx->stream))
+    unsigned long long* acc = ctx->acc + ctx->acc_slot * kDtWords;
+    unsigned long long* other = ctx->acc + (ctx->acc_slot ^ 1) * kDtWords;
+    if (launch_dt(ctx->p.N, ctx->dm, kparams(ctx), ctx->U, mode, acc, other, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "dt kernel launch failed");
+    ctx->acc_slot ^= 1;
+    src->dt = nullptr;
+    src->dtmax = acc;
+    src->cfl = cfl;
+    src->dt_out = ctx->dt_dev;
+    return 0;
+}
+
+// dt = cfl / max computed on the host from the accumulator (same IEEE division)
+static int host_dt(dgidp_ctx* ctx, double cfl, int mode, double* dt)
+{
+    DtSource src;
+    int rc = enqueue_dt(ctx, cfl, mode, &src);
+    if (rc) return rc;
+    std::vector<unsigned long long> bits(kDtWords);
+    HIPCHK(hipMemcpyAsync(bits.data(), src.dtmax, kDtWords * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double m = 0.0;
+    for (int i = 0; i < kDtSpread; ++i) {
+        double v;
+        std::memcpy(&v, &bits[(size_t)i * kDtStride], sizeof(v));
+        m = std::max(m, v);
+    }
+    *dt = cfl / m;
     return 0;
 }
 
@@ -563,11 +595,7 @@ int dgidp_max_dt(dgidp_ctx* ctx, double cfl, double* dt)
 {
     if (!ctx || !dt || !(cfl > 0)) return DGIDP_E_INVALID_ARG;
     if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
-    int rc = enqueue_dt(ctx, cfl, ctx->p.dt_mode, nullptr);
-    if (rc) return rc;
-    HIPCHK(hipMemcpyAsync(dt, ctx->dt_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    return 0;
+    return host_dt(ctx, cfl, ctx->p.dt_mode, dt);
 }
 
 int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s)
@@ -576,17 +604,15 @@ int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s)
     if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
     if (ctx->p.strict_dt) {
         double bound = 0;
-        int rc = enqueue_dt(ctx, 1.0, DGIDP_DT_IDP, nullptr);
+        int rc = host_dt(ctx, 1.0, DGIDP_DT_IDP, &bound);
         if (rc) return rc;
-        HIPCHK(hipMemcpyAsync(&bound, ctx->dt_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
         if (dt > bound)
             return fail(ctx, DGIDP_E_DT, "dt above the IDP bound " + std::to_string(bound));
     }
     if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
     DevStats* st = s ? ctx->stats : nullptr;
     if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
-    int rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st);
+    int rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st, stored_dt(ctx));
     if (rc) return rc;
     std::swap(ctx->U, ctx->W1);
     if (s) {
@@ -597,13 +623,16 @@ int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s)
     return 0;
 }
 
-static int ssprk3(dgidp_ctx* ctx, dgidp_stats* s)
+// the three stages; the first takes dt from first_dt, the others from the
+// stored value (which the first stage writes when it computes dt itself)
+static int ssprk3(dgidp_ctx* ctx, dgidp_stats* s, const DtSource& first_dt)
 {
     DevStats* st = s ? ctx->stats : nullptr;
+    const DtSource dt = stored_dt(ctx);
     int rc;
-    if ((rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st))) return rc;
-    if ((rc = stage(ctx, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, st))) return rc;
-    if ((rc = stage(ctx, ctx->W2, ctx->U, ctx->U, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
+    if ((rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st, first_dt))) return rc;
+    if ((rc = stage(ctx, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, st, dt))) return rc;
+    if ((rc = stage(ctx, ctx->W2, ctx->U, ctx->U, 1.0 / 3.0, 2.0 / 3.0, st, dt))) return rc;
     return 0;
 }
 
@@ -613,9 +642,10 @@ int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s)
     if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
     DevStats* st = s ? ctx->stats : nullptr;
     if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
-    int rc = enqueue_dt(ctx, cfl, ctx->p.dt_mode, st);
+    DtSource src;
+    int rc = enqueue_dt(ctx, cfl, ctx->p.dt_mode, &src);
     if (rc) return rc;
-    if ((rc = ssprk3(ctx, s))) return rc;
+    if ((rc = ssprk3(ctx, s, src))) return rc;
     if (dt_used) {
         HIPCHK(hipMemcpyAsync(dt_used, ctx->dt_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -631,7 +661,7 @@ int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s)
     if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
     DevStats* st = s ? ctx->stats : nullptr;
     if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
-    int rc = ssprk3(ctx, s);
+    int rc = ssprk3(ctx, s, stored_dt(ctx));
     if (rc) return rc;
     if (s) {
         rc = sync_stats(ctx, s, 3);
@@ -651,11 +681,13 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     // stage operands as in the second SSP-RK3 stage: W1 -> W2 with u^n = U
     HIPCHK(hipMemcpyAsync(ctx->W1, ctx->U, (size_t)ctx->E * 4 * (ctx->p.N + 1) * (ctx->p.N + 1) * sizeof(double),
                           hipMemcpyDeviceToDevice, ctx->stream));
-    int rc = enqueue_dt(ctx, 0.5, ctx->p.dt_mode, nullptr);
+    double dt = 0.0;
+    int rc = host_dt(ctx, 0.5, ctx->p.dt_mode, &dt);
     if (rc) return rc;
+    if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
     for (int r = 0; r < reps; ++r)
-        if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, ctx->dt_dev, nullptr,
+        if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, stored_dt(ctx), nullptr,
                          ctx->stream))
             return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
     HIPCHK(hipEventRecord(ev[1], ctx->stream));
@@ -665,8 +697,9 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
             return fail(ctx, DGIDP_E_DEVICE, "mortar kernel launch failed");
     HIPCHK(hipEventRecord(ev[3], ctx->stream));
     HIPCHK(hipEventRecord(ev[4], ctx->stream));
+    DtSource src;
     for (int r = 0; r < reps; ++r)
-        if ((rc = enqueue_dt(ctx, 0.5, ctx->p.dt_mode, nullptr))) return rc;
+        if ((rc = enqueue_dt(ctx, 0.5, ctx->p.dt_mode, &src))) return rc;
     HIPCHK(hipEventRecord(ev[5], ctx->stream));
     HIPCHK(hipEventSynchronize(ev[5]));
     for (int k = 0; k < 3; ++k) {

@@ -64,18 +64,34 @@ struct KernelParams {
     int precision;
 };
 
+// the dt maximum is merged into kDtSpread accumulators kDtStride words apart
+// (one cache line each), so that the per-block atomics do not all meet at one
+// address; an accumulator set holds kDtSpread * kDtStride words
+constexpr int kDtSpread = 64;
+constexpr int kDtStride = 16;
+constexpr int kDtWords = kDtSpread * kDtStride;
+
+// where a stage kernel takes dt from: a stored value (dt), or the maximum that
+// the dt kernel accumulated (dtmax, then dt = cfl / max, stored to dt_out)
+struct DtSource {
+    const double* dt = nullptr;
+    const unsigned long long* dtmax = nullptr;
+    double cfl = 0.0;
+    double* dt_out = nullptr;
+};
+
 // launchers (dgidp_kernels.hip)
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
-                 const double* un, double* uout, double a, double b, const double* dt,
+                 const double* un, double* uout, double a, double b, const DtSource& dt,
                  DevStats* st, hipStream_t s);
 int launch_rhs(int N, const DevMesh& m, const KernelParams& kp, const double* u, int which,
                double* du, hipStream_t s);
 int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st, hipStream_t s,
                   double gamma, int limiter);
-int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, double cfl,
-              int mode, double* partial, unsigned int* counter, int nblocks, double* dt_out,
-              DevStats* st, hipStream_t s);
-int dt_blocks(int N, int E);
+// max over nodes of the dt denominator, atomically merged into the accumulator
+// set acc (all zero on entry); the set other is cleared for the next step
+int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, int mode,
+              unsigned long long* acc, unsigned long long* other, hipStream_t s);
 int launch_permute(int N, int E, const int* perm, const double* src, double* dst, int to_internal,
                    hipStream_t s);
 int launch_stats_reset(DevStats* st, hipStream_t s);

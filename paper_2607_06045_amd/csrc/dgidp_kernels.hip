@@ -16,8 +16,9 @@
 //   k_mortar  one thread per mortar slot: the mortar's factor is the minimum
 //             over its slots (one factor per mortar keeps the flux conservative,
 //             Sec. 2.3); corrections are added in ascending mortar order.
-// The time step (eq. timestep_restriction) is a per-block max (k_dt) and a
-// one-block final reduction (k_dt_final).
+// The time step (eq. timestep_restriction) is a per-block max (k_dt) merged by
+// one 64-bit atomic max per block into one of kDtSpread accumulators; the first
+// stage kernel of the step reduces those and takes dt = cfl / max.
 #include <hip/hip_runtime.h>
 
 #include "dgidp_internal.h"
@@ -314,6 +315,11 @@ struct StageArgs {
     double* uout;
     double a, b;
     const double* dt;
+    // when set, dt = cfl / max over the accumulator set dtmax (bits of
+    // non-negative doubles); block 0 stores it in dt_out
+    const unsigned long long* dtmax;
+    double cfl;
+    double* dt_out;
     const int* fnbr;
     const int* fmort;
     const int* mort;
@@ -409,6 +415,8 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     double onb[4];  // conforming neighbour state across face ff at position fk
     double un4[4] = {0, 0, 0, 0};  // u^n of this node for the SSP combination
     bool blk_mortar = false;
+    const double dtpart =
+        A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
     if (act) {
         // issue the independent global loads first
 #pragma unroll
@@ -448,6 +456,17 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         }
     }
     const bool any_mortar = __syncthreads_or(blk_mortar);
+    double dt;
+    if (A.dtmax) {
+        const double m = wave_max(dtpart);
+        dt = A.cfl / m;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *A.dt_out = dt;
+            if (A.st) A.st->dt = dt;
+        }
+    } else {
+        dt = A.dt ? *A.dt : 0.0;
+    }
 
     // ---- phase 2: one surface flux per face node ----
     const int dff = ff >> 1;
@@ -735,7 +754,6 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         return;
     }
 
-    const double dt = *A.dt;
     const double dtm = dt * im;
     double uFV[4], cf[4][4];
     double rmin = 0.0, pmin = 0.0, th = 1.0;
@@ -917,7 +935,8 @@ struct DtArgs {
     int E;
     double gamma;
     int mode;
-    double* partial;
+    unsigned long long* acc;    // running maximum, bits of a non-negative double
+    unsigned long long* other;  // the other accumulator, cleared for the next step
 };
 
 __device__ __forceinline__ double wave_speed(const NodeP& s, int d)
@@ -1015,26 +1034,15 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
     s = wave_max(s);
     if ((tid & 63) == 0) sRed[tid >> 6] = s;
     __syncthreads();
-    if (tid == 0) A.partial[blockIdx.x] = fmax(sRed[0], sRed[1]);
-}
-
-// one block: max of the per-block maxima, dt = cfl / max
-__global__ __launch_bounds__(256) void k_dt_final(const double* partial, int nb, double cfl,
-                                                  double* dt_out, DevStats* st)
-{
-    __shared__ double sRed[4];
-    const int tid = threadIdx.x;
-    double m = 0.0;
-    for (int i = tid; i < nb; i += 256) m = fmax(m, partial[i]);
-    m = wave_max(m);
-    if ((tid & 63) == 0) sRed[tid >> 6] = m;
-    __syncthreads();
     if (tid == 0) {
-        m = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
-        const double dt = cfl / m;
-        *dt_out = dt;
-        if (st) st->dt = dt;
+        // non-negative doubles order like their bit patterns; NaN and zero
+        // maxima are left out, as fmax would
+        const double m = fmax(sRed[0], sRed[1]);
+        if (m > 0.0)
+            atomicMax(A.acc + (blockIdx.x % kDtSpread) * kDtStride,
+                      (unsigned long long)__double_as_longlong(m));
     }
+    if (blockIdx.x == 0 && tid < kDtSpread) A.other[tid * kDtStride] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -1090,7 +1098,7 @@ __global__ void k_check_state(int total_nodes, int NN, double g, const double* u
 // ---------------------------------------------------------------------------
 template <int N>
 static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, const double* un,
-                   double* uout, double a, double b, const double* dt, DevStats* st, int mode,
+                   double* uout, double a, double b, const DtSource& dt, DevStats* st, int mode,
                    hipStream_t s)
 {
     using G = Geo<N>;
@@ -1100,7 +1108,10 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.uout = uout;
     A.a = a;
     A.b = b;
-    A.dt = dt;
+    A.dt = dt.dt;
+    A.dtmax = dt.dtmax;
+    A.cfl = dt.cfl;
+    A.dt_out = dt.dt_out;
     A.fnbr = m.fnbr;
     A.fmort = m.fmort;
     A.mort = m.mort;
@@ -1127,7 +1138,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
 }
 
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
-                 const double* un, double* uout, double a, double b, const double* dt,
+                 const double* un, double* uout, double a, double b, const DtSource& dt,
                  DevStats* st, hipStream_t s)
 {
     if (m.E == 0) return 0;
@@ -1141,8 +1152,9 @@ int launch_rhs(int N, const DevMesh& m, const KernelParams& kp, const double* u,
 {
     if (m.E == 0) return 0;
     const int mode = which == DGIDP_RHS_HIGH ? MODE_RHS_HIGH : MODE_RHS_LOW;
-    if (N == 3) return stage_N<3>(m, kp, u, nullptr, du, 0.0, 1.0, nullptr, nullptr, mode, s);
-    if (N == 4) return stage_N<4>(m, kp, u, nullptr, du, 0.0, 1.0, nullptr, nullptr, mode, s);
+    const DtSource none;
+    if (N == 3) return stage_N<3>(m, kp, u, nullptr, du, 0.0, 1.0, none, nullptr, mode, s);
+    if (N == 4) return stage_N<4>(m, kp, u, nullptr, du, 0.0, 1.0, none, nullptr, mode, s);
     return -1;
 }
 
@@ -1164,17 +1176,10 @@ int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st,
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int dt_blocks(int N, int E)
+int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, int mode,
+              unsigned long long* acc, unsigned long long* other, hipStream_t s)
 {
-    const int EPB = 128 / ((N + 1) * (N + 1));
-    return (E + EPB - 1) / EPB;
-}
-
-int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, double cfl,
-              int mode, double* partial, unsigned int* counter, int nblocks, double* dt_out,
-              DevStats* st, hipStream_t s)
-{
-    (void)counter;
+    const int nblocks = (m.E + 128 / ((N + 1) * (N + 1)) - 1) / (128 / ((N + 1) * (N + 1)));
     DtArgs A;
     A.u = u;
     A.fnbr = m.fnbr;
@@ -1184,11 +1189,11 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
     A.E = m.E;
     A.gamma = kp.gamma;
     A.mode = mode;
-    A.partial = partial;
+    A.acc = acc;
+    A.other = other;
     if (N == 3) hipLaunchKernelGGL(k_dt<3>, dim3(nblocks), dim3(128), 0, s, A);
     else if (N == 4) hipLaunchKernelGGL(k_dt<4>, dim3(nblocks), dim3(128), 0, s, A);
     else return -1;
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, partial, nblocks, cfl, dt_out, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
