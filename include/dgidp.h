@@ -143,11 +143,13 @@ int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s);
 /* Same with a given dt (used to land exactly on an end time). */
 int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s);
 
-/* Mean duration in milliseconds of one launch of each kernel of a stage,
- * measured with HIP events on the context's stream over `reps` back-to-back
- * launches: ms[0] the element stage kernel (operands of the second SSP-RK3
- * stage), ms[1] the mortar limiter kernel, ms[2] the time-step reduction.
- * Uses the current state; leaves it unchanged.  Synchronises. */
+/* Mean duration in milliseconds of one launch of each kernel of a step,
+ * measured with HIP events on the context's stream over back-to-back launches:
+ * ms[0] the element stage kernel, averaged over `reps` rounds of its three
+ * SSP-RK3 stage configurations (stage 1 reads one state, stages 2 and 3 read
+ * two), ms[1] the mortar limiter kernel, ms[2] the time-step reduction.
+ * Uses the current state; leaves it unchanged (outputs go to scratch
+ * buffers).  Synchronises. */
 int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms);
 
 /* Host-only: the operator tables the library uploads for degree N, flat

@@ -678,17 +678,20 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     const KernelParams kp = kparams(ctx);
     hipEvent_t ev[6];
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-    // stage operands as in the second SSP-RK3 stage: W1 -> W2 with u^n = U
-    HIPCHK(hipMemcpyAsync(ctx->W1, ctx->U, (size_t)ctx->E * 4 * (ctx->p.N + 1) * (ctx->p.N + 1) * sizeof(double),
-                          hipMemcpyDeviceToDevice, ctx->stream));
+    // the three stage configurations on the current state: U -> W1 (a = 0),
+    // then (W1, U) -> W2 and (W2, U) -> W1 with u^n = U; U is only read
     double dt = 0.0;
     int rc = host_dt(ctx, 0.5, ctx->p.dt_mode, &dt);
     if (rc) return rc;
     if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
     for (int r = 0; r < reps; ++r)
-        if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, stored_dt(ctx), nullptr,
-                         ctx->stream))
+        if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->U, nullptr, ctx->W1, 0.0, 1.0, stored_dt(ctx), nullptr,
+                         ctx->stream) ||
+            launch_stage(ctx->p.N, ctx->dm, kp, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, stored_dt(ctx), nullptr,
+                         ctx->stream) ||
+            launch_stage(ctx->p.N, ctx->dm, kp, ctx->W2, ctx->U, ctx->W1, 1.0 / 3.0, 2.0 / 3.0, stored_dt(ctx),
+                         nullptr, ctx->stream))
             return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
     HIPCHK(hipEventRecord(ev[1], ctx->stream));
     HIPCHK(hipEventRecord(ev[2], ctx->stream));
@@ -705,7 +708,7 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     for (int k = 0; k < 3; ++k) {
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
-        ms[k] = (double)t / reps;
+        ms[k] = (double)t / (k == 0 ? 3 * reps : reps);
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     return 0;

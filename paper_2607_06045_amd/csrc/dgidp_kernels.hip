@@ -64,8 +64,10 @@ struct Geo {
     static constexpr int NP = 2 * n * NPL;         // node pairs per element
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
     // padded LDS strides: a half wave covers two N = 3 elements; an element's
-    // stride of 16 (mod 32) doubles puts the second one on the other 32 banks
-    static constexpr int PU = N == 3 ? NN + 2 : NN + 1;    // sU variable stride
+    // stride of 16 (mod 32) doubles puts the second one on the other 32 banks.
+    // sU stays unpadded at N = 3: the block then needs at most 32000 bytes, and
+    // five blocks fit the 160 KiB of a compute unit instead of four
+    static constexpr int PU = N == 3 ? NN : NN + 1;        // sU variable stride
     static constexpr int PR = N == 3 ? NN + 2 : NN + 1;    // sR variable stride
     static constexpr int PP = N == 3 ? NP + 4 : NP;        // sPair variable stride
     static constexpr int PFN = N == 3 ? NFN + 4 : NFN + 2;  // sFace variable stride

@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+  python -m paper_2607_06045_amd.profiling stats --csv RUN_kernel_stats.csv \\
+      --out profiles/kernels_blast22k.txt --command "..."
+      per-kernel call count and mean / min / max duration of a --kernel-trace
+      --stats run, as a short text table
+
+  python -m paper_2607_06045_amd.profiling traffic --fetch DIR --write DIR \\
+      --copy-fetch DIR --copy-write DIR --copy-mib 512 --kernel k_stage \\
+      --dofs D --algorithmic-bytes-per-node B --out profiles/traffic_....json
+      HBM bytes per launch of one kernel from a FETCH_SIZE pass and a WRITE_SIZE
+      pass (KiB per dispatch), each scaled by the ratio of known bytes to what
+      the same counter reads for a plain device copy of --copy-mib MiB
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2607_06045_amd", "csrc", "dgidp_kernels.hip")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _mean_counter(rows, name_part, counter):
+    vals = [float(r["Counter_Value"]) for r in rows
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {name_part!r}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(a):
+    f_kib, nf = _mean_counter(_counter_rows(a.fetch), a.kernel, "FETCH_SIZE")
+    w_kib, nw = _mean_counter(_counter_rows(a.write), a.kernel, "WRITE_SIZE")
+    cf_kib, _ = _mean_counter(_counter_rows(a.copy_fetch), a.copy_kernel, "FETCH_SIZE")
+    cw_kib, _ = _mean_counter(_counter_rows(a.copy_write), a.copy_kernel, "WRITE_SIZE")
+    known_kib = a.copy_mib * 1024.0
+    ff, wf = known_kib / cf_kib, known_kib / cw_kib
+    fetch_b = f_kib * 1024.0 * ff
+    write_b = w_kib * 1024.0 * wf
+    alg = a.algorithmic_bytes_per_node * a.dofs if a.dofs else None
+    out = {
+        "kernel": a.kernel, "workload": a.workload,
+        "fetch_kib_per_dispatch_raw": f_kib, "write_kib_per_dispatch_raw": w_kib,
+        "dispatches": [nf, nw],
+        "copy_calibration": {"mib": a.copy_mib, "fetch_kib_raw": cf_kib, "write_kib_raw": cw_kib,
+                             "fetch_factor": ff, "write_factor": wf},
+        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "algorithmic_bytes_per_launch": alg,
+        "kernel_source_sha256_16": kernel_source_hash(),
+        "command": a.command,
+    }
+    with open(a.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def stats(a):
+    with open(a.csv) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = [f"# {a.title}", f"# command: {a.command}", "",
+             f"{'kernel':60s} {'calls':>6s} {'mean_us':>9s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}"]
+    for r in rows:
+        name = r["Name"].split("(")[0][:60]
+        lines.append(f"{name:60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f} "
+                     f"{float(r['Percentage']):6.2f}")
+    text = "\n".join(lines) + "\n"
+    with open(a.out, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "out"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-mib", type=float, default=512)
+    t.add_argument("--copy-kernel", default="copyBuffer")
+    t.add_argument("--kernel", default="k_stage")
+    t.add_argument("--workload", default="")
+    t.add_argument("--dofs", type=int, default=0)
+    t.add_argument("--algorithmic-bytes-per-node", type=float, default=0.0)
+    t.add_argument("--command", default="")
+    s = sub.add_parser("stats")
+    s.add_argument("--csv", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="rocprofv3 kernel statistics")
+    s.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    if a.mode == "traffic":
+        traffic(a)
+    else:
+        stats(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
