@@ -98,22 +98,24 @@ def main():
 
     N = 3
     spec = config_mesh(2)
-    s = P.Solver(N, gamma=1.4, beta=0.1, precision=P.FP64, dt_mode=P.DT_IDP,
-                 limiter=P.LIMIT_POSITIVITY)
-    s.set_mesh(*spec.args())
-    x, y = s.node_coords()
-    u0 = states.config_state(2, x, y)
-    s.upload(u0)
-    dofs = s.E * (N + 1) ** 2
 
-    for _ in range(args.warmup):
-        s.step(0.5, stats=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step(0.5, stats=False)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def run(precision):
+        s = P.Solver(N, gamma=1.4, beta=0.1, precision=precision, dt_mode=P.DT_IDP,
+                     limiter=P.LIMIT_POSITIVITY)
+        s.set_mesh(*spec.args())
+        x, y = s.node_coords()
+        s.upload(states.config_state(2, x, y))
+        for _ in range(args.warmup):
+            s.step(0.5, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.step(0.5, stats=False)
+        torch.cuda.synchronize()
+        return s, time.perf_counter() - t0
+
+    s, elapsed = run(P.FP64)
+    dofs = s.E * (N + 1) ** 2
     value = dofs * 3 * args.steps / elapsed
 
     # one more step with statistics: bounds and limiter activity of the run
@@ -138,6 +140,15 @@ def main():
         "run_stats": {"violations": st["violations"], "theta_vol_min": st["theta_vol_min"],
                       "theta_mort_min": st["theta_mort_min"], "dt": st["dt"]},
     }
+    # the same workload in the mixed mode (FP32 volume flux differencing and
+    # mortar interpolation / projection; FP64 state, bounds, limiter, update)
+    sm, el_m = run(P.MIXED)
+    stm = sm.step(0.5, stats=True)
+    kmm = sm.time_kernels(reps=50)
+    out["mixed"] = {"value": dofs * 3 * args.steps / el_m, "unit": "DOF-updates/s",
+                    "ms_per_step": el_m / args.steps * 1e3, "kernel_ms": kmm["stage"],
+                    "dtype": "f64 state and limiter, f32 volume fluxes and mortar projection",
+                    "violations": stm["violations"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, N)
     print(json.dumps(out), flush=True)

@@ -431,7 +431,9 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         hy = A.h[2 * e + 1];
 #pragma unroll
         for (int v = 0; v < 4; ++v) sU[le][v][q] = me.u[v];
-        const double lr = log(me.r);
+        // the logarithms feed only the two-point volume fluxes: FP32 in the
+        // mixed mode (exactly representable in the FP64 slots)
+        const double lr = MIXED ? (double)__logf((float)me.r) : log(me.r);
         const double z = me.r * frcp(me.p);
         sR[le][0][q] = me.r;
         sR[le][1][q] = me.v1;
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         sR[le][4][q] = me.c;
         sR[le][5][q] = lr;
         sR[le][6][q] = z;
-        sR[le][7][q] = log(z);
+        sR[le][7][q] = MIXED ? (double)__logf((float)z) : log(z);
         if (fnode) {
             fcode_f = fcode[ff];
             if (fcode_f < 0) {
@@ -497,10 +499,17 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 load_node<N>(A.uin, A.mort[S * 4 + 2 + hh], face_q<N>(ff ^ 1, fk), us, g);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    double acc = 0.0;
+                    if (MIXED) {
+                        float acc = 0.0f;
 #pragma unroll
-                    for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sU[le][v][face_q<N>(ff, j)];
-                    ui.u[v] = acc;
+                        for (int j = 0; j < n; ++j) acc += tb.If[hh][fk][j] * (float)sU[le][v][face_q<N>(ff, j)];
+                        ui.u[v] = acc;
+                    } else {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sU[le][v][face_q<N>(ff, j)];
+                        ui.u[v] = acc;
+                    }
                 }
                 make_node(ui, g);
                 double F[4];
@@ -514,10 +523,17 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             NodeP ui;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double acc = 0.0;
+                if (MIXED) {
+                    float acc = 0.0f;
 #pragma unroll
-                for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sPair[le][v][ff * n + j];
-                ui.u[v] = acc;
+                    for (int j = 0; j < n; ++j) acc += tb.If[hh][fk][j] * (float)sPair[le][v][ff * n + j];
+                    ui.u[v] = acc;
+                } else {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sPair[le][v][ff * n + j];
+                    ui.u[v] = acc;
+                }
             }
             make_node(ui, g);
             double F[4], ho[4], lo[4] = {0, 0, 0, 0};
@@ -560,11 +576,21 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
 #pragma unroll 1
             for (int v = 0; v < 4; ++v) {
                 double acc = 0.0;
+                if (MIXED) {
+                    float accf = 0.0f;
 #pragma unroll
-                for (int hh = 0; hh < 2; ++hh)
+                    for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-                    for (int l = 0; l < n; ++l)
-                        acc += tb.P[hh][fk][l] * sPair[le][v][MB + (ff * 2 + hh) * n + l];
+                        for (int l = 0; l < n; ++l)
+                            accf += tb.Pf[hh][fk][l] * (float)sPair[le][v][MB + (ff * 2 + hh) * n + l];
+                    acc = accf;
+                } else {
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                        for (int l = 0; l < n; ++l)
+                            acc += tb.P[hh][fk][l] * sPair[le][v][MB + (ff * 2 + hh) * n + l];
+                }
                 ho[v] = sgf * tb.w[fk] * hff * 0.5 * acc;
             }
             for (int hh = 0; hh < 2; ++hh) {
