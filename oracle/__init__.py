@@ -56,6 +56,11 @@ def lib():
                                   ctypes.c_double, ctypes.c_int, _D, _D]
         L.orc_ssprk3.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, _D]
+        L.orc_adapt.restype = ctypes.c_int64
+        L.orc_adapt.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 3 + [ctypes.c_int] * 2 + \
+            [ctypes.c_void_p] * 6
+        L.orc_transfer.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                   _D, _D, ctypes.c_double, ctypes.c_double, _I64]
         L.orc_ssprk3_dt.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, _D]
         L.orc_basis.argtypes = [ctypes.c_int, _D, _D, _D, _D]
@@ -74,6 +79,42 @@ def lib():
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
+
+
+def adapt(level, ix, iy, nx0, ny0, flags):
+    """New leaf list after refine (+1) / coarsen (-1) flags, 2:1 balanced
+    (rules in dgo_amr.c).  Returns (level, ix, iy, kind, src): kind 0 kept,
+    1 child, 2 parent; src [E_new, 4] old leaf ids (child: parent, child index)."""
+    L = lib()
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    flags = np.ascontiguousarray(flags, dtype=np.int8)
+    E = len(level)
+    cap = 4 * max(E, 1)
+    nl, nx, ny = np.zeros(cap, np.int8), np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+    kind, src = np.zeros(cap, np.int8), np.zeros((cap, 4), np.int64)
+    n = L.orc_adapt(ctypes.c_int64(E), _ptr(level, ctypes.c_void_p), _ptr(ix, ctypes.c_void_p),
+                    _ptr(iy, ctypes.c_void_p), nx0, ny0, _ptr(flags, ctypes.c_void_p),
+                    _ptr(nl, ctypes.c_void_p), _ptr(nx, ctypes.c_void_p), _ptr(ny, ctypes.c_void_p),
+                    _ptr(kind, ctypes.c_void_p), _ptr(src, ctypes.c_void_p))
+    return nl[:n].copy(), nx[:n].copy(), ny[:n].copy(), kind[:n].copy(), src[:n].copy()
+
+
+def transfer(N, kind, src, u_old, eps=1e-10, gamma=1.4):
+    """Solution transfer onto the new leaves (interpolation / L2 projection),
+    then the Zhang-Shu limiter with threshold eps (eps <= 0: none).  Returns
+    (u_new, n_limited_groups, n_unfixable_groups)."""
+    L = lib()
+    kind = np.ascontiguousarray(kind, dtype=np.int8)
+    src = np.ascontiguousarray(src, dtype=np.int64)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    n = N + 1
+    un = np.zeros((len(kind), 4, n, n))
+    counts = np.zeros(2, np.int64)
+    L.orc_transfer(N, ctypes.c_int64(len(kind)), _ptr(kind, ctypes.c_void_p), _ptr(src, ctypes.c_void_p),
+                   _ptr(u_old), _ptr(un), ctypes.c_double(eps), ctypes.c_double(gamma), _ptr(counts, _I64))
+    return un, int(counts[0]), int(counts[1])
 
 
 def set_threads(t):

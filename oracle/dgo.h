@@ -104,4 +104,16 @@ double dgo_theta_pressure(const double* u0, const double* dc, double pt, double 
 int dgo_ssprk3_dt(const dgo_mesh* m, double* u, double dt, double gamma, double beta, int limiter,
                   dgo_stats* st);
 
+/* ---------------- adaptation (Sec. 2.4), dgo_amr.c ---------------- */
+/* new leaf list (capacity 4 E) and its source map: kind 0 kept (src[0] = old
+   leaf), 1 child (src[0] = old parent, src[1] = child index cx + 2 cy), 2 parent
+   (src[0..3] = old children by child index); returns the new leaf count */
+int64_t dgo_adapt(int64_t E, const int8_t* level, const int32_t* ix, const int32_t* iy, int nx0,
+                  int ny0, const int8_t* flags, int8_t* nlevel, int32_t* nix, int32_t* niy,
+                  int8_t* kind, int64_t* src);
+void dgo_transfer(int N, int64_t En, const int8_t* kind, const int64_t* src, const double* uo,
+                  double* un);
+void dgo_zhang_shu(int N, int64_t En, const int8_t* kind, const int64_t* src, const double* uo,
+                   double* un, double eps, double gamma, int64_t* n_limited, int64_t* n_unfixable);
+
 #endif

@@ -198,3 +198,18 @@ int orc_set_threads(int t)
     return 1;
 #endif
 }
+
+int64_t orc_adapt(int64_t E, const int8_t* level, const int32_t* ix, const int32_t* iy, int nx0,
+                  int ny0, const int8_t* flags, int8_t* nlevel, int32_t* nix, int32_t* niy,
+                  int8_t* kind, int64_t* src)
+{
+    return dgo_adapt(E, level, ix, iy, nx0, ny0, flags, nlevel, nix, niy, kind, src);
+}
+
+void orc_transfer(int N, int64_t En, const int8_t* kind, const int64_t* src, const double* uo,
+                  double* un, double eps, double gamma, int64_t* counts)
+{
+    dgo_transfer(N, En, kind, src, uo, un);
+    if (eps > 0.0) dgo_zhang_shu(N, En, kind, src, uo, un, eps, gamma, &counts[0], &counts[1]);
+    else counts[0] = counts[1] = 0;
+}

@@ -1,0 +1,276 @@
+"""Oracle pins for mesh adaptation, solution transfer and the Zhang-Shu
+transfer limiter (Sec. 2.4).
+
+Adaptation is integer work, pinned by brute force on a raster of the finest
+level: the result tiles the domain, is 2:1 balanced across faces, refines
+every flagged leaf, refines no leaf that balance does not force, coarsens only
+whole flagged sibling groups and every such group whose parent would be
+balanced.  Transfer is pinned by closed forms (polynomials of degree N are
+reproduced exactly by interpolation and by projection), by an independent L2
+projection (numpy Gauss-Legendre quadrature and Legendre series), and by
+conservation of sum_i m_i u_i.  The Zhang-Shu limiter is pinned by its bounds,
+by conservation, and by a brute-force scan of its factor on small cases."""
+import numpy as np
+import pytest
+
+from workloads import states
+from workloads.meshes import config_mesh, random_flags, random_mesh, to_spec
+
+
+def raster(level, ix, iy, nx0, ny0):
+    """Leaf id covering each cell of the finest-level grid; -1 if uncovered,
+    raises on overlap."""
+    L = int(level.max())
+    g = -np.ones((ny0 << L, nx0 << L), dtype=np.int64)
+    for e, (l, i, j) in enumerate(zip(level.tolist(), ix.tolist(), iy.tolist())):
+        s = 1 << (L - l)
+        blk = g[j * s:(j + 1) * s, i * s:(i + 1) * s]
+        assert (blk == -1).all(), "overlapping leaves"
+        blk[...] = e
+    return g, L
+
+
+def balanced(level, ix, iy, nx0, ny0):
+    g, L = raster(level, ix, iy, nx0, ny0)
+    assert (g >= 0).all(), "gap in the tiling"
+    lv = level.astype(np.int64)[g]
+    for ax in (0, 1):
+        d = np.abs(lv - np.roll(lv, 1, axis=ax))
+        if d.max() > 1:
+            return False
+    return True
+
+
+def test_random_flags_deterministic():
+    spec = random_mesh(2, 4, 3, 0.4)
+    assert np.array_equal(random_flags(spec, 11), random_flags(spec, 11))
+    assert not np.array_equal(random_flags(spec, 11), random_flags(spec, 12))
+
+
+def _neighbour_levels_after(spec, ref, e, g, L):
+    """Levels (after refinement flags ref) of the leaves touching leaf e across
+    its faces, read off the raster."""
+    l, i, j = int(spec.level[e]), int(spec.ix[e]), int(spec.iy[e])
+    s = 1 << (L - l)
+    ny, nx = g.shape
+    cells = []
+    for k in range(s):
+        cells += [((j * s + k) % ny, (i * s - 1) % nx), ((j * s + k) % ny, ((i + 1) * s) % nx),
+                  ((j * s - 1) % ny, (i * s + k) % nx), (((j + 1) * s) % ny, (i * s + k) % nx)]
+    nb = {int(g[c]) for c in cells}
+    return [int(spec.level[b]) + int(ref[b]) for b in nb]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_adapt_rules_brute_force(oracle, seed):
+    spec = random_mesh(seed, 4, 3, 0.4)
+    flags = random_flags(spec, 100 + seed)
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)
+    assert balanced(nl, nx, ny, spec.nx0, spec.ny0)
+    E = spec.E
+    refined = np.zeros(E, bool)
+    coarsened = np.zeros(E, bool)
+    kept = np.zeros(E, bool)
+    for k, s in zip(kind, src):
+        if k == 0:
+            kept[s[0]] = True
+        elif k == 1:
+            refined[s[0]] = True
+        else:
+            coarsened[s] = True
+    # every old leaf has exactly one fate
+    assert np.array_equal(kept.astype(int) + refined + coarsened, np.ones(E, int))
+    assert refined[flags > 0].all()
+    assert (flags[coarsened] < 0).all()
+    # children and parents are where the source map says
+    for k, s, l, i, j in zip(kind, src, nl, nx, ny):
+        if k == 1:
+            p = s[0]
+            assert (l, i, j) == (spec.level[p] + 1, 2 * spec.ix[p] + (s[1] & 1), 2 * spec.iy[p] + (s[1] >> 1))
+        elif k == 2:
+            for c in range(4):
+                ch = s[c]
+                assert (spec.level[ch], spec.ix[ch], spec.iy[ch]) == (l + 1, 2 * i + (c & 1), 2 * j + (c >> 1))
+    g, L = raster(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
+    ref = refined.astype(int)
+    # no refinement that balance does not force
+    for e in np.nonzero(refined & (flags <= 0))[0]:
+        assert max(_neighbour_levels_after(spec, ref, e, g, L)) >= spec.level[e] + 2
+    # every flagged sibling group whose parent would be balanced is coarsened
+    groups = {}
+    for e in range(E):
+        if spec.level[e] > 0:
+            groups.setdefault((int(spec.level[e]), int(spec.ix[e]) >> 1, int(spec.iy[e]) >> 1), []).append(e)
+    n_coarse = 0
+    for (l, pi, pj), mem in groups.items():
+        if len(mem) != 4 or not all(flags[m] < 0 and not refined[m] for m in mem):
+            assert not coarsened[mem].any()
+            continue
+        ok = all(lv <= l for m in mem for lv in _neighbour_levels_after(spec, ref, m, g, L))
+        assert coarsened[mem].all() == ok and coarsened[mem].any() == ok
+        n_coarse += ok
+    print(f"seed {seed}: {E} -> {len(nl)} leaves, {refined.sum()} refined "
+          f"({(refined & (flags <= 0)).sum()} by balance), {n_coarse} groups coarsened", flush=True)
+
+
+def test_adapt_all_coarsen_and_refine(oracle):
+    """A uniform level-1 mesh flagged -1 everywhere coarsens to the root grid;
+    flagged +1 everywhere refines every leaf."""
+    spec = to_spec((0.0, 0.0, 1.0, 1.0, 2, 2), {(1, i, j) for i in range(4) for j in range(4)})
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, 2, 2, -np.ones(16, np.int8))
+    assert len(nl) == 4 and (nl == 0).all() and (kind == 2).all()
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, 2, 2, np.ones(16, np.int8))
+    assert len(nl) == 64 and (nl == 2).all() and (kind == 1).all()
+
+
+def _poly_state(x, y, N, seed):
+    """A state whose variables are polynomials of degree N in x and y."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for v in range(4):
+        c = rng.uniform(-1, 1, (N + 1, N + 1)) * 0.1
+        f = sum(c[a, b] * x ** a * y ** b for a in range(N + 1) for b in range(N + 1))
+        out.append(f + (2.0 if v in (0, 3) else 0.0))
+    return np.stack(out, axis=1)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_transfer_reproduces_polynomials(oracle, N):
+    spec = random_mesh(4, 4, 2, 0.4)
+    flags = random_flags(spec, 5)
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)
+    M0 = oracle.Mesh(N, *spec.args())
+    M1 = oracle.Mesh(N, nl, nx, ny, *spec.args()[3:])
+    x0, y0, m0 = M0.geometry()
+    x1, y1, m1 = M1.geometry()
+    # a polynomial of degree N per element (global polynomial: exact on both meshes)
+    u0 = _poly_state(x0, y0, N, 1)
+    u1, nlim, nbad = oracle.transfer(N, kind, src, u0, eps=0.0)
+    assert np.abs(u1 - _poly_state(x1, y1, N, 1)).max() < 1e-13
+    assert (kind == 1).any() and (kind == 2).any()
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_transfer_conserves(oracle, N):
+    spec = random_mesh(5, 4, 3, 0.4)
+    flags = random_flags(spec, 6, p_refine=0.2, p_coarsen=0.6)
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)
+    M0 = oracle.Mesh(N, *spec.args())
+    M1 = oracle.Mesh(N, nl, nx, ny, *spec.args()[3:])
+    x0, y0, m0 = M0.geometry()
+    m1 = M1.geometry()[2]
+    u0 = states.random_admissible(x0, 9)
+    u1, _, _ = oracle.transfer(N, kind, src, u0, eps=0.0)
+    tot0 = (m0[:, None] * u0).sum(axis=(0, 2, 3))
+    tot1 = (m1[:, None] * u1).sum(axis=(0, 2, 3))
+    assert np.abs(tot1 - tot0).max() < 1e-13 * np.abs(tot0).max()
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_coarsen_is_l2_projection(oracle, N):
+    """Independent L2 projection: Gauss-Legendre quadrature of the piecewise
+    polynomial against Legendre polynomials, evaluated at the LGL nodes."""
+    from numpy.polynomial import legendre as Lg
+    n = N + 1
+    xi = oracle.basis(N)[0]
+    rng = np.random.default_rng(3)
+    u_children = rng.uniform(0.5, 1.5, (4, 4, n, n))
+    kind = np.array([2], np.int8)
+    src = np.array([[0, 1, 2, 3]], np.int64)
+    up, _, _ = oracle.transfer(N, kind, src, u_children, eps=0.0)
+
+    def lagrange_eval(vals, s):  # nodal values at xi -> value at s (1D, barycentric via numpy)
+        V = np.vander(xi, n, increasing=True)
+        coef = np.linalg.solve(V, vals)
+        return np.polyval(coef[::-1], s)
+
+    gq, gw = Lg.leggauss(2 * n)
+    for v in range(4):
+        C = np.zeros((n, n))  # Legendre coefficients c_ij of the projection, i along x
+        for c in range(4):
+            cx, cy = c & 1, c >> 1
+            # quadrature points of the child's half in parent coordinates
+            X = 0.5 * (gq + (2 * cx - 1))
+            Y = 0.5 * (gq + (2 * cy - 1))
+            vals = np.array([[lagrange_eval(np.array([lagrange_eval(u_children[c, v, b, :], sx) for b in range(n)]), sy)
+                              for sx in gq] for sy in gq])  # [y][x]
+            for i in range(n):
+                for j in range(n):
+                    Li = Lg.legval(X, np.eye(n)[i])
+                    Lj = Lg.legval(Y, np.eye(n)[j])
+                    C[i, j] += 0.25 * np.einsum("yx,x,y->", vals * np.outer(gw, gw), Li, Lj) * \
+                        (2 * i + 1) / 2 * (2 * j + 1) / 2
+        ref = np.array([[sum(C[i, j] * Lg.legval(xi[a], np.eye(n)[i]) * Lg.legval(xi[b], np.eye(n)[j])
+                             for i in range(n) for j in range(n)) for a in range(n)] for b in range(n)])
+        assert np.abs(up[0, v] - ref).max() < 1e-13
+
+
+def test_zhang_shu_untouched_when_admissible(oracle):
+    spec = random_mesh(6, 4, 2, 0.4)
+    flags = random_flags(spec, 7)
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)
+    x0, y0, m0 = oracle.Mesh(3, *spec.args()).geometry()
+    u0 = states.vortex(x0, y0)
+    a, _, _ = oracle.transfer(3, kind, src, u0, eps=0.0)
+    b, nlim, nbad = oracle.transfer(3, kind, src, u0, eps=1e-10)
+    assert nlim == 0 and nbad == 0 and np.array_equal(a, b)
+
+
+def pressure(u, gamma):
+    """p of states u[..., 4, n, n] (axis -3 holds the variables)."""
+    r, m1, m2, E = u[..., 0, :, :], u[..., 1, :, :], u[..., 2, :, :], u[..., 3, :, :]
+    return (gamma - 1.0) * (E - 0.5 * (m1 * m1 + m2 * m2) / r)
+
+
+def _near_vacuum_case(N, eps):
+    """One refined element holding a sharp blast: the interpolation to the
+    children undershoots below eps somewhere."""
+    n = N + 1
+    from oracle import basis
+    xi = basis(N)[0]
+    X, Y = np.meshgrid(xi, xi)  # [b][a]
+    rho = 1e-3 + np.exp(-((X - 0.9) ** 2 + (Y - 0.9) ** 2) / 0.02)
+    p = 1e-3 + 5 * np.exp(-((X + 0.9) ** 2 + (Y - 0.8) ** 2) / 0.01)
+    rho, p = rho[None], p[None]
+    return states.conservative(rho, 0.5 * np.ones_like(rho), -0.3 * np.ones_like(rho), p, 1.4)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_zhang_shu_bounds_and_conservation(oracle, N):
+    eps = 1e-3
+    u0 = _near_vacuum_case(N, eps)
+    kind = np.ones(4, np.int8)
+    src = np.array([[0, c, -1, -1] for c in range(4)], np.int64)
+    raw, _, _ = oracle.transfer(N, kind, src, u0, eps=0.0)
+    lim, nlim, nbad = oracle.transfer(N, kind, src, u0, eps=eps)
+    assert (raw[:, 0] < eps).any() or (pressure(raw, 1.4) < eps).any(), "case must trigger"
+    assert nlim == 1 and nbad == 0
+    assert (lim[:, 0] >= eps).all() and (pressure(lim, 1.4) >= eps).all()
+    w = oracle.basis(N)[1]
+    W = np.outer(w, w)
+    tot_raw = (raw * W).sum(axis=(0, 2, 3))
+    tot_lim = (lim * W).sum(axis=(0, 2, 3))
+    assert np.abs(tot_lim - tot_raw).max() < 1e-14 * np.abs(tot_raw).max()
+    # brute force: theta is the largest grid value that keeps the bounds
+    ub = (u0[0] * W).sum(axis=(1, 2)) / 4.0
+    d = raw - ub[None, :, None, None]
+    theta = ((lim - ub[None, :, None, None]) * d).sum() / (d * d).sum()
+    grid = np.linspace(0.0, 1.0, 200001)
+    ok = [t for t in grid[::100]
+          if ((ub[0] + t * d[:, 0]) >= eps).all() and (pressure(ub[None, :, None, None] + t * d, 1.4) >= eps).all()]
+    t_max = max(ok)
+    assert t_max - 1e-3 <= theta <= t_max + 1e-3 + 1e-12
+    fine = [t for t in grid if abs(t - theta) < 2e-3]
+    bad_above = [t for t in fine if t > theta + 1e-5 and
+                 (((ub[0] + t * d[:, 0]) < eps).any() or (pressure(ub[None, :, None, None] + t * d, 1.4) < eps).any())]
+    assert bad_above, "a slightly larger factor must violate a bound"
+
+
+def test_zhang_shu_unfixable_mean(oracle):
+    """A parent whose mean is already below the threshold cannot be fixed."""
+    N = 3
+    u0 = _near_vacuum_case(N, 1e-3)
+    kind = np.ones(4, np.int8)
+    src = np.array([[0, c, -1, -1] for c in range(4)], np.int64)
+    lim, nlim, nbad = oracle.transfer(N, kind, src, u0, eps=10.0)
+    assert nlim == 1 and nbad == 1

@@ -154,3 +154,22 @@ def random_mesh(seed, n_base=4, maxlev=2, frac=0.35, L=1.0, x0=0.0, y0=0.0):
                         leaves.add((l + 1, 2 * i + a, 2 * j + b))
         _balance(leaves, n_base, n_base)
     return to_spec(box, leaves)
+
+
+def random_flags(spec, seed, p_refine=0.15, p_coarsen=0.5):
+    """Seeded refine (+1) / coarsen (-1) / keep (0) flags for the leaves of spec.
+    A leaf is flagged +1 with probability p_refine; the leaves of a parent cell
+    are flagged -1 together with probability p_coarsen (so that whole sibling
+    groups ask to be coarsened), unless flagged +1."""
+    from .rng import uniform
+
+    E = spec.E
+    lev = spec.level.astype(np.int64)
+    ur = uniform(seed, np.arange(E, dtype=np.uint64))
+    # one draw per parent cell, keyed by (level, parent ix, parent iy)
+    pkey = (lev << 50) | ((spec.ix.astype(np.int64) >> 1) << 25) | (spec.iy.astype(np.int64) >> 1)
+    uc = uniform(seed + 7919, pkey.astype(np.uint64))
+    flags = np.zeros(E, dtype=np.int8)
+    flags[(uc < p_coarsen) & (lev > 0)] = -1
+    flags[ur < p_refine] = 1
+    return flags
