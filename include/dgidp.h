@@ -143,6 +143,58 @@ int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s);
 /* Same with a given dt (used to land exactly on an end time). */
 int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s);
 
+/* ---------------- adaptive mesh refinement (Sec. 2.4) ---------------- */
+
+/* Counts of one adaptation. */
+typedef struct {
+    int64_t n_refined;         /* old leaves replaced by four children (flagged or balance) */
+    int64_t n_balance_refined; /* of those, refined only to keep 2:1 balance */
+    int64_t n_coarsened;       /* sibling groups replaced by their parent */
+    int64_t zs_limited;        /* transferred groups the Zhang-Shu limiter scaled */
+    int64_t zs_unfixable;      /* of those, groups whose mean is below the threshold */
+} dgidp_adapt_stats;
+
+/* Host-only: the leaf list after refine / coarsen flags (+1 refine, -1 ask to
+ * coarsen, 0 keep; one per leaf, external order), without a context.
+ * Rules: flagged leaves are refined; a leaf that would end up two levels
+ * coarser than a face neighbour is refined too (repeated until stable); four
+ * sibling leaves all flagged -1 and none refined are merged into their parent
+ * if every leaf touching the parent across a face is at most one level finer
+ * than the parent.  New order: the old order with a refined leaf replaced by
+ * its children (x half fastest: (0,0) (1,0) (0,1) (1,1)) and a merged group by
+ * its parent at the place of its first member.  Source map per new leaf:
+ * kind 0 kept (src[0] old leaf), 1 child (src[0] old parent, src[1] child
+ * index), 2 parent (src[0..3] old children by child index); src is [n][4].
+ * With new_level == NULL only *n_new is returned.  Errors:
+ * DGIDP_E_INVALID_ARG (also when capacity < *n_new). */
+int dgidp_adapt_leaves(int64_t n_leaves, const int8_t* level, const int32_t* ix, const int32_t* iy,
+                       int nx0, int ny0, const int8_t* flags, int64_t capacity, int8_t* new_level,
+                       int32_t* new_ix, int32_t* new_iy, int8_t* kind, int64_t* src,
+                       int64_t* n_new);
+
+/* Adapt the context's mesh by the host array `flags` (rules of
+ * dgidp_adapt_leaves) and transfer the state (Sec. 2.4): interpolation onto
+ * children, exact L2 projection onto merged parents, then, if zs_eps > 0, the
+ * Zhang-Shu scaling limiter on every transferred group (four children, or one
+ * parent) that has a node with rho < zs_eps or p < zs_eps: all its nodes are
+ * scaled toward the parent's mean (before refinement) or the projected mean
+ * (after coarsening) by the largest common factor that restores the
+ * thresholds, which keeps the group's mass.  The new leaf order is that of
+ * dgidp_adapt_leaves; dgidp_mesh_download returns it.  Synchronises.
+ * Errors: DGIDP_E_NO_STATE, DGIDP_E_INVALID_ARG, DGIDP_E_DEVICE (after which
+ * the context may hold the new mesh without a state). */
+int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int64_t* n_leaves_out,
+                         dgidp_adapt_stats* st);
+/* The current leaf list (external order), host arrays of mesh_info's size. */
+int dgidp_mesh_download(dgidp_ctx* ctx, int8_t* level, int32_t* ix, int32_t* iy);
+
+/* Host-only three-level controller: target level = max_level where
+ * indicator >= max_threshold, else med_level where indicator >= med_threshold,
+ * else base_level; flag = +1 below the target, -1 above it, 0 at it. */
+int dgidp_amr_flags(int64_t n, const float* indicator, const int8_t* level, int base_level,
+                    int med_level, float med_threshold, int max_level, float max_threshold,
+                    int8_t* flags);
+
 /* Mean duration in milliseconds of one launch of each kernel of a step,
  * measured with HIP events on the context's stream over back-to-back launches:
  * ms[0] the element stage kernel, averaged over `reps` rounds of its three

@@ -46,6 +46,15 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class AdaptStats(ctypes.Structure):
+    _fields_ = [("n_refined", ctypes.c_int64), ("n_balance_refined", ctypes.c_int64),
+                ("n_coarsened", ctypes.c_int64), ("zs_limited", ctypes.c_int64),
+                ("zs_unfixable", ctypes.c_int64)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp, _d, _i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
 _lib = ctypes.CDLL(LIB_PATH)
 _SIGS = {
@@ -69,6 +78,13 @@ _SIGS = {
     "dgidp_mesh_validate": (_i, [_i, ctypes.c_int64, _vp, _vp, _vp, _i, _i,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.c_char_p, _i]),
+    "dgidp_adapt_leaves": (_i, [ctypes.c_int64, _vp, _vp, _vp, _i, _i, _vp, ctypes.c_int64,
+                                _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "dgidp_refine_coarsen": (_i, [_vp, _vp, _d, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(AdaptStats)]),
+    "dgidp_mesh_download": (_i, [_vp, _vp, _vp, _vp]),
+    "dgidp_amr_flags": (_i, [ctypes.c_int64, _vp, _vp, _i, _i, ctypes.c_float, _i,
+                             ctypes.c_float, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -114,6 +130,40 @@ def validate_mesh(N, level, ix, iy, nx0, ny0):
     if rc:
         raise DgidpError(f"dgidp_mesh_validate: {ERRORS.get(rc, rc)}: {msg.value.decode()}")
     return M.value, T2.value
+
+
+def adapt_leaves(level, ix, iy, nx0, ny0, flags):
+    """Host-only: new leaf list after refine/coarsen flags (rules in
+    include/dgidp.h).  Returns (level, ix, iy, kind, src[n, 4])."""
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    flags = np.ascontiguousarray(flags, dtype=np.int8)
+    E = len(level)
+    cap = 4 * max(E, 1)
+    nl, nx, ny = np.zeros(cap, np.int8), np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+    kind, src = np.zeros(cap, np.int8), np.zeros((cap, 4), np.int64)
+    n = ctypes.c_int64()
+    rc = _lib.dgidp_adapt_leaves(E, level.ctypes.data, ix.ctypes.data, iy.ctypes.data, nx0, ny0,
+                                 flags.ctypes.data, cap, nl.ctypes.data, nx.ctypes.data,
+                                 ny.ctypes.data, kind.ctypes.data, src.ctypes.data, ctypes.byref(n))
+    if rc:
+        raise DgidpError(f"dgidp_adapt_leaves: {ERRORS.get(rc, rc)}")
+    k = n.value
+    return nl[:k].copy(), nx[:k].copy(), ny[:k].copy(), kind[:k].copy(), src[:k].copy()
+
+
+def amr_flags(indicator, level, base_level, med_level, med_threshold, max_level, max_threshold):
+    """Host-only three-level controller: refine (+1) / coarsen (-1) / keep (0)."""
+    ind = np.ascontiguousarray(indicator, dtype=np.float32)
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    flags = np.zeros(len(level), np.int8)
+    rc = _lib.dgidp_amr_flags(len(level), ind.ctypes.data, level.ctypes.data, base_level,
+                              med_level, med_threshold, max_level, max_threshold,
+                              flags.ctypes.data)
+    if rc:
+        raise DgidpError(f"dgidp_amr_flags: {ERRORS.get(rc, rc)}")
+    return flags
 
 
 class Solver:
@@ -228,6 +278,28 @@ class Solver:
         ms = np.zeros(3)
         self._check(_lib.dgidp_time_kernels(self._h, reps, ms.ctypes.data), "dgidp_time_kernels")
         return {"stage": ms[0], "mortar": ms[1], "dt": ms[2]}
+
+    def refine_coarsen(self, flags, zs_eps=1e-10):
+        """Adapt the mesh by per-leaf flags and transfer the state (Sec. 2.4)."""
+        flags = np.ascontiguousarray(flags, dtype=np.int8)
+        if len(flags) != self.E:
+            raise ValueError("one flag per leaf")
+        n = ctypes.c_int64()
+        st = AdaptStats()
+        self._check(_lib.dgidp_refine_coarsen(self._h, flags.ctypes.data, zs_eps, ctypes.byref(n),
+                                              ctypes.byref(st)), "dgidp_refine_coarsen")
+        E, M = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.dgidp_mesh_info(self._h, ctypes.byref(E), ctypes.byref(M)), "dgidp_mesh_info")
+        self.E, self.M = E.value, M.value
+        return st.to_dict()
+
+    def mesh(self):
+        """Current leaf list (level, ix, iy), external order."""
+        lv = np.zeros(self.E, np.int8)
+        ix, iy = np.zeros(self.E, np.int32), np.zeros(self.E, np.int32)
+        self._check(_lib.dgidp_mesh_download(self._h, lv.ctypes.data, ix.ctypes.data, iy.ctypes.data),
+                    "dgidp_mesh_download")
+        return lv, ix, iy
 
     def synchronize(self):
         self._check(_lib.dgidp_synchronize(self._h), "dgidp_synchronize")

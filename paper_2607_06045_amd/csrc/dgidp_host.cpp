@@ -714,6 +714,113 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     return 0;
 }
 
+int dgidp_mesh_download(dgidp_ctx* ctx, int8_t* level, int32_t* ix, int32_t* iy)
+{
+    if (!ctx || !level || !ix || !iy) return DGIDP_E_INVALID_ARG;
+    if (!ctx->E) return fail(ctx, DGIDP_E_NO_MESH, "no mesh");
+    std::copy(ctx->level.begin(), ctx->level.end(), level);
+    std::copy(ctx->ix.begin(), ctx->ix.end(), ix);
+    std::copy(ctx->iy.begin(), ctx->iy.end(), iy);
+    return 0;
+}
+
+int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int64_t* n_leaves_out,
+                         dgidp_adapt_stats* st)
+{
+    if (!ctx || !flags || !(zs_eps >= 0.0)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    const int N = ctx->p.N, NN = (N + 1) * (N + 1);
+    AdaptPlan plan;
+    std::string err;
+    int rc = adapt_leaves(ctx->E, ctx->level.data(), ctx->ix.data(), ctx->iy.data(), ctx->nx0,
+                          ctx->ny0, flags, plan, err);
+    if (rc) return fail(ctx, rc, err);
+    const int64_t En = (int64_t)plan.level.size();
+    // old external -> old internal
+    std::vector<int> inv_old((size_t)ctx->E);
+    for (int64_t i = 0; i < ctx->E; ++i) inv_old[ctx->perm[i]] = (int)i;
+    // keep the old state; installing the new mesh frees everything else
+    double* uold = ctx->U;
+    ctx->U = nullptr;
+    const double x0 = ctx->x0, y0 = ctx->y0, Lx = ctx->Lx, Ly = ctx->Ly;
+    rc = dgidp_mesh_upload(ctx, En, plan.level.data(), plan.ix.data(), plan.iy.data(), x0, y0, Lx,
+                           Ly, ctx->nx0, ctx->ny0);
+    if (rc) {
+        (void)hipFree(uold);
+        return rc;
+    }
+    // new external -> new internal
+    std::vector<int> inv_new((size_t)En);
+    for (int64_t i = 0; i < En; ++i) inv_new[ctx->perm[i]] = (int)i;
+    std::vector<int> tkind((size_t)En), tsrc((size_t)En * 4, -1), zgrp;
+    for (int64_t i = 0; i < En; ++i) {
+        const int64_t x = ctx->perm[i];  // external id of new internal element i
+        const int k = plan.kind[x];
+        tkind[i] = k;
+        const int64_t* sx = &plan.src[4 * x];
+        if (k == 0) {
+            tsrc[4 * i] = inv_old[sx[0]];
+        } else if (k == 1) {
+            tsrc[4 * i] = inv_old[sx[0]];
+            tsrc[4 * i + 1] = (int)sx[1];
+        } else {
+            for (int c = 0; c < 4; ++c) tsrc[4 * i + c] = inv_old[sx[c]];
+        }
+    }
+    for (int64_t x = 0; x < En; ++x) {
+        if (plan.kind[x] == 1 && plan.src[4 * x + 1] == 0) {
+            // the four children of one parent are consecutive in the new order
+            zgrp.insert(zgrp.end(), {1, inv_old[plan.src[4 * x]], inv_new[x], inv_new[x + 1],
+                                     inv_new[x + 2], inv_new[x + 3]});
+        } else if (plan.kind[x] == 2) {
+            zgrp.insert(zgrp.end(), {2, -1, inv_new[x], -1, -1, -1});
+        }
+    }
+    const int G = (int)(zgrp.size() / 6);
+    int *dk = nullptr, *ds = nullptr, *dg = nullptr;
+    unsigned long long* dcount = nullptr;
+    unsigned long long counts[2] = {0, 0};
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(dk);
+        (void)hipFree(ds);
+        (void)hipFree(dg);
+        (void)hipFree(dcount);
+        (void)hipFree(uold);
+    };
+    if (hipMalloc((void**)&dk, tkind.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&ds, tsrc.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&dg, std::max<size_t>(1, zgrp.size()) * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&dcount, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemcpyAsync(dk, tkind.data(), tkind.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ds, tsrc.data(), tsrc.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        (G > 0 && hipMemcpyAsync(dg, zgrp.data(), zgrp.size() * sizeof(int), hipMemcpyHostToDevice,
+                                 ctx->stream) != hipSuccess) ||
+        hipMemsetAsync(dcount, 0, 2 * sizeof(unsigned long long), ctx->stream) != hipSuccess) {
+        cleanup();
+        return fail(ctx, DGIDP_E_DEVICE, "transfer buffers");
+    }
+    if (launch_transfer(N, (int)En, dk, ds, uold, ctx->U, ctx->stream) ||
+        (zs_eps > 0.0 && launch_zhang_shu(N, G, dg, uold, ctx->U, zs_eps, ctx->p.gamma, dcount, ctx->stream))) {
+        cleanup();
+        return fail(ctx, DGIDP_E_DEVICE, "transfer kernel launch failed");
+    }
+    const hipError_t e1 = hipMemcpyAsync(counts, dcount, sizeof(counts), hipMemcpyDeviceToHost, ctx->stream);
+    cleanup();
+    if (e1 != hipSuccess) return fail(ctx, DGIDP_E_DEVICE, "transfer counters");
+    ctx->has_state = true;
+    (void)NN;
+    if (n_leaves_out) *n_leaves_out = En;
+    if (st) {
+        st->n_refined = plan.n_refined;
+        st->n_balance_refined = plan.n_balance;
+        st->n_coarsened = plan.n_coarsened;
+        st->zs_limited = (int64_t)counts[0];
+        st->zs_unfixable = (int64_t)counts[1];
+    }
+    return 0;
+}
+
 // host copy of the operator tables (flat layout, see host_tables)
 int dgidp_host_tables(int N, double* out) { return host_tables(N, out); }
 

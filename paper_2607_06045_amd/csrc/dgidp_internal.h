@@ -80,6 +80,28 @@ struct DtSource {
     double* dt_out = nullptr;
 };
 
+// new leaf list of an adaptation and its source map (external leaf ids):
+// kind 0 kept (src[0] the old leaf), 1 child (src[0] the old parent, src[1] the
+// child index cx + 2 cy), 2 parent (src[0..3] the old children by child index)
+struct AdaptPlan {
+    std::vector<int8_t> level;
+    std::vector<int32_t> ix, iy;
+    std::vector<int8_t> kind;
+    std::vector<int64_t> src;  // [4 * new leaves]
+    int64_t n_refined = 0, n_balance = 0, n_coarsened = 0;
+};
+int adapt_leaves(int64_t E, const int8_t* lev, const int32_t* ix, const int32_t* iy, int nx0,
+                 int ny0, const int8_t* flags, AdaptPlan& plan, std::string& err);
+
+// transfer onto a new mesh, new internal element order: tkind[e] 0 copy,
+// 1 child, 2 parent; tsrc[e][4] old internal elements (child: parent, child
+// index).  Zhang-Shu groups zgrp[g][6] = kind (1 refine, 2 coarsen), old
+// parent (refine), new elements (4 children, or the parent and -1).
+int launch_transfer(int N, int E_new, const int* tkind, const int* tsrc, const double* uold,
+                    double* unew, hipStream_t s);
+int launch_zhang_shu(int N, int G, const int* zgrp, const double* uold, double* unew, double eps,
+                     double gamma, unsigned long long* counts, hipStream_t s);
+
 // launchers (dgidp_kernels.hip)
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
                  const double* un, double* uout, double a, double b, const DtSource& dt,

@@ -1074,6 +1074,163 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// solution transfer between meshes (Sec. 2.4): one thread per new node.
+// Children take the parent polynomial at their nodes (tensor product of the
+// mortar interpolation matrices); a new parent takes the exact L2 projection
+// of its four children (tensor product of the mortar projections, summed).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_transfer(int E, const int* __restrict__ tkind,
+                                                  const int* __restrict__ tsrc,
+                                                  const double* __restrict__ uold,
+                                                  double* __restrict__ unew)
+{
+    constexpr int n = N + 1, NN = n * n;
+    const Tab<N>& tb = T<N>();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E * NN) return;
+    const int e = i / NN, q = i - e * NN, a = q % n, b = q / n;
+    const int kind = tkind[e];
+    double out[4] = {0, 0, 0, 0};
+    if (kind == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = uold[((size_t)tsrc[4 * e] * 4 + v) * NN + q];
+    } else if (kind == 1) {
+        const int p = tsrc[4 * e], c = tsrc[4 * e + 1], cx = c & 1, cy = c >> 1;
+        const double* up = uold + (size_t)p * 4 * NN;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < n; ++l) {
+                double row = 0.0;
+#pragma unroll
+                for (int k = 0; k < n; ++k) row += tb.I[cx][a][k] * up[(v * n + l) * n + k];
+                acc += tb.I[cy][b][l] * row;
+            }
+            out[v] = acc;
+        }
+    } else {
+        for (int c = 0; c < 4; ++c) {
+            const int cx = c & 1, cy = c >> 1;
+            const double* uc = uold + (size_t)tsrc[4 * e + c] * 4 * NN;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < n; ++l) {
+                    double row = 0.0;
+#pragma unroll
+                    for (int k = 0; k < n; ++k) row += tb.P[cx][a][k] * uc[(v * n + l) * n + k];
+                    acc += tb.P[cy][b][l] * row;
+                }
+                out[v] += acc;
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) unew[((size_t)e * 4 + v) * NN + q] = out[v];
+}
+
+// Zhang-Shu scaling toward the reference mean (Sec. 2.4): one wave per group
+// (the four children of a refined element, or one new parent).  A troubled
+// group (a node with rho < eps or p < eps) is scaled by the largest theta that
+// lifts every node to rho, p >= eps (aimed at eps (1 + 2^-40)); one theta per
+// group keeps the group's mass.  counts[0] limited groups, counts[1] groups
+// whose mean is itself below the thresholds (theta = 0).
+template <int N>
+__global__ __launch_bounds__(256) void k_zhang_shu(int G, const int* __restrict__ grp,
+                                                   const double* __restrict__ uold,
+                                                   double* __restrict__ unew, double eps,
+                                                   double gamma, unsigned long long* counts)
+{
+    constexpr int n = N + 1, NN = n * n;
+    const Tab<N>& tb = T<N>();
+    const int lane = threadIdx.x & 63;
+    const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (g >= G) return;  // whole waves leave together
+    const int* R = grp + 6 * g;
+    const int kind = R[0];
+    const int cnt = kind == 1 ? 4 : 1;
+    const double ig1 = 1.0 / (gamma - 1.0);
+    // reference mean: the old parent (refinement) or the projected parent
+    const double* ref = kind == 1 ? uold + (size_t)R[1] * 4 * NN : unew + (size_t)R[2] * 4 * NN;
+    double ub[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double s = 0.0;
+        for (int q = lane; q < NN; q += 64) s += tb.w[q % n] * tb.w[q / n] * ref[v * NN + q];
+        ub[v] = wave_sum(s) * 0.25;
+    }
+    int trouble = 0;
+    for (int j = lane; j < cnt * NN; j += 64) {
+        const double* ue = unew + (size_t)R[2 + j / NN] * 4 * NN;
+        const int q = j % NN;
+        double w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[v] = ue[v * NN + q];
+        const double p = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+        if (!(w[0] >= eps) || !(p >= eps)) trouble = 1;
+    }
+    if (!__any(trouble)) return;
+    const double et = eps * kMargin;
+    const double pb = (gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+    const bool fixable = ub[0] > et && pb > et;
+    double theta = 0.0;
+    if (fixable) {
+        double t = 1.0;
+        for (int j = lane; j < cnt * NN; j += 64) {
+            const double* ue = unew + (size_t)R[2 + j / NN] * 4 * NN;
+            const int q = j % NN;
+            double d[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) d[v] = ue[v * NN + q] - ub[v];
+            double ti = 1.0;
+            if (ub[0] + d[0] < et) ti = (ub[0] - et) / (-d[0]);
+            ti = fmin(ti, theta_p(ub, d, et, ig1));
+            t = fmin(t, ti);
+        }
+        theta = wave_min(t);
+    }
+    for (int j = lane; j < cnt * NN; j += 64) {
+        double* ue = unew + (size_t)R[2 + j / NN] * 4 * NN;
+        const int q = j % NN;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ue[v * NN + q] = ub[v] + theta * (ue[v * NN + q] - ub[v]);
+    }
+    if (lane == 0) {
+        atomicAdd(&counts[0], 1ull);
+        if (!fixable) atomicAdd(&counts[1], 1ull);
+    }
+}
+
+int launch_transfer(int N, int E_new, const int* tkind, const int* tsrc, const double* uold,
+                    double* unew, hipStream_t s)
+{
+    const int NN = (N + 1) * (N + 1);
+    const int grid = (E_new * NN + 255) / 256;
+    if (E_new <= 0) return 0;
+    if (N == 3) hipLaunchKernelGGL(k_transfer<3>, dim3(grid), dim3(256), 0, s, E_new, tkind, tsrc, uold, unew);
+    else if (N == 4) hipLaunchKernelGGL(k_transfer<4>, dim3(grid), dim3(256), 0, s, E_new, tkind, tsrc, uold, unew);
+    else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_zhang_shu(int N, int G, const int* zgrp, const double* uold, double* unew, double eps,
+                     double gamma, unsigned long long* counts, hipStream_t s)
+{
+    if (G <= 0) return 0;
+    const int grid = (G + 3) / 4;  // four waves (groups) per block
+    if (N == 3)
+        hipLaunchKernelGGL(k_zhang_shu<3>, dim3(grid), dim3(256), 0, s, G, zgrp, uold, unew, eps, gamma, counts);
+    else if (N == 4)
+        hipLaunchKernelGGL(k_zhang_shu<4>, dim3(grid), dim3(256), 0, s, G, zgrp, uold, unew, eps, gamma, counts);
+    else
+        return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------------
 // small utility kernels
 // ---------------------------------------------------------------------------
 __global__ void k_permute(int E, int NN, const int* perm, const double* src, double* dst, int to_int)
