@@ -207,8 +207,10 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms);
 /* Host-only: the operator tables the library uploads for degree N, flat
  * doubles: w[n] (LGL weights, Sec. 2.1), Sbar[n][n] (Sec. 2.1), mortar
  * interpolation I[2][n][n] and L2 projection P[2][n][n] (Sec. 2.2, Kopriva's
- * mortar), sparse mortar weights Wt[n][2n] (eq. local_weights, App. A); n = N+1.
- * `out` holds at least n + 5 n^2 + 2 n^2 doubles.  Needs no GPU. */
+ * mortar), sparse mortar weights Wt[n][2n] (eq. local_weights, App. A), and the
+ * nodal-to-modal transform Vinv[n][n] onto orthonormal Legendre polynomials
+ * (indicator and features); n = N+1.  `out` holds at least n + 8 n^2 doubles.
+ * Needs no GPU. */
 int dgidp_host_tables(int N, double* out);
 
 #ifdef __cplusplus

@@ -101,16 +101,16 @@ class DgidpError(RuntimeError):
 
 
 def host_tables(N):
-    """The library's operator tables for degree N: dict of w, S, I, P, Wt."""
+    """The library's operator tables for degree N: dict of w, S, I, P, Wt, Vinv."""
     n = N + 1
-    out = np.zeros(n + 7 * n * n)
+    out = np.zeros(n + 8 * n * n)
     rc = _lib.dgidp_host_tables(N, out.ctypes.data)
     if rc:
         raise DgidpError(ERRORS.get(rc, rc))
     o = 0
     res = {}
     for key, shape in (("w", (n,)), ("S", (n, n)), ("I", (2, n, n)), ("P", (2, n, n)),
-                       ("Wt", (n, 2 * n))):
+                       ("Wt", (n, 2 * n)), ("Vinv", (n, n))):
         size = int(np.prod(shape))
         res[key] = out[o:o + size].reshape(shape)
         o += size

@@ -31,6 +31,7 @@ struct Tab {
     double P[2][n][n];            // L2 projection: half h, large node k, small node l
     double Wt[n][2 * n];          // sparse mortar weights, reference measure on [-1, 1]
     float wf[n], Sf[n][n], If[2][n][n], Pf[2][n][n];  // FP32 copies for the mixed mode
+    double Vinv[n][n];            // nodal -> modal, orthonormal Legendre: m_i = sum_a Vinv[i][a] q_a
 };
 
 // Device-side statistics accumulator.
@@ -101,6 +102,10 @@ int launch_transfer(int N, int E_new, const int* tkind, const int* tsrc, const d
                     double* unew, hipStream_t s);
 int launch_zhang_shu(int N, int G, const int* zgrp, const double* uold, double* unew, double eps,
                      double gamma, unsigned long long* counts, hipStream_t s);
+
+// modal indicator alpha[E] and features feat[E][16], external order (either may be null)
+int launch_indicator(int N, int E, const double* u, const int* perm, double gamma, float* alpha,
+                     float* feat, hipStream_t s);
 
 // launchers (dgidp_kernels.hip)
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,

@@ -1074,6 +1074,105 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// modal indicator and features: one thread per node stages rho p, rho and p,
+// one thread per mode (i, j) forms its squared orthonormal-Legendre
+// coefficient, and one thread per element reduces the shells.
+//  Hennemann indicator on rho p: energy = max of the energy fractions of the
+//  highest and the second-highest mode shells, alpha = logistic with threshold
+//  T = 0.5 10^(-1.8 (N+1)^(1/4)) and sharpness ln(9999), zero below 1e-3,
+//  capped at 0.5.
+//  Features: x- and y-shell energy fractions of rho and of p for the shells
+//  N-3 .. N (16 values).
+// Outputs (FP32) go to the external element order through perm.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(128) void k_indicator(const double* __restrict__ u, int E,
+                                                   const int* __restrict__ perm, double gamma,
+                                                   float* alpha, float* feat)
+{
+    constexpr int n = N + 1, NN = n * n, EPB = 128 / NN;
+    __shared__ double sQ[3][EPB][NN];
+    __shared__ double sM[3][EPB][NN];
+    const Tab<N>& tb = T<N>();
+    const int tid = threadIdx.x;
+    const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = tid < EPB * NN && e < E;
+    if (act) {
+        double w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
+        const double p = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+        sQ[0][le][q] = w[0] * p;
+        sQ[1][le][q] = w[0];
+        sQ[2][le][q] = p;
+    }
+    __syncthreads();
+    if (act) {
+        // mode (i, j) = (a, b): m = sum_b' Vinv[j][b'] sum_a' Vinv[i][a'] q[b'][a']
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double m = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < n; ++bb) {
+                double r = 0.0;
+#pragma unroll
+                for (int aa = 0; aa < n; ++aa) r += tb.Vinv[a][aa] * sQ[k][le][bb * n + aa];
+                m += tb.Vinv[b][bb] * r;
+            }
+            sM[k][le][q] = m * m;
+        }
+    }
+    __syncthreads();
+    if (!act || q != 0) return;
+    const int x = perm[e];
+    if (alpha) {
+        double all = 0.0, low1 = 0.0, low2 = 0.0;
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const double m2 = sM[0][le][j * n + i];
+                all += m2;
+                if (i < N && j < N) low1 += m2;
+                if (i < N - 1 && j < N - 1) low2 += m2;
+            }
+        const double en = fmax((all - low1) / all, (low1 - low2) / low1);
+        const double T = 0.5 * pow(10.0, -1.8 * sqrt(sqrt((double)(N + 1))));
+        const double s = log((1.0 - 1e-4) / 1e-4);
+        double al = 1.0 / (1.0 + exp(-(s / T) * (en - T)));
+        if (al < 1e-3) al = 0.0;
+        alpha[x] = (float)fmin(al, 0.5);
+    }
+    if (feat) {
+        for (int k = 1; k < 3; ++k) {
+            double tot = 0.0;
+            for (int i = 0; i < NN; ++i) tot += sM[k][le][i];
+            for (int sh = 0; sh < 4; ++sh) {
+                const int kk = N - 3 + sh;
+                double xs = 0.0, ys = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    xs += sM[k][le][j * n + kk];  // x mode kk, all y modes j
+                    ys += sM[k][le][kk * n + j];  // y mode kk, all x modes j
+                }
+                feat[(size_t)x * 16 + (k - 1) * 8 + sh] = (float)(xs / tot);
+                feat[(size_t)x * 16 + (k - 1) * 8 + 4 + sh] = (float)(ys / tot);
+            }
+        }
+    }
+}
+
+int launch_indicator(int N, int E, const double* u, const int* perm, double gamma, float* alpha,
+                     float* feat, hipStream_t s)
+{
+    if (E <= 0) return 0;
+    const int EPB = 128 / ((N + 1) * (N + 1));
+    const int grid = (E + EPB - 1) / EPB;
+    if (N == 3) hipLaunchKernelGGL(k_indicator<3>, dim3(grid), dim3(128), 0, s, u, E, perm, gamma, alpha, feat);
+    else if (N == 4) hipLaunchKernelGGL(k_indicator<4>, dim3(grid), dim3(128), 0, s, u, E, perm, gamma, alpha, feat);
+    else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------------
 // solution transfer between meshes (Sec. 2.4): one thread per new node.
 // Children take the parent polynomial at their nodes (tensor product of the
 // mortar interpolation matrices); a new parent takes the exact L2 projection

@@ -252,6 +252,26 @@ void build(Tab<N>& t)
                 const ld hi = std::min(-1 + C[k + 1], -1 + h + C[l + 1] / 2);
                 t.Wt[k][h * n + l] = hi - lo > 1e-12L ? (double)(hi - lo) : 0.0;
             }
+    // modal transform: V[a][i] = sqrt((2i+1)/2) P_i(x_a), Vinv = V^-1
+    {
+        std::vector<std::vector<ld>> V(n, std::vector<ld>(n, 0)), R(n, std::vector<ld>(n, 0));
+        for (int a = 0; a < n; ++a) {
+            ld pm = 1, pc = x[a];
+            for (int i = 0; i < n; ++i) {
+                const ld pi = i == 0 ? 1 : (i == 1 ? x[a] : pc);
+                V[a][i] = std::sqrt((2 * i + 1) / 2.0L) * pi;
+                if (i >= 1) {
+                    const ld pn = ((2 * i + 1) * x[a] * pc - i * pm) / (i + 1);
+                    pm = pc;
+                    pc = pn;
+                }
+            }
+            R[a][a] = 1;
+        }
+        solve(V, R);
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < n; ++a) t.Vinv[i][a] = (double)R[i][a];
+    }
     for (int i = 0; i < n; ++i) {
         t.wf[i] = (float)t.w[i];
         for (int j = 0; j < n; ++j) t.Sf[i][j] = (float)t.S[i][j];
@@ -292,7 +312,7 @@ int build_and_upload_tables(int N, std::vector<double>* nodes)
 }
 
 // host copy of the tables for tests of the table builder (flat doubles:
-// w[n], S[n*n], I[2*n*n], P[2*n*n], Wt[n*2n])
+// w[n], S[n*n], I[2*n*n], P[2*n*n], Wt[n*2n], Vinv[n*n])
 int host_tables(int N, double* out)
 {
     auto dump = [&](auto& t, int n) {
@@ -308,6 +328,8 @@ int host_tables(int N, double* out)
                 for (int j = 0; j < n; ++j) *o++ = t.P[h][i][j];
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < 2 * n; ++j) *o++ = t.Wt[i][j];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) *o++ = t.Vinv[i][j];
     };
     if (N == 3) {
         Tab<3> t;

@@ -39,6 +39,8 @@ def test_library_tables_match_oracle(oracle, N):
     assert np.abs(t["P"] - Pm).max() < 1e-14
     assert np.abs(t["Wt"] - W).max() < 1e-15
     assert np.array_equal(t["Wt"] > 0, W > 0)
+    from oracle import indicator as IND
+    assert np.abs(t["Vinv"] - np.linalg.inv(IND.vandermonde(N))).max() < 1e-13
 
 
 def test_solver_refuses_without_gpu():
