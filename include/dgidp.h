@@ -195,6 +195,49 @@ int dgidp_amr_flags(int64_t n, const float* indicator, const int8_t* level, int 
                     int med_level, float med_threshold, int max_level, float max_threshold,
                     int8_t* flags);
 
+/* ---------------- troubled-cell / AMR indicators ---------------- */
+
+enum { DGIDP_IND_HENNEMANN = 0, DGIDP_IND_MLP = 1 };
+#define DGIDP_MLP_NPARAM 5313
+
+/* Per-element indicator of the current state, FP32 [E], external order.
+ * DGIDP_IND_HENNEMANN: the modal shock indicator of Hennemann et al. (the
+ * paper's AMR indicator for shocks, Sec. 3.3 to 3.6) on rho p: orthonormal
+ * Legendre modes, energy = max of the energy fractions of the highest and the
+ * second-highest mode shells, alpha = 1 / (1 + exp(-(s/T)(energy - T))) with
+ * T = 0.5 10^(-1.8 (N+1)^(1/4)), s = ln(9999); alpha < 1e-3 -> 0; capped at 0.5.
+ * DGIDP_IND_MLP: the learned network of dgidp_mlp_* applied to the features of
+ * dgidp_features (its raw output).  Errors: DGIDP_E_NO_STATE,
+ * DGIDP_E_INVALID_ARG (unknown kind, network weights not set). */
+int dgidp_indicator(dgidp_ctx* ctx, int kind, float* alpha, int on_device);
+/* The 16 learned-indicator features per element, FP32 [E][16], external
+ * order: for q = rho, then p, the x-shell energy fractions sum_j m_kj^2 / E_q
+ * and then the y-shell fractions sum_i m_ik^2 / E_q of the orthonormal
+ * Legendre modes m of q, shells k = N-3 .. N. */
+int dgidp_features(dgidp_ctx* ctx, float* f, int on_device);
+
+/* Learned indicator network, 16 -> 64 -> 64 -> 1, ReLU, for the callers that
+ * want a cheaper or trained AMR indicator.  Parameters, FP32, in this order:
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3 (W[j][k]: unit j, input
+ * k), DGIDP_MLP_NPARAM values.  The context keeps FP32 master weights and a
+ * BF16 copy (round to nearest even) that every pass uses; arithmetic FP32.
+ * set_weights copies host weights and resets the Adam state; get_weights
+ * returns the masters (host). */
+int dgidp_mlp_set_weights(dgidp_ctx* ctx, const float* w);
+int dgidp_mlp_get_weights(dgidp_ctx* ctx, float* w);
+/* y[B] = network(x[B][16]). */
+int dgidp_mlp_forward(dgidp_ctx* ctx, const float* x, int64_t B, float* y, int on_device);
+/* Gradient of loss = (1/B) sum_s (y_s - t_s)^2 at the BF16 weights, into
+ * grad[DGIDP_MLP_NPARAM] (host or device as on_device); *loss (host, may be
+ * NULL) receives the loss.  Deterministic. */
+int dgidp_mlp_grad(dgidp_ctx* ctx, const float* x, const float* t, int64_t B, float* grad, float* loss,
+                   int on_device);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr > 0) on
+ * that gradient, applied to the FP32 masters; new BF16 copy.  *loss (host,
+ * may be NULL) receives the loss before the step. */
+int dgidp_mlp_train_step(dgidp_ctx* ctx, const float* x, const float* t, int64_t B, float lr,
+                         float* loss, int on_device);
+
 /* Mean duration in milliseconds of one launch of each kernel of a step,
  * measured with HIP events on the context's stream over back-to-back launches:
  * ms[0] the element stage kernel, averaged over `reps` rounds of its three

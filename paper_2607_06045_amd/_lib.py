@@ -21,6 +21,8 @@ FP64, MIXED = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
 LIMIT_NONE, LIMIT_POSITIVITY = 0, 1
 RHS_HIGH, RHS_LOW = 0, 1
+IND_HENNEMANN, IND_MLP = 0, 1
+MLP_NPARAM = 5313
 
 ERRORS = {
     -1: "DGIDP_E_INVALID_ARG", -2: "DGIDP_E_UNSUPPORTED_N", -3: "DGIDP_E_DEVICE",
@@ -85,6 +87,14 @@ _SIGS = {
     "dgidp_mesh_download": (_i, [_vp, _vp, _vp, _vp]),
     "dgidp_amr_flags": (_i, [ctypes.c_int64, _vp, _vp, _i, _i, ctypes.c_float, _i,
                              ctypes.c_float, _vp]),
+    "dgidp_indicator": (_i, [_vp, _i, _vp, _i]),
+    "dgidp_features": (_i, [_vp, _vp, _i]),
+    "dgidp_mlp_set_weights": (_i, [_vp, _vp]),
+    "dgidp_mlp_get_weights": (_i, [_vp, _vp]),
+    "dgidp_mlp_forward": (_i, [_vp, _vp, ctypes.c_int64, _vp, _i]),
+    "dgidp_mlp_grad": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_float), _i]),
+    "dgidp_mlp_train_step": (_i, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float,
+                                  ctypes.POINTER(ctypes.c_float), _i]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -300,6 +310,91 @@ class Solver:
         self._check(_lib.dgidp_mesh_download(self._h, lv.ctypes.data, ix.ctypes.data, iy.ctypes.data),
                     "dgidp_mesh_download")
         return lv, ix, iy
+
+    # ---- indicators and the learned-indicator network ----
+    def indicator(self, kind=IND_HENNEMANN, device=False):
+        """Per-element indicator, FP32 [E] (numpy, or a cuda tensor if device)."""
+        if device:
+            out = torch.empty(self.E, dtype=torch.float32, device="cuda")
+            self._check(_lib.dgidp_indicator(self._h, kind, out.data_ptr(), 1), "dgidp_indicator")
+            return out
+        out = np.zeros(self.E, np.float32)
+        self._check(_lib.dgidp_indicator(self._h, kind, out.ctypes.data, 0), "dgidp_indicator")
+        return out
+
+    def features(self, device=False):
+        """The 16 learned-indicator features per element, FP32 [E, 16]."""
+        if device:
+            out = torch.empty((self.E, 16), dtype=torch.float32, device="cuda")
+            self._check(_lib.dgidp_features(self._h, out.data_ptr(), 1), "dgidp_features")
+            return out
+        out = np.zeros((self.E, 16), np.float32)
+        self._check(_lib.dgidp_features(self._h, out.ctypes.data, 0), "dgidp_features")
+        return out
+
+    def mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != MLP_NPARAM:
+            raise ValueError(f"{MLP_NPARAM} parameters expected")
+        self._check(_lib.dgidp_mlp_set_weights(self._h, w.ctypes.data), "dgidp_mlp_set_weights")
+
+    def mlp_get_weights(self):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        self._check(_lib.dgidp_mlp_get_weights(self._h, w.ctypes.data), "dgidp_mlp_get_weights")
+        return w
+
+    @staticmethod
+    def _mlp_args(x, t=None):
+        dev = isinstance(x, torch.Tensor)
+        if dev:
+            x = x.contiguous().float()
+            if x.dim() != 2 or x.shape[1] != 16 or not x.is_cuda:
+                raise ValueError("x must be a [B, 16] cuda tensor")
+            if t is not None:
+                t = t.contiguous().float()
+                if t.shape != (x.shape[0],) or not t.is_cuda:
+                    raise ValueError("t must be a [B] cuda tensor")
+            return dev, x, t, x.data_ptr(), (t.data_ptr() if t is not None else None)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        if x.ndim != 2 or x.shape[1] != 16:
+            raise ValueError("x must be [B, 16]")
+        if t is not None:
+            t = np.ascontiguousarray(t, dtype=np.float32)
+            if t.shape != (x.shape[0],):
+                raise ValueError("t must be [B]")
+        return dev, x, t, x.ctypes.data, (t.ctypes.data if t is not None else None)
+
+    def mlp_forward(self, x):
+        dev, x, _, px, _ = self._mlp_args(x)
+        B = x.shape[0]
+        if dev:
+            y = torch.empty(B, dtype=torch.float32, device="cuda")
+            py = y.data_ptr()
+        else:
+            y = np.zeros(B, np.float32)
+            py = y.ctypes.data
+        self._check(_lib.dgidp_mlp_forward(self._h, px, B, py, int(dev)), "dgidp_mlp_forward")
+        return y
+
+    def mlp_grad(self, x, t):
+        dev, x, t, px, pt = self._mlp_args(x, t)
+        loss = ctypes.c_float()
+        if dev:
+            g = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+            pg = g.data_ptr()
+        else:
+            g = np.zeros(MLP_NPARAM, np.float32)
+            pg = g.ctypes.data
+        self._check(_lib.dgidp_mlp_grad(self._h, px, pt, x.shape[0], pg, ctypes.byref(loss), int(dev)),
+                    "dgidp_mlp_grad")
+        return g, loss.value
+
+    def mlp_train_step(self, x, t, lr):
+        dev, x, t, px, pt = self._mlp_args(x, t)
+        loss = ctypes.c_float()
+        self._check(_lib.dgidp_mlp_train_step(self._h, px, pt, x.shape[0], lr, ctypes.byref(loss),
+                                              int(dev)), "dgidp_mlp_train_step")
+        return loss.value
 
     def synchronize(self):
         self._check(_lib.dgidp_synchronize(self._h), "dgidp_synchronize")

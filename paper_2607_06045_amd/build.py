@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgidp.so")
-SOURCES = ["dgidp_kernels.hip", "dgidp_tables.cpp", "dgidp_host.cpp", "dgidp_amr.cpp"]
+SOURCES = ["dgidp_kernels.hip", "dgidp_tables.cpp", "dgidp_host.cpp", "dgidp_amr.cpp", "dgidp_mlp.hip"]
 # packed FP32 instructions are disabled: hipcc would otherwise emit them from
 # ordinary float code
 HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wno-pass-failed",

@@ -39,6 +39,9 @@ struct dgidp_ctx {
     int acc_slot = 0;
     DevStats* stats = nullptr;
     unsigned long long* bad = nullptr;
+    MlpState* mlp = nullptr;       // learned indicator, created on first use
+    float* ind_buf = nullptr;      // [E] indicator / [E*16] features staging
+    size_t ind_cap = 0;
     bool has_state = false;
 };
 
@@ -369,6 +372,8 @@ void dgidp_destroy(dgidp_ctx* ctx)
     free_mesh(ctx);
     dfree(ctx->dt_dev);
     dfree(ctx->acc);
+    dfree(ctx->ind_buf);
+    if (ctx->mlp) mlp_destroy(ctx->mlp);
     dfree(ctx->stats);
     dfree(ctx->bad);
     delete ctx;
@@ -819,6 +824,156 @@ int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int
         st->zs_unfixable = (int64_t)counts[1];
     }
     return 0;
+}
+
+static float* ind_staging(dgidp_ctx* ctx, size_t floats)
+{
+    if (ctx->ind_cap < floats) {
+        dfree(ctx->ind_buf);
+        ctx->ind_cap = 0;
+        if (hipMalloc((void**)&ctx->ind_buf, floats * sizeof(float)) != hipSuccess) return nullptr;
+        ctx->ind_cap = floats;
+    }
+    return ctx->ind_buf;
+}
+
+static MlpState* get_mlp(dgidp_ctx* ctx)
+{
+    if (!ctx->mlp) ctx->mlp = mlp_create();
+    return ctx->mlp;
+}
+
+int dgidp_features(dgidp_ctx* ctx, float* f, int on_device)
+{
+    if (!ctx || !f) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    float* out = on_device ? f : ind_staging(ctx, (size_t)ctx->E * 16);
+    if (!out) return fail(ctx, DGIDP_E_DEVICE, "staging buffer");
+    if (launch_indicator(ctx->p.N, (int)ctx->E, ctx->U, ctx->dm.perm, ctx->p.gamma, nullptr, out,
+                         ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(f, out, (size_t)ctx->E * 16 * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+int dgidp_indicator(dgidp_ctx* ctx, int kind, float* alpha, int on_device)
+{
+    if (!ctx || !alpha || (kind != DGIDP_IND_HENNEMANN && kind != DGIDP_IND_MLP)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    const size_t E = (size_t)ctx->E;
+    float* out = alpha;
+    if (kind == DGIDP_IND_HENNEMANN) {
+        if (!on_device && !(out = ind_staging(ctx, E))) return fail(ctx, DGIDP_E_DEVICE, "staging buffer");
+        if (launch_indicator(ctx->p.N, (int)E, ctx->U, ctx->dm.perm, ctx->p.gamma, out, nullptr, ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
+    } else {
+        MlpState* m = get_mlp(ctx);
+        if (!m) return fail(ctx, DGIDP_E_DEVICE, "network buffers");
+        if (!mlp_has_weights(m)) return fail(ctx, DGIDP_E_INVALID_ARG, "network weights not set");
+        float* feat = ind_staging(ctx, E * 17);
+        if (!feat) return fail(ctx, DGIDP_E_DEVICE, "staging buffer");
+        if (!on_device) out = feat + E * 16;
+        if (launch_indicator(ctx->p.N, (int)E, ctx->U, ctx->dm.perm, ctx->p.gamma, nullptr, feat, ctx->stream) ||
+            mlp_forward(m, feat, (int64_t)E, out, ctx->stream))
+            return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
+    }
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(alpha, out, E * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+int dgidp_mlp_set_weights(dgidp_ctx* ctx, const float* w)
+{
+    if (!ctx || !w) return DGIDP_E_INVALID_ARG;
+    for (int i = 0; i < mlp_num_params(); ++i)
+        if (!std::isfinite(w[i])) return fail(ctx, DGIDP_E_INVALID_ARG, "non-finite weight");
+    MlpState* m = get_mlp(ctx);
+    if (!m || mlp_set_weights(m, w, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "network weights");
+    return 0;
+}
+
+int dgidp_mlp_get_weights(dgidp_ctx* ctx, float* w)
+{
+    if (!ctx || !w) return DGIDP_E_INVALID_ARG;
+    MlpState* m = get_mlp(ctx);
+    if (!m) return fail(ctx, DGIDP_E_DEVICE, "network buffers");
+    if (!mlp_has_weights(m)) return fail(ctx, DGIDP_E_INVALID_ARG, "network weights not set");
+    if (mlp_get_weights(m, w, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "network weights");
+    return 0;
+}
+
+int dgidp_mlp_forward(dgidp_ctx* ctx, const float* x, int64_t B, float* y, int on_device)
+{
+    if (!ctx || !x || !y || B < 0 || B > (int64_t)1 << 30) return DGIDP_E_INVALID_ARG;
+    MlpState* m = get_mlp(ctx);
+    if (!m) return fail(ctx, DGIDP_E_DEVICE, "network buffers");
+    if (!mlp_has_weights(m)) return fail(ctx, DGIDP_E_INVALID_ARG, "network weights not set");
+    if (B == 0) return 0;
+    const float* dx = x;
+    float* dy = y;
+    if (!on_device) {
+        float* sx = mlp_scratch(m, 0, (size_t)B * 16);
+        float* sy = mlp_scratch(m, 2, (size_t)B);
+        if (!sx || !sy) return fail(ctx, DGIDP_E_DEVICE, "network scratch");
+        HIPCHK(hipMemcpyAsync(sx, x, (size_t)B * 16 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        dx = sx;
+        dy = sy;
+    }
+    if (mlp_forward(m, dx, B, dy, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "network kernel launch failed");
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(y, dy, (size_t)B * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+static int mlp_grad_common(dgidp_ctx* ctx, const float* x, const float* t, int64_t B, float lr,
+                           float* grad, float* loss, int on_device)
+{
+    if (!ctx || !x || !t || B <= 0 || B > (int64_t)1 << 30 || !(lr >= 0.0f)) return DGIDP_E_INVALID_ARG;
+    MlpState* m = get_mlp(ctx);
+    if (!m) return fail(ctx, DGIDP_E_DEVICE, "network buffers");
+    if (!mlp_has_weights(m)) return fail(ctx, DGIDP_E_INVALID_ARG, "network weights not set");
+    const float *dx = x, *dt = t;
+    float* dg = grad;
+    const size_t np = (size_t)mlp_num_params();
+    if (!on_device) {
+        float* sx = mlp_scratch(m, 0, (size_t)B * 16);
+        float* st = mlp_scratch(m, 1, (size_t)B);
+        float* sg = mlp_scratch(m, 3, np);
+        if (!sx || !st || !sg) return fail(ctx, DGIDP_E_DEVICE, "network scratch");
+        HIPCHK(hipMemcpyAsync(sx, x, (size_t)B * 16 * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(st, t, (size_t)B * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        dx = sx;
+        dt = st;
+        dg = grad ? sg : nullptr;
+    }
+    if (mlp_grad_step(m, dx, dt, B, lr, dg, loss, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "network kernel launch failed");
+    if (!on_device && grad) {
+        HIPCHK(hipMemcpyAsync(grad, dg, np * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+int dgidp_mlp_grad(dgidp_ctx* ctx, const float* x, const float* t, int64_t B, float* grad, float* loss,
+                   int on_device)
+{
+    if (!grad) return DGIDP_E_INVALID_ARG;
+    return mlp_grad_common(ctx, x, t, B, 0.0f, grad, loss, on_device);
+}
+
+int dgidp_mlp_train_step(dgidp_ctx* ctx, const float* x, const float* t, int64_t B, float lr,
+                         float* loss, int on_device)
+{
+    if (!(lr > 0.0f)) return DGIDP_E_INVALID_ARG;
+    return mlp_grad_common(ctx, x, t, B, lr, nullptr, loss, on_device);
 }
 
 // host copy of the operator tables (flat layout, see host_tables)

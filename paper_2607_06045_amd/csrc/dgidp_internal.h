@@ -107,6 +107,21 @@ int launch_zhang_shu(int N, int G, const int* zgrp, const double* uold, double* 
 int launch_indicator(int N, int E, const double* u, const int* perm, double gamma, float* alpha,
                      float* feat, hipStream_t s);
 
+// learned indicator network (dgidp_mlp.hip); device pointers on stream st
+struct MlpState;
+int mlp_num_params();
+MlpState* mlp_create();
+void mlp_destroy(MlpState* s);
+bool mlp_has_weights(const MlpState* s);
+float* mlp_scratch(MlpState* s, int which, size_t floats);  // which in 0..3, grown on demand
+int mlp_set_weights(MlpState* s, const float* host_w, hipStream_t st);
+int mlp_get_weights(MlpState* s, float* host_w, hipStream_t st);
+int mlp_forward(MlpState* s, const float* x, int64_t B, float* y, hipStream_t st);
+// gradient (to grad, if not null) and loss (to *loss_host, if not null); an
+// Adam step when lr > 0
+int mlp_grad_step(MlpState* s, const float* x, const float* t, int64_t B, float lr, float* grad,
+                  float* loss_host, hipStream_t st);
+
 // launchers (dgidp_kernels.hip)
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
                  const double* un, double* uout, double a, double b, const DtSource& dt,
