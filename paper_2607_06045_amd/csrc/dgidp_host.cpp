@@ -70,6 +70,7 @@ void dfree(T*& p)
 void free_mesh(dgidp_ctx* c)
 {
     dfree(c->dm.fnbr);
+    dfree(c->dm.fnbr2);
     dfree(c->dm.fmort);
     dfree(c->dm.mort);
     dfree(c->dm.h);
@@ -138,6 +139,7 @@ struct HostMesh {
     int M = 0;
     std::vector<int> perm;          // internal -> external
     std::vector<int> fnbr, fmort;   // [E*4]
+    std::vector<int> fnbr2;         // [E*4] second small element of a large face, else -1
     std::vector<int> mort;          // [M*4] large, face, small0, small1
     std::vector<int> snode, spart;  // [M*3n]
 };
@@ -209,6 +211,7 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         inv[ord[i].second] = (int)i;
     }
     hm.fnbr.assign(E * 4, -1);
+    hm.fnbr2.assign(E * 4, -1);
     hm.fmort.assign(E * 4, -1);
     hm.mort.clear();
     int M = 0;
@@ -241,6 +244,7 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
                 return DGIDP_E_MESH_NOT_BALANCED;
             }
             hm.fnbr[i * 4 + f] = inv[s0];
+            hm.fnbr2[i * 4 + f] = inv[s1];
             hm.fmort[i * 4 + f] = (M << 2);
             hm.mort.push_back((int)i);
             hm.mort.push_back(f);
@@ -427,7 +431,8 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     ctx->nx0 = nx0;
     ctx->ny0 = ny0;
     int rc = 0;
-    if ((rc = upload(ctx, ctx->dm.fnbr, hm.fnbr)) || (rc = upload(ctx, ctx->dm.fmort, hm.fmort)) ||
+    if ((rc = upload(ctx, ctx->dm.fnbr, hm.fnbr)) || (rc = upload(ctx, ctx->dm.fnbr2, hm.fnbr2)) ||
+        (rc = upload(ctx, ctx->dm.fmort, hm.fmort)) ||
         (rc = upload(ctx, ctx->dm.mort, hm.mort)) || (rc = upload(ctx, ctx->dm.h, hh)) ||
         (rc = upload(ctx, ctx->dm.slot_node, hm.snode)) ||
         (rc = upload(ctx, ctx->dm.slot_partner, hm.spart)) || (rc = upload(ctx, ctx->dm.perm, hm.perm)))

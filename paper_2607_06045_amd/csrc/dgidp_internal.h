@@ -50,6 +50,7 @@ struct DevStats {
 struct DevMesh {
     int E = 0, M = 0;
     int* fnbr = nullptr;        // [E*4] neighbour element across the face (large element for small sides)
+    int* fnbr2 = nullptr;       // [E*4] second small element across a large face, else -1
     int* fmort = nullptr;       // [E*4] face codes
     int* mort = nullptr;        // [M*4] large element, large face, small 0, small 1
     double* h = nullptr;        // [E*2] hx, hy

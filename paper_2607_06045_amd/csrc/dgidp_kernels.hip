@@ -1,8 +1,8 @@
 // HIP kernels of dgidp for gfx950 (MI355X).
 //
 // One SSP-RK3 stage (Sec. 2.3 and Sec. 3 intro of the paper) is two kernels:
-//   k_stage   one thread per LGL node; a block of 128 threads holds 8 elements
-//             (N = 3) or 5 elements (N = 4).  It stages the element in LDS,
+//   k_stage   one thread per LGL node; a block holds 4 elements in one wave
+//             (N = 3) or 5 elements in two waves (N = 4).  It stages the element in LDS,
 //             evaluates the surface fluxes with one lane per face node
 //             (conforming LLF, Kopriva's L2 mortar, the sparse IDP mortar flux
 //             of eq. interfaceflux_local), the Ranocha two-point fluxes once per
@@ -52,25 +52,27 @@ __device__ __forceinline__ int xcd_batch(int bid, int nb)
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
 }
 
-// launch geometry per degree: 128-thread blocks (two waves)
+// launch geometry per degree: one-wave blocks of 4 elements at N = 3 (the
+// phase barriers stay inside a wave and a late block holds less work), two-wave
+// blocks of 5 elements at N = 4 (25 nodes do not pack a wave)
 template <int N>
 struct Geo {
     static constexpr int n = N + 1, NN = n * n;
-    static constexpr int EPB = 128 / NN;           // 8 for N = 3, 5 for N = 4
+    static constexpr int BS = N == 3 ? 64 : 128;   // block size
+    static constexpr int EPB = BS / NN;            // 4 for N = 3, 5 for N = 4
     static constexpr int NT = EPB * NN;            // active threads
-    static constexpr int BS = 128;                 // block size
     static constexpr int NFN = 4 * n;              // face nodes per element
     static constexpr int NPL = n * (n - 1) / 2;    // node pairs per line
     static constexpr int NP = 2 * n * NPL;         // node pairs per element
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
     // padded LDS strides: a half wave covers two N = 3 elements; an element's
     // stride of 16 (mod 32) doubles puts the second one on the other 32 banks.
-    // sU stays unpadded at N = 3: the block then needs at most 32000 bytes, and
-    // five blocks fit the 160 KiB of a compute unit instead of four
+    // sU and sFace stay unpadded at N = 3: a block then needs 15616 bytes and
+    // ten blocks fit a compute unit (measured: with 15872 bytes only nine do)
     static constexpr int PU = N == 3 ? NN : NN + 1;        // sU variable stride
     static constexpr int PR = N == 3 ? NN + 2 : NN + 1;    // sR variable stride
     static constexpr int PP = N == 3 ? NP + 4 : NP;        // sPair variable stride
-    static constexpr int PFN = N == 3 ? NFN + 4 : NFN + 2;  // sFace variable stride
+    static constexpr int PFN = N == 3 ? NFN : NFN + 2;    // sFace variable stride
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
@@ -323,6 +325,7 @@ struct StageArgs {
     double cfl;
     double* dt_out;
     const int* fnbr;
+    const int* fnbr2;
     const int* fmort;
     const int* mort;
     const double* h;
@@ -382,7 +385,7 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
     } while (0)
 
 template <int N, int MODE, bool MIXED>
-__global__ __launch_bounds__(128) void k_stage(StageArgs A)
+__global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
 {
     using G = Geo<N>;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
@@ -413,8 +416,9 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     int fcode[4] = {-1, -1, -1, -1};
     const bool fnode = act && q < NFN;       // this lane also evaluates one face node
     const int ff = q / n, fk = q - (q / n) * n;  // its face and position
-    int fcode_f = -1, fnb = 0;
+    int fcode_f = -1, fnb = 0, fnb2 = -1;
     double onb[4];  // conforming neighbour state across face ff at position fk
+    double us1[4];  // large side: the second small element's trace at position fk
     double un4[4] = {0, 0, 0, 0};  // u^n of this node for the SSP combination
     bool blk_mortar = false;
     const double dtpart =
@@ -423,7 +427,10 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
         // issue the independent global loads first
 #pragma unroll
         for (int f = 0; f < 4; ++f) fcode[f] = A.fmort[e * 4 + f];
-        if (fnode) fnb = A.fnbr[e * 4 + ff];
+        if (fnode) {
+            fnb = A.fnbr[e * 4 + ff];
+            fnb2 = A.fnbr2[e * 4 + ff];
+        }
         if (MODE == MODE_STAGE && A.a != 0.0) load_u<N>(A.un, e, q, un4);
         NodeP me;
         load_node<N>(A.uin, e, q, me, g);
@@ -448,6 +455,16 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             if (fcode_f < 0) {
                 load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
             } else if (!fm_small(fcode_f)) {
+                // large side: both small traces at position fk, kept in
+                // registers for the mortar-node fluxes and staged for the
+                // sparse low-order pairs of the other positions
+                load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
+                load_u<N>(A.uin, fnb2, face_q<N>(ff ^ 1, fk), us1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    sPair[le][v][MB + (ff * 2 + 0) * n + fk] = onb[v];
+                    sPair[le][v][MB + (ff * 2 + 1) * n + fk] = us1[v];
+                }
                 blk_mortar = true;
             } else {
                 // small side: stage the large face trace for the interpolation
@@ -493,10 +510,13 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
             for (int v = 0; v < 4; ++v) sFace[le][v][q] = W * F[v];
         } else if (!fm_small(fcode_f)) {
             // large side: mortar-node fluxes at position fk of both halves
-            const int S = fm_mortar(fcode_f);
+            // (kept in registers until every lane has read the staged small
+            // traces), and the sparse low-order pairs of this node
             for (int hh = 0; hh < 2; ++hh) {
                 NodeP ui, us;
-                load_node<N>(A.uin, A.mort[S * 4 + 2 + hh], face_q<N>(ff ^ 1, fk), us, g);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) us.u[v] = hh == 0 ? onb[v] : us1[v];
+                make_node(us, g);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     if (MIXED) {
@@ -515,8 +535,31 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 double F[4];
                 mortar_flux(dff, lowf, ui, us, F);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) sPair[le][v][MB + (ff * 2 + hh) * n + fk] = F[v];
+                for (int v = 0; v < 4; ++v) {
+                    if (hh == 0) onb[v] = F[v];
+                    else us1[v] = F[v];
+                }
             }
+            double lo[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                for (int l = 0; l < n; ++l) {
+                    const double wt = tb.Wt[fk][hh * n + l];
+                    if (wt == 0.0) continue;
+                    NodeP us;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) us.u[v] = sPair[le][v][MB + (ff * 2 + hh) * n + l];
+                    make_node(us, g);
+                    double Gf[4];
+                    if (lowf) llf_dir(dff, own, us, Gf);
+                    else llf_dir(dff, us, own, Gf);
+                    const double W = sgf * wt * hff * 0.5;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
+                }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sFace[le][v][q] = lo[v];
         } else {
             // small side: interpolate the large face, LLF on the mortar = this face
             const int hh = fm_half(fcode_f);
@@ -567,12 +610,19 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
     }
     if (any_mortar) {
         __syncthreads();
-        // ---- phase 3: large sides project the mortar fluxes; sparse low order ----
-        if (fnode && fcode_f >= 0 && !fm_small(fcode_f)) {
+        // ---- phase 3: large sides publish and project the mortar fluxes ----
+        const bool large = fnode && fcode_f >= 0 && !fm_small(fcode_f);
+        if (large) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sPair[le][v][MB + (ff * 2 + 0) * n + fk] = onb[v];
+                sPair[le][v][MB + (ff * 2 + 1) * n + fk] = us1[v];
+            }
+        }
+        __syncthreads();
+        if (large) {
             const int S = fm_mortar(fcode_f);
-            NodeP own;
-            LDS_NODE(own, face_q<N>(ff, fk));
-            double ho[4], lo[4] = {0, 0, 0, 0};
+            double ho[4];
 #pragma unroll 1
             for (int v = 0; v < 4; ++v) {
                 double acc = 0.0;
@@ -593,28 +643,9 @@ __global__ __launch_bounds__(128) void k_stage(StageArgs A)
                 }
                 ho[v] = sgf * tb.w[fk] * hff * 0.5 * acc;
             }
-            for (int hh = 0; hh < 2; ++hh) {
-                const int sm = A.mort[S * 4 + 2 + hh];
-                for (int l = 0; l < n; ++l) {
-                    const double wt = tb.Wt[fk][hh * n + l];
-                    if (wt == 0.0) continue;
-                    NodeP us;
-                    load_node<N>(A.uin, sm, face_q<N>(ff ^ 1, l), us, g);
-                    double Gf[4];
-                    if (lowf) llf_dir(dff, own, us, Gf);
-                    else llf_dir(dff, us, own, Gf);
-                    const double W = sgf * wt * hff * 0.5;
+            double* R = A.slot + (size_t)(S * 3 * n + fk) * kSlotW;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sFace[le][v][q] = lo[v];
-            {
-                double* R = A.slot + (size_t)(S * 3 * n + fk) * kSlotW;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) R[4 + v] = ho[v] - lo[v];
-            }
+            for (int v = 0; v < 4; ++v) R[4 + v] = ho[v] - sFace[le][v][q];
         }
         __syncthreads();
     }
@@ -957,6 +988,7 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
 struct DtArgs {
     const double* u;
     const int* fnbr;
+    const int* fnbr2;
     const int* fmort;
     const int* mort;
     const double* h;
@@ -973,13 +1005,15 @@ __device__ __forceinline__ double wave_speed(const NodeP& s, int d)
 }
 
 template <int N>
-__global__ __launch_bounds__(128) void k_dt(DtArgs A)
+__global__ __launch_bounds__(Geo<N>::BS) void k_dt(DtArgs A)
 {
     using G = Geo<N>;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     __shared__ double sL[EPB][2][NN];
     __shared__ double sF[EPB][NFN];
-    __shared__ double sRed[2];
+    __shared__ double sMl[EPB][8 * n];  // wave speeds across mortars, staged per position
+    constexpr int NW = G::BS / 64;  // waves per block
+    __shared__ double sRed[NW];
     const Tab<N>& tb = T<N>();
     const double g = A.gamma;
     const int tid = threadIdx.x;
@@ -990,7 +1024,7 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
     const bool fnode = act && idp && q < NFN;
     const int ff = q / n, fk = q - (q / n) * n, dff = ff >> 1;
     double hx = 1.0, hy = 1.0, lo_nb = 0.0;
-    int code = -1, nb = 0;
+    int code = -1, nb = 0, nb2 = -1;
     if (act) {
         NodeP me;
         load_node<N>(A.u, e, q, me, g);
@@ -1001,10 +1035,19 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
         if (fnode) {
             code = A.fmort[e * 4 + ff];
             nb = A.fnbr[e * 4 + ff];
-            if (code < 0) {
-                NodeP o;
-                load_node<N>(A.u, nb, face_q<N>(ff ^ 1, fk), o, g);
-                lo_nb = wave_speed(o, dff);
+            nb2 = A.fnbr2[e * 4 + ff];
+            NodeP o;
+            load_node<N>(A.u, nb, face_q<N>(ff ^ 1, fk), o, g);
+            lo_nb = wave_speed(o, dff);
+            if (code >= 0) {
+                // mortar: stage the wave speeds of the other side at position fk
+                // (large side: both small elements; small side: the large one)
+                sMl[le][(ff * 2) * n + fk] = lo_nb;
+                if (!fm_small(code)) {
+                    NodeP o2;
+                    load_node<N>(A.u, nb2, face_q<N>(ff ^ 1, fk), o2, g);
+                    sMl[le][(ff * 2 + 1) * n + fk] = wave_speed(o2, dff);
+                }
             }
         }
     }
@@ -1017,25 +1060,21 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
         if (code < 0) {
             sum = 2.0 * tb.w[fk] * hf * 0.25 * fmax(lm, lo_nb);
         } else if (!fm_small(code)) {
-            const int S = fm_mortar(code);
-            for (int hh = 0; hh < 2; ++hh) {
-                const int sm = A.mort[S * 4 + 2 + hh];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
                 for (int l = 0; l < n; ++l) {
                     const double wt = tb.Wt[fk][hh * n + l];
                     if (wt == 0.0) continue;
-                    NodeP o;
-                    load_node<N>(A.u, sm, face_q<N>(ff ^ 1, l), o, g);
-                    sum += 2.0 * wt * hf * 0.25 * fmax(lm, wave_speed(o, dff));
+                    sum += 2.0 * wt * hf * 0.25 * fmax(lm, sMl[le][(ff * 2 + hh) * n + l]);
                 }
-            }
         } else {
             const int hh = fm_half(code);
+#pragma unroll
             for (int j = 0; j < n; ++j) {
                 const double wt = tb.Wt[j][hh * n + fk];
                 if (wt == 0.0) continue;
-                NodeP o;
-                load_node<N>(A.u, nb, face_q<N>(ff ^ 1, j), o, g);
-                sum += 2.0 * wt * (2.0 * hf) * 0.25 * fmax(lm, wave_speed(o, dff));
+                sum += 2.0 * wt * (2.0 * hf) * 0.25 * fmax(lm, sMl[le][(ff * 2) * n + j]);
             }
         }
         sF[le][q] = sum;
@@ -1065,7 +1104,9 @@ __global__ __launch_bounds__(128) void k_dt(DtArgs A)
     if (tid == 0) {
         // non-negative doubles order like their bit patterns; NaN and zero
         // maxima are left out, as fmax would
-        const double m = fmax(sRed[0], sRed[1]);
+        double m = sRed[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) m = fmax(m, sRed[w]);
         if (m > 0.0)
             atomicMax(A.acc + (blockIdx.x % kDtSpread) * kDtStride,
                       (unsigned long long)__double_as_longlong(m));
@@ -1397,6 +1438,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.cfl = dt.cfl;
     A.dt_out = dt.dt_out;
     A.fnbr = m.fnbr;
+    A.fnbr2 = m.fnbr2;
     A.fmort = m.fmort;
     A.mort = m.mort;
     A.h = m.h;
@@ -1463,10 +1505,10 @@ int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st,
 int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, int mode,
               unsigned long long* acc, unsigned long long* other, hipStream_t s)
 {
-    const int nblocks = (m.E + 128 / ((N + 1) * (N + 1)) - 1) / (128 / ((N + 1) * (N + 1)));
     DtArgs A;
     A.u = u;
     A.fnbr = m.fnbr;
+    A.fnbr2 = m.fnbr2;
     A.fmort = m.fmort;
     A.mort = m.mort;
     A.h = m.h;
@@ -1475,8 +1517,10 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
     A.mode = mode;
     A.acc = acc;
     A.other = other;
-    if (N == 3) hipLaunchKernelGGL(k_dt<3>, dim3(nblocks), dim3(128), 0, s, A);
-    else if (N == 4) hipLaunchKernelGGL(k_dt<4>, dim3(nblocks), dim3(128), 0, s, A);
+    if (N == 3)
+        hipLaunchKernelGGL(k_dt<3>, dim3((m.E + Geo<3>::EPB - 1) / Geo<3>::EPB), dim3(Geo<3>::BS), 0, s, A);
+    else if (N == 4)
+        hipLaunchKernelGGL(k_dt<4>, dim3((m.E + Geo<4>::EPB - 1) / Geo<4>::EPB), dim3(Geo<4>::BS), 0, s, A);
     else return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
