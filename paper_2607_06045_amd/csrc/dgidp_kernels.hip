@@ -123,30 +123,30 @@ __device__ __forceinline__ double pressure(const double* u, double g)
     return (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) * frcp(u[0]));
 }
 
-// local Lax-Friedrichs flux in direction D between the low-side state L and the
-// high-side state R
-template <int D>
-__device__ __forceinline__ void llf(const NodeP& L, const NodeP& R, double* F)
+// local Lax-Friedrichs flux across a face (eq. FVmethod): 1/2 (f_n(u_L) + f_n(u_R)) -
+// 1/2 lambda (u_R - u_L), lambda = max(|v_n| + c) of the two states.
+// Normal direction d and side are run-time values (lanes of a wave hold
+// different faces): this element's state `own`, the other side's state `o`,
+// own_low = this element is on the low side.  Branch free, so a wave evaluates
+// one flux body whatever mix of faces its lanes hold.
+__device__ __forceinline__ void llf_face(int d, bool own_low, const NodeP& own, const NodeP& o,
+                                         double* F)
 {
-    const double vL = D == 0 ? L.v1 : L.v2, vR = D == 0 ? R.v1 : R.v2;
-    const double lam = fmax(fabs(vL) + L.c, fabs(vR) + R.c);
-    double fL[4], fR[4];
-    fL[0] = L.r * vL;
-    fL[1] = L.u[1] * vL + (D == 0 ? L.p : 0.0);
-    fL[2] = L.u[2] * vL + (D == 1 ? L.p : 0.0);
-    fL[3] = (L.u[3] + L.p) * vL;
-    fR[0] = R.r * vR;
-    fR[1] = R.u[1] * vR + (D == 0 ? R.p : 0.0);
-    fR[2] = R.u[2] * vR + (D == 1 ? R.p : 0.0);
-    fR[3] = (R.u[3] + R.p) * vR;
+    const bool dx = d == 0;
+    const double va = dx ? own.v1 : own.v2, vb = dx ? o.v1 : o.v2;
+    const double lam = fmax(fabs(va) + own.c, fabs(vb) + o.c);
+    const double hl = own_low ? 0.5 * lam : -0.5 * lam;
+    double fa[4], fb[4];
+    fa[0] = own.r * va;
+    fa[1] = own.u[1] * va + (dx ? own.p : 0.0);
+    fa[2] = own.u[2] * va + (dx ? 0.0 : own.p);
+    fa[3] = (own.u[3] + own.p) * va;
+    fb[0] = o.r * vb;
+    fb[1] = o.u[1] * vb + (dx ? o.p : 0.0);
+    fb[2] = o.u[2] * vb + (dx ? 0.0 : o.p);
+    fb[3] = (o.u[3] + o.p) * vb;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) F[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (R.u[v] - L.u[v]);
-}
-
-__device__ __forceinline__ void llf_dir(int d, const NodeP& L, const NodeP& R, double* F)
-{
-    if (d == 0) llf<0>(L, R, F);
-    else llf<1>(L, R, F);
+    for (int v = 0; v < 4; ++v) F[v] = 0.5 * (fa[v] + fb[v]) - hl * (o.u[v] - own.u[v]);
 }
 
 // LLF flux on a mortar node between the interpolated large-face state ui and
@@ -161,8 +161,7 @@ __device__ __forceinline__ void mortar_flux(int d, bool large_low, const NodeP& 
         F[0] = F[1] = F[2] = F[3] = nan;
         return;
     }
-    if (large_low) llf_dir(d, ui, us, F);
-    else llf_dir(d, us, ui, F);
+    llf_face(d, large_low, ui, us, F);
 }
 
 // logarithmic mean (x - y) / (ln x - ln y) and its reciprocal from precomputed
@@ -503,8 +502,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             for (int v = 0; v < 4; ++v) o.u[v] = onb[v];
             make_node(o, g);
             double F[4];
-            if (lowf) llf_dir(dff, own, o, F);
-            else llf_dir(dff, o, own, F);
+            llf_face(dff, lowf, own, o, F);
             const double W = sgf * tb.w[fk] * hff * 0.5;
 #pragma unroll
             for (int v = 0; v < 4; ++v) sFace[le][v][q] = W * F[v];
@@ -552,8 +550,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                     for (int v = 0; v < 4; ++v) us.u[v] = sPair[le][v][MB + (ff * 2 + hh) * n + l];
                     make_node(us, g);
                     double Gf[4];
-                    if (lowf) llf_dir(dff, own, us, Gf);
-                    else llf_dir(dff, us, own, Gf);
+                    llf_face(dff, lowf, own, us, Gf);
                     const double W = sgf * wt * hff * 0.5;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
@@ -592,8 +589,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                 for (int v = 0; v < 4; ++v) uj.u[v] = sPair[le][v][ff * n + j];
                 make_node(uj, g);
                 double Gf[4];
-                if (lowf) llf_dir(dff, own, uj, Gf);
-                else llf_dir(dff, uj, own, Gf);
+                llf_face(dff, lowf, own, uj, Gf);
                 const double W = sgf * wt * hff;  // wt * h_L / 2 with h_L = 2 h
 #pragma unroll
                 for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
@@ -723,7 +719,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             LDS_NODE(o, qn);
             LDS_NODE(me, q);
             double F[4];
-            llf_dir(d, me, o, F);
+            llf_face(d, true, me, o, F);
             const double hs = 0.5 * (d == 0 ? hy : hx), wl = tb.w[line];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
