@@ -197,13 +197,36 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         auto it = find.find(key_of(l, i, j));
         return it == find.end() ? -1 : it->second;
     };
-    // internal order: Morton order of the leaves on the finest grid
+    // internal order: Morton order of the leaves on the finest grid, cut into
+    // the eight contiguous ranges that the stage kernel hands to the eight
+    // XCDs; inside each range the leaves with a nonconforming face come first.
+    // A wave then holds either mortar elements (with their longer surface
+    // work) or none, and the longer waves start first on each XCD instead of
+    // ending the launch late.
     std::vector<std::pair<uint64_t, int>> ord((size_t)E);
     for (int64_t e = 0; e < E; ++e) {
         const int s = lmax - level[e];
         ord[e] = {morton((uint64_t)ix[e] << s, (uint64_t)iy[e] << s), (int)e};
     }
     std::sort(ord.begin(), ord.end());
+    {
+        const int64_t epb = stage_block_elems(N);
+        const int64_t nb = (E + epb - 1) / epb, q = nb >> 3, r = nb & 7;
+        int64_t g0 = 0;
+        for (int x = 0; x < 8; ++x) {
+            const int64_t gn = q + (x < r ? 1 : 0);
+            const int64_t lo = std::min<int64_t>(E, g0 * epb), hi = std::min<int64_t>(E, (g0 + gn) * epb);
+            std::stable_partition(ord.begin() + lo, ord.begin() + hi, [&](const std::pair<uint64_t, int>& o) {
+                const int e = o.second;
+                for (int f = 0; f < 4; ++f) {
+                    const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
+                    if (lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy) < 0) return true;
+                }
+                return false;
+            });
+            g0 += gn;
+        }
+    }
     std::vector<int> inv(E);
     hm.perm.assign(E, 0);
     for (int64_t i = 0; i < E; ++i) {

@@ -60,6 +60,7 @@ struct Geo {
     static constexpr int n = N + 1, NN = n * n;
     static constexpr int BS = N == 3 ? 64 : 128;   // block size
     static constexpr int EPB = BS / NN;            // 4 for N = 3, 5 for N = 4
+    static_assert(EPB == stage_block_elems(N), "host element order assumes this block size");
     static constexpr int NT = EPB * NN;            // active threads
     static constexpr int NFN = 4 * n;              // face nodes per element
     static constexpr int NPL = n * (n - 1) / 2;    // node pairs per line
