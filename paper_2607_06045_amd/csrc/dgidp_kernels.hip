@@ -68,12 +68,13 @@ struct Geo {
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
     // padded LDS strides: a half wave covers two N = 3 elements; an element's
     // stride of 16 (mod 32) doubles puts the second one on the other 32 banks.
-    // sU and sFace stay unpadded at N = 3: a block then needs 15616 bytes and
-    // ten blocks fit a compute unit (measured: with 15872 bytes only nine do)
+    // At N = 3 the arrays stay unpadded: a block then needs 14592 bytes and
+    // ten blocks fit a compute unit (measured: with 15616 bytes only nine do);
+    // the tenth wave is worth more than the bank conflicts the padding saved.
     static constexpr int PU = N == 3 ? NN : NN + 1;        // sU variable stride
-    static constexpr int PR = N == 3 ? NN + 2 : NN + 1;    // sR variable stride
-    static constexpr int PP = N == 3 ? NP + 4 : NP;        // sPair variable stride
-    static constexpr int PFN = N == 3 ? NFN : NFN + 2;    // sFace variable stride
+    static constexpr int PR = N == 3 ? NN : NN + 1;        // sR variable stride
+    static constexpr int PP = NP;                          // sPair variable stride
+    static constexpr int PFN = N == 3 ? NFN : NFN + 2;     // sFace variable stride
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
@@ -102,6 +103,18 @@ __device__ __forceinline__ double frcp(double y)
     r = fma(r, e, r);
     e = fma(-y, r, 1.0);
     return fma(r, e, r);
+}
+
+// t[k] for a lane-dependent k < M from lane-uniform table entries: the entries
+// come through the scalar cache and the choice is made with selects, instead
+// of one vector memory round trip per lane-indexed table read
+template <int M>
+__device__ __forceinline__ double pick(const double (&t)[M], int k)
+{
+    double r = t[0];
+#pragma unroll
+    for (int i = 1; i < M; ++i) r = k == i ? t[i] : r;
+    return r;
 }
 
 struct NodeP {
@@ -423,6 +436,18 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     bool blk_mortar = false;
     const double dtpart =
         A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
+    // Sbar of this thread's volume pairs, loaded with the state so that the
+    // lane-indexed table reads do not wait in the pair phase; the empty asm
+    // keeps them in registers (no reload at the use)
+    double spair[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int p = q + i * NN;
+        const int rem = p % (n * NPL), pi = rem % NPL;
+        const int lk = (int)((PCODE >> (6 * pi)) & 63ull);
+        spair[i] = act ? tb.S[lk & 7][lk >> 3] : 0.0;
+        asm volatile("" : "+v"(spair[i]));
+    }
     if (act) {
         // issue the independent global loads first
 #pragma unroll
@@ -504,7 +529,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             make_node(o, g);
             double F[4];
             llf_face(dff, lowf, own, o, F);
-            const double W = sgf * tb.w[fk] * hff * 0.5;
+            const double W = sgf * pick(tb.w, fk) * hff * 0.5;
 #pragma unroll
             for (int v = 0; v < 4; ++v) sFace[le][v][q] = W * F[v];
         } else if (!fm_small(fcode_f)) {
@@ -580,7 +605,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             double F[4], ho[4], lo[4] = {0, 0, 0, 0};
             mortar_flux(dff, !lowf, ui, own, F);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ho[v] = sgf * tb.w[fk] * hff * 0.5 * F[v];
+            for (int v = 0; v < 4; ++v) ho[v] = sgf * pick(tb.w, fk) * hff * 0.5 * F[v];
 #pragma unroll
             for (int j = 0; j < n; ++j) {
                 const double wt = tb.Wt[j][hh * n + fk];
@@ -638,7 +663,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                         for (int l = 0; l < n; ++l)
                             acc += tb.P[hh][fk][l] * sPair[le][v][MB + (ff * 2 + hh) * n + l];
                 }
-                ho[v] = sgf * tb.w[fk] * hff * 0.5 * acc;
+                ho[v] = sgf * pick(tb.w, fk) * hff * 0.5 * acc;
             }
             double* R = A.slot + (size_t)(S * 3 * n + fk) * kSlotW;
 #pragma unroll
@@ -658,7 +683,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             const int l = lk & 7, k = lk >> 3;
             const int ql = d == 0 ? line * n + l : l * n + line;
             const int qk = d == 0 ? line * n + k : k * n + line;
-            const double scale = tb.S[l][k] * 0.5 * (d == 0 ? hy : hx);
+            const double scale = spair[i] * 0.5 * (d == 0 ? hy : hx);
             double L[8], R[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -721,7 +746,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             LDS_NODE(me, q);
             double F[4];
             llf_face(d, true, me, o, F);
-            const double hs = 0.5 * (d == 0 ? hy : hx), wl = tb.w[line];
+            const double hs = 0.5 * (d == 0 ? hy : hx), wl = pick(tb.w, line);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 FVo[d][v] = hs * F[v];
@@ -759,14 +784,15 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     int slot0 = -1, slot1 = -1, nmf = 0;
     double im = 1.0;  // 1 / m_i
     if (act) {
-        im = 4.0 / (hx * hy) * tb.winv[a] * tb.winv[b];
+        im = 4.0 / (hx * hy) * pick(tb.winv, a) * pick(tb.winv, b);
+        const double wa = pick(tb.w, a), wb = pick(tb.w, b);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double r = 0.0;
-            if (a > 0) r += tb.w[b] * sPair[le][v][fxl];
-            if (a < N) r -= tb.w[b] * sPair[le][v][fxr];
-            if (b > 0) r += tb.w[a] * sPair[le][v][fyb];
-            if (b < N) r -= tb.w[a] * sPair[le][v][fyt];
+            if (a > 0) r += wb * sPair[le][v][fxl];
+            if (a < N) r -= wb * sPair[le][v][fxr];
+            if (b > 0) r += wa * sPair[le][v][fyb];
+            if (b < N) r -= wa * sPair[le][v][fyt];
             RLO[v] = r;
         }
 #pragma unroll
@@ -1055,7 +1081,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_dt(DtArgs A)
         const double lm = sL[le][dff][face_q<N>(ff, fk)];
         double sum = 0.0;
         if (code < 0) {
-            sum = 2.0 * tb.w[fk] * hf * 0.25 * fmax(lm, lo_nb);
+            sum = 2.0 * pick(tb.w, fk) * hf * 0.25 * fmax(lm, lo_nb);
         } else if (!fm_small(code)) {
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh)
@@ -1084,15 +1110,16 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_dt(DtArgs A)
             s = (N + 1) * (lx / hx + ly / hy);
         } else {
             double sum = 0.0;
-            if (a > 0) sum += 2.0 * tb.w[b] * hy * 0.25 * fmax(lx, sL[le][0][q - 1]);
-            if (a < N) sum += 2.0 * tb.w[b] * hy * 0.25 * fmax(lx, sL[le][0][q + 1]);
-            if (b > 0) sum += 2.0 * tb.w[a] * hx * 0.25 * fmax(ly, sL[le][1][q - n]);
-            if (b < N) sum += 2.0 * tb.w[a] * hx * 0.25 * fmax(ly, sL[le][1][q + n]);
+            const double wa = pick(tb.w, a), wb = pick(tb.w, b);
+            if (a > 0) sum += 2.0 * wb * hy * 0.25 * fmax(lx, sL[le][0][q - 1]);
+            if (a < N) sum += 2.0 * wb * hy * 0.25 * fmax(lx, sL[le][0][q + 1]);
+            if (b > 0) sum += 2.0 * wa * hx * 0.25 * fmax(ly, sL[le][1][q - n]);
+            if (b < N) sum += 2.0 * wa * hx * 0.25 * fmax(ly, sL[le][1][q + n]);
             if (a == 0) sum += sF[le][0 * n + b];
             if (a == N) sum += sF[le][1 * n + b];
             if (b == 0) sum += sF[le][2 * n + a];
             if (b == N) sum += sF[le][3 * n + a];
-            s = sum * 4.0 / (hx * hy) * tb.winv[a] * tb.winv[b];
+            s = sum * 4.0 / (hx * hy) * pick(tb.winv, a) * pick(tb.winv, b);
         }
     }
     s = wave_max(s);
