@@ -68,13 +68,13 @@ struct Geo {
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
     // padded LDS strides: a half wave covers two N = 3 elements; an element's
     // stride of 16 (mod 32) doubles puts the second one on the other 32 banks.
-    // At N = 3 the arrays stay unpadded: a block then needs 14592 bytes and
-    // ten blocks fit a compute unit (measured: with 15616 bytes only nine do);
-    // the tenth wave is worth more than the bank conflicts the padding saved.
+    // At N = 3 the arrays stay unpadded: a block then needs 12544 bytes and
+    // twelve blocks fit a compute unit (measured: with 15616 bytes only nine
+    // do); the extra waves are worth more than the bank conflicts the padding
+    // saved.
     static constexpr int PU = N == 3 ? NN : NN + 1;        // sU variable stride
     static constexpr int PR = N == 3 ? NN : NN + 1;        // sR variable stride
     static constexpr int PP = NP;                          // sPair variable stride
-    static constexpr int PFN = N == 3 ? NFN : NFN + 2;     // sFace variable stride
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
@@ -406,6 +406,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     static_assert(NP % NN == 0, "pair split");
     static_assert(G::PP >= 2 * NF, "subcell face buffers reuse the pair buffer");
     static_assert(G::PP >= 12 * n, "mortar buffers reuse the pair buffer");
+    static_assert(G::PU >= NFN, "surface terms reuse the state buffer");
     constexpr int MB = 4 * n;  // offset of the mortar-node fluxes in the pair buffer
     constexpr unsigned long long PCODE = pair_code<N>();
 
@@ -413,7 +414,6 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     __shared__ double sU[EPB][4][G::PU];
     __shared__ double sR[EPB][8][G::PR];     // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
     __shared__ double sPair[EPB][4][G::PP];  // pair fluxes; later FV and A of the subcell faces
-    __shared__ double sFace[EPB][4][G::PFN]; // per face node: low-order surface term
     // node factors of the volume limiter reuse the first row of sR (free after phase 5)
 #define sTh(qq) sR[le][0][qq]
 
@@ -433,6 +433,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     double onb[4];  // conforming neighbour state across face ff at position fk
     double us1[4];  // large side: the second small element's trace at position fk
     double un4[4] = {0, 0, 0, 0};  // u^n of this node for the SSP combination
+    double u0[4] = {0, 0, 0, 0};   // this node's state (uin)
+    // the low-order surface term of this lane's face node, kept in registers
+    // until phase 5 frees sU, which then carries it to the node's own thread
+    double fterm[4] = {0, 0, 0, 0};
     bool blk_mortar = false;
     const double dtpart =
         A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
@@ -462,7 +466,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
         hx = A.h[2 * e];
         hy = A.h[2 * e + 1];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sU[le][v][q] = me.u[v];
+        for (int v = 0; v < 4; ++v) {
+            sU[le][v][q] = me.u[v];
+            u0[v] = me.u[v];
+        }
         // the logarithms feed only the two-point volume fluxes: FP32 in the
         // mixed mode (exactly representable in the FP64 slots)
         const double lr = MIXED ? (double)__logf((float)me.r) : log(me.r);
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             llf_face(dff, lowf, own, o, F);
             const double W = sgf * pick(tb.w, fk) * hff * 0.5;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sFace[le][v][q] = W * F[v];
+            for (int v = 0; v < 4; ++v) fterm[v] = W * F[v];
         } else if (!fm_small(fcode_f)) {
             // large side: mortar-node fluxes at position fk of both halves
             // (kept in registers until every lane has read the staged small
@@ -582,7 +589,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                     for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
                 }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sFace[le][v][q] = lo[v];
+            for (int v = 0; v < 4; ++v) fterm[v] = lo[v];
         } else {
             // small side: interpolate the large face, LLF on the mortar = this face
             const int hh = fm_half(fcode_f);
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                 for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sFace[le][v][q] = lo[v];
+            for (int v = 0; v < 4; ++v) fterm[v] = lo[v];
             {
                 const int S = fm_mortar(fcode_f);
                 double* R = A.slot + (size_t)(S * 3 * n + n + fm_half(fcode_f) * n + fk) * kSlotW;
@@ -667,7 +674,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             }
             double* R = A.slot + (size_t)(S * 3 * n + fk) * kSlotW;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) R[4 + v] = ho[v] - sFace[le][v][q];
+            for (int v = 0; v < 4; ++v) R[4 + v] = ho[v] - fterm[v];
         }
         __syncthreads();
     }
@@ -773,6 +780,11 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             }
         }
     }
+    // sU is no longer read: it now carries the surface terms of the face nodes
+    if (fnode) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sU[le][v][q] = fterm[v];
+    }
     __syncthreads();
 
     // ---- phase 6: low-order residual, bounds, node factors ----
@@ -800,7 +812,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             if (!onf[f]) continue;
             const int fq = fnq[f];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) RLO[v] += sFace[le][v][fq];
+            for (int v = 0; v < 4; ++v) RLO[v] += sU[le][v][fq];
             const int code = fcode[f];
             if (code >= 0) {
                 const int S = fm_mortar(code), k = f < 2 ? b : a;
@@ -842,7 +854,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     unsigned long long inad = 0;
     if (act) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) uFV[v] = sU[le][v][q] + dtm * RLO[v];
+        for (int v = 0; v < 4; ++v) uFV[v] = u0[v] + dtm * RLO[v];
         const double pFV = pressure(uFV, g);
         if (!(uFV[0] > 0.0) || !(pFV > 0.0)) inad = 1;
         rmin = A.beta * uFV[0];
