@@ -140,6 +140,12 @@ int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s);
  * the start of the step.  dt_used and s may be NULL (then nothing is copied to
  * the host and the call only enqueues work). */
 int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s);
+/* enable != 0: enqueue-only steps (dt_used and s both NULL) replay a HIP graph
+ * of the step's kernels, captured on first use per cfl (and per internal
+ * time-step accumulator); results are identical to kernel-by-kernel launches.
+ * Default: disabled (on the 22k-element blast a replayed step took 107 us
+ * against 102 us for direct launches). */
+int dgidp_set_graphs(dgidp_ctx* ctx, int enable);
 /* Same with a given dt (used to land exactly on an end time). */
 int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s);
 

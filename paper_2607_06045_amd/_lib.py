@@ -87,6 +87,7 @@ _SIGS = {
     "dgidp_mesh_download": (_i, [_vp, _vp, _vp, _vp]),
     "dgidp_amr_flags": (_i, [ctypes.c_int64, _vp, _vp, _i, _i, ctypes.c_float, _i,
                              ctypes.c_float, _vp]),
+    "dgidp_set_graphs": (_i, [_vp, _i]),
     "dgidp_indicator": (_i, [_vp, _i, _vp, _i]),
     "dgidp_features": (_i, [_vp, _vp, _i]),
     "dgidp_mlp_set_weights": (_i, [_vp, _vp]),
@@ -282,6 +283,10 @@ class Solver:
         self._check(_lib.dgidp_step_dt(self._h, dt, ctypes.byref(st) if stats else None),
                     "dgidp_step_dt")
         return st.to_dict() if stats else None
+
+    def set_graphs(self, enable):
+        """Replay enqueue-only steps from a captured HIP graph (default) or not."""
+        self._check(_lib.dgidp_set_graphs(self._h, int(bool(enable))), "dgidp_set_graphs")
 
     def time_kernels(self, reps=50):
         """Mean ms per launch of (stage kernel, mortar kernel, dt kernel), HIP events."""

@@ -40,6 +40,12 @@ struct dgidp_ctx {
     DevStats* stats = nullptr;
     unsigned long long* bad = nullptr;
     MlpState* mlp = nullptr;       // learned indicator, created on first use
+    // enqueue-only SSP-RK3 steps may replay a captured graph, one per dt
+    // accumulator; off by default (measured slower than direct launches here)
+    bool use_graphs = false;
+    hipStream_t cap = nullptr;     // capture stream
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    double gcfl[2] = {0.0, 0.0};
     float* ind_buf = nullptr;      // [E] indicator / [E*16] features staging
     size_t ind_cap = 0;
     bool has_state = false;
@@ -67,8 +73,17 @@ void dfree(T*& p)
     p = nullptr;
 }
 
+void drop_graphs(dgidp_ctx* c)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+        c->gexec[i] = nullptr;
+    }
+}
+
 void free_mesh(dgidp_ctx* c)
 {
+    drop_graphs(c);
     dfree(c->dm.fnbr);
     dfree(c->dm.fnbr2);
     dfree(c->dm.fmort);
@@ -401,6 +416,7 @@ void dgidp_destroy(dgidp_ctx* ctx)
     dfree(ctx->acc);
     dfree(ctx->ind_buf);
     if (ctx->mlp) mlp_destroy(ctx->mlp);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     dfree(ctx->stats);
     dfree(ctx->bad);
     delete ctx;
@@ -669,10 +685,63 @@ static int ssprk3(dgidp_ctx* ctx, dgidp_stats* s, const DtSource& first_dt)
     return 0;
 }
 
+// record one enqueue-only step (dt kernel and three stages) for accumulator
+// slot `slot` into a graph; nothing runs during the capture
+static int capture_step(dgidp_ctx* ctx, double cfl, int slot)
+{
+    if (!ctx->cap && hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
+        ctx->cap = nullptr;
+        return -1;
+    }
+    if (ctx->gexec[slot]) (void)hipGraphExecDestroy(ctx->gexec[slot]);
+    ctx->gexec[slot] = nullptr;
+    hipStream_t keep = ctx->stream;
+    ctx->stream = ctx->cap;
+    ctx->acc_slot = slot;
+    int rc = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) == hipSuccess ? 0 : -1;
+    if (!rc) {
+        DtSource src;
+        rc = enqueue_dt(ctx, cfl, ctx->p.dt_mode, &src);
+        if (!rc) rc = ssprk3(ctx, nullptr, src);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+        if (!rc && e == hipSuccess && g &&
+            hipGraphInstantiate(&ctx->gexec[slot], g, nullptr, nullptr, 0) == hipSuccess)
+            ctx->gcfl[slot] = cfl;
+        else
+            rc = -1;
+        if (g) (void)hipGraphDestroy(g);
+    }
+    ctx->stream = keep;
+    ctx->acc_slot = slot;
+    if (rc) {
+        ctx->gexec[slot] = nullptr;
+        (void)hipGetLastError();
+    }
+    return rc;
+}
+
+int dgidp_set_graphs(dgidp_ctx* ctx, int enable)
+{
+    if (!ctx) return DGIDP_E_INVALID_ARG;
+    ctx->use_graphs = enable != 0;
+    if (!ctx->use_graphs) drop_graphs(ctx);
+    return 0;
+}
+
 int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s)
 {
     if (!ctx || !(cfl > 0)) return DGIDP_E_INVALID_ARG;
     if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    if (!dt_used && !s && ctx->use_graphs) {
+        const int slot = ctx->acc_slot;
+        if ((ctx->gexec[slot] && ctx->gcfl[slot] == cfl) || capture_step(ctx, cfl, slot) == 0) {
+            HIPCHK(hipGraphLaunch(ctx->gexec[slot], ctx->stream));
+            ctx->acc_slot ^= 1;
+            return 0;
+        }
+        ctx->use_graphs = false;  // capture not available: launch kernel by kernel
+    }
     DevStats* st = s ? ctx->stats : nullptr;
     if (st && launch_stats_reset(st, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
     DtSource src;

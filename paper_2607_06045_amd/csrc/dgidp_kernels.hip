@@ -1039,10 +1039,18 @@ __device__ __forceinline__ double wave_speed(const NodeP& s, int d)
     return fabs(d == 0 ? s.v1 : s.v2) + s.c;
 }
 
+// the dt kernel: 256-thread blocks (16 elements at N = 3, 10 at N = 4), fewer
+// blocks and so fewer atomics than the stage kernel's geometry
 template <int N>
-__global__ __launch_bounds__(Geo<N>::BS) void k_dt(DtArgs A)
+struct DtGeo {
+    static constexpr int n = N + 1, NN = n * n, NFN = 4 * n;
+    static constexpr int BS = 256, EPB = BS / NN, NT = EPB * NN;
+};
+
+template <int N>
+__global__ __launch_bounds__(256) void k_dt(DtArgs A)
 {
-    using G = Geo<N>;
+    using G = DtGeo<N>;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     __shared__ double sL[EPB][2][NN];
     __shared__ double sF[EPB][NFN];
@@ -1061,6 +1069,11 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_dt(DtArgs A)
     double hx = 1.0, hy = 1.0, lo_nb = 0.0;
     int code = -1, nb = 0, nb2 = -1;
     if (act) {
+        if (fnode) {  // face tables first: the neighbour loads depend on them
+            code = A.fmort[e * 4 + ff];
+            nb = A.fnbr[e * 4 + ff];
+            nb2 = A.fnbr2[e * 4 + ff];
+        }
         NodeP me;
         load_node<N>(A.u, e, q, me, g);
         hx = A.h[2 * e];
@@ -1068,9 +1081,6 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_dt(DtArgs A)
         sL[le][0][q] = wave_speed(me, 0);
         sL[le][1][q] = wave_speed(me, 1);
         if (fnode) {
-            code = A.fmort[e * 4 + ff];
-            nb = A.fnbr[e * 4 + ff];
-            nb2 = A.fnbr2[e * 4 + ff];
             NodeP o;
             load_node<N>(A.u, nb, face_q<N>(ff ^ 1, fk), o, g);
             lo_nb = wave_speed(o, dff);
@@ -1554,9 +1564,9 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
     A.acc = acc;
     A.other = other;
     if (N == 3)
-        hipLaunchKernelGGL(k_dt<3>, dim3((m.E + Geo<3>::EPB - 1) / Geo<3>::EPB), dim3(Geo<3>::BS), 0, s, A);
+        hipLaunchKernelGGL(k_dt<3>, dim3((m.E + DtGeo<3>::EPB - 1) / DtGeo<3>::EPB), dim3(256), 0, s, A);
     else if (N == 4)
-        hipLaunchKernelGGL(k_dt<4>, dim3((m.E + Geo<4>::EPB - 1) / Geo<4>::EPB), dim3(Geo<4>::BS), 0, s, A);
+        hipLaunchKernelGGL(k_dt<4>, dim3((m.E + DtGeo<4>::EPB - 1) / DtGeo<4>::EPB), dim3(256), 0, s, A);
     else return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
