@@ -36,7 +36,7 @@ python3 -m paper_2607_06045_amd.profiling stats --csv "$STATS" \
     --title "kernel durations, bench.py workload (Sedov blast, 22,156 leaves, N=3, FP64, 20 steps + kernel timing)" \
     --command "$CMD" || exit 1
 python3 -m paper_2607_06045_amd.profiling traffic --fetch "$OUT/fetch" --write "$OUT/write" \
-    --copy-fetch "$OUT/copyfetch" --copy-write "$OUT/copywrite" --copy-mib 512 --kernel k_stage \
+    --copy-fetch "$OUT/copyfetch" --copy-write "$OUT/copywrite" --copy-mib 512 --kernel "k_stage<3, 0, false>" \
     --workload "Sedov blast, 22,156 leaves, N=3, FP64; mean over the three stage configurations" \
     --dofs 354496 --algorithmic-bytes-per-node 85.33333333333333 \
     --out "$OUT/summary/traffic_k_stage_blast22k.json" --command "$CMD" || exit 1
