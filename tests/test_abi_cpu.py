@@ -96,3 +96,24 @@ def test_mesh_validate_errors():
         P.validate_mesh(3, np.r_[lv, 1], np.r_[ix, 0], np.r_[iy, 0], 2, 2)
     with pytest.raises(P.DgidpError, match="UNSUPPORTED_N"):
         P.validate_mesh(7, lv, ix, iy, 2, 2)
+    # empty leaf list, empty root grid
+    e8, e32 = np.zeros(0, np.int8), np.zeros(0, np.int32)
+    with pytest.raises(P.DgidpError, match="INVALID_ARG"):
+        P.validate_mesh(3, e8, e32, e32, 2, 2)
+    with pytest.raises(P.DgidpError, match="INVALID_ARG"):
+        P.validate_mesh(3, lv, ix, iy, 0, 2)
+
+
+def test_mesh_validate_degenerate_meshes(oracle):
+    """One leaf that is its own neighbour on every face (periodic 1 x 1 root),
+    a 1 x 2 root, and a refined 1 x 1 root whose mortars wrap around: valid,
+    and the library agrees with the oracle on the mortar count."""
+    import paper_2607_06045_amd as P
+    from workloads.meshes import to_spec
+    cases = [to_spec((0.0, 0.0, 1.0, 1.0, 1, 1), {(0, 0, 0)}),
+             to_spec((0.0, 0.0, 2.0, 1.0, 2, 1), {(0, 0, 0), (0, 1, 0)}),
+             to_spec((0.0, 0.0, 1.0, 1.0, 1, 1),
+                     {(1, 0, 0), (1, 1, 0), (1, 0, 1), (2, 2, 2), (2, 3, 2), (2, 2, 3), (2, 3, 3)})]
+    for spec in cases:
+        M, _ = P.validate_mesh(3, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
+        assert M == oracle.Mesh(3, *spec.args()).M

@@ -218,3 +218,45 @@ def test_graph_replay_matches_eager():
         out.append(s.download())
     print(f"graph vs eager: max |diff| {np.abs(out[0] - out[1]).max():.3e}", flush=True)
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_degenerate_meshes_parity(oracle, N):
+    """A single leaf that is its own neighbour across every face, a 1 x 2 root,
+    and a refined 1 x 1 root whose mortars wrap around the periodic box."""
+    from workloads.meshes import to_spec
+    cases = {"single": to_spec((0.0, 0.0, 1.0, 1.0, 1, 1), {(0, 0, 0)}),
+             "two": to_spec((0.0, 0.0, 2.0, 1.0, 2, 1), {(0, 0, 0), (0, 1, 0)}),
+             "wrap": to_spec((0.0, 0.0, 1.0, 1.0, 1, 1),
+                             {(1, 0, 0), (1, 1, 0), (1, 0, 1), (2, 2, 2), (2, 3, 2), (2, 2, 3), (2, 3, 3)})}
+    for name, spec in cases.items():
+        s, M = pair(oracle, spec, N)
+        x, y, m = M.geometry()
+        u = states.density_wave(x, y)
+        s.upload(u)
+        w0 = oracle.basis(N)[1][0]
+        for which in (0, 1):
+            err = rate_err(s.rhs(which), M.rhs(u, which), u, x, y, w0)
+            assert err < TOL, (name, which, err)
+        st = s.step(0.5)
+        c, _ = M.ssprk3(u, 0.5)
+        err = state_err(s.download(), c)
+        print(f"{name} N={N}: E={s.E} M={s.M} step err={err:.2e}", flush=True)
+        assert err < TOL and st["violations"] == 0
+
+
+def test_full_size_config5_n4(oracle):
+    """The largest workload (N = 4, 246,736 leaves, 6.2 M nodes, 5,536
+    mortars): one SSP-RK3 step compared with the oracle on every node."""
+    spec = config_mesh(5)
+    s, M = pair(oracle, spec, 4)
+    x, y, m = M.geometry()
+    u = states.config_state(5, x, y)
+    s.upload(u)
+    st = s.step(0.5)
+    c, sc = M.ssprk3(u, 0.5)
+    err = state_err(s.download(), c)
+    print(f"config5 N=4 E={s.E} M={s.M} err={err:.2e} dt gpu {st['dt']!r} oracle {sc['dt']!r}", flush=True)
+    assert err < TOL
+    assert st["violations"] == 0
+    assert abs(st["dt"] - sc["dt"]) <= 1e-14 * sc["dt"]
