@@ -1,0 +1,291 @@
+"""Evaluation runs of the two extensions on the GPU (synthetic workloads).
+
+  python -m paper_2607_06045_amd.evaluate mixed [--steps 200]
+      shear layer on the 59,392-leaf band mesh (N = 3) with dynamic AMR from
+      the modal indicator every 5 steps: the FP64 run chooses the refine /
+      coarsen flags, the mixed-precision run replays them, so both share every
+      mesh; reports per-variable relative L1 and max errors of the mixed state
+      against the FP64 state, bound violations, mass change and wall times
+
+  python -m paper_2607_06045_amd.evaluate learned [--steps 100]
+      trains the indicator network on the GPU from (features, modal indicator)
+      pairs of seeded blasts and shear layers, then runs the 22,156-leaf blast
+      with dynamic AMR every 5 steps twice, with the modal indicator and with
+      the network; reports the refine / keep / coarsen agreement of the two
+      indicators on the learned run's states, the element counts over time,
+      the L1 density difference of the two runs (base-cell means) and wall times
+
+Prints one JSON object.  All inputs are seeded and synthetic.
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _solver(P, spec, N=3, precision=None):
+    s = P.Solver(N, precision=P.FP64 if precision is None else precision)
+    s.set_mesh(*spec.args())
+    return s
+
+
+def base_means(s, u, w, base_level, nx0, ny0):
+    """Area-weighted means of every variable on the cells of the base level
+    (each leaf lies in one base cell), [4, ny0 2^base, nx0 2^base]."""
+    lv, ix, iy = s.mesh()
+    shift = lv.astype(np.int64) - base_level
+    if (shift < 0).any():
+        raise ValueError("leaf coarser than the base level")
+    bx, by = ix >> shift, iy >> shift
+    W = np.outer(w, w) / 4.0
+    leaf_mean = (u * W).sum(axis=(2, 3))  # [E, 4]
+    area = 0.25 ** shift.astype(np.float64)  # in base-cell units
+    nxb, nyb = nx0 << base_level, ny0 << base_level
+    out = np.zeros((4, nyb, nxb))
+    for v in range(4):
+        np.add.at(out[v], (by, bx), leaf_mean[:, v] * area)
+    return out
+
+
+def adapt_run(P, spec, u_fn, steps, every, ctrl, indicator, precision=None, replay=None,
+              record=None, on_adapt=None, zs_eps=1e-10):
+    """Run with dynamic AMR.  indicator(s) -> per-leaf float array; ctrl is
+    (base, med, med_threshold, max, max_threshold); replay: list of flag arrays
+    to apply instead of the indicator's; record: list that receives the flags."""
+    import torch
+    s = _solver(P, spec, precision=precision)
+    x, y = s.node_coords()
+    s.upload(u_fn(x, y))
+    counts, viol, k = [], 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        if it % every == 0:
+            if replay is not None:
+                flags = replay[k]
+            else:
+                lv, _, _ = s.mesh()
+                flags = P.amr_flags(indicator(s), lv, *ctrl)
+            if on_adapt is not None:
+                on_adapt(s, flags)
+            if record is not None:
+                record.append(flags.copy())
+            k += 1
+            s.refine_coarsen(flags, zs_eps=zs_eps)
+            counts.append(s.E)
+            if k % 5 == 1:
+                log(f"  step {it}: {s.E} leaves")
+        st = s.step(0.5)
+        viol += st["violations"]
+    torch.cuda.synchronize()
+    return s, {"wall_s": time.perf_counter() - t0, "elements": counts, "violations": int(viol)}
+
+
+def run_mixed(steps):
+    import paper_2607_06045_amd as P
+    from workloads import states
+    from workloads.meshes import config_mesh
+    spec = config_mesh(3)
+    # levels relative to the 128 x 128 root grid (absolute levels 7 to 10)
+    ctrl = (0, 1, 0.01, 3, 0.1)
+    w = P.host_tables(3)["w"]
+    flags = []
+
+    def ind(s):
+        return s.indicator(P.IND_HENNEMANN)
+
+    def mass(s, absolute=False):
+        """sum_i m_i u_i per variable (or of |u_i|)"""
+        lv, _, _ = s.mesh()
+        u = s.download()
+        if absolute:
+            u = np.abs(u)
+        W = np.outer(w, w) / 4.0
+        h2 = (2.0 / (128 << lv.astype(np.int64))) ** 2
+        return ((u * W).sum(axis=(2, 3)) * h2[:, None]).sum(axis=0)
+
+    u_fn = lambda x, y: states.config_state(3, x, y)  # noqa: E731
+    log("FP64 run")
+    s64, r64 = adapt_run(P, spec, u_fn, steps, 5, ctrl, ind, record=flags)
+    log("mixed run")
+    smx, rmx = adapt_run(P, spec, u_fn, steps, 5, ctrl, ind, precision=P.MIXED, replay=flags)
+    a, b = s64.download(), smx.download()
+    m0 = _solver(P, spec)
+    x, y = m0.node_coords()
+    m0.upload(u_fn(x, y))
+    mass0, abs0 = mass(m0), mass(m0, True)
+    rel_l1 = np.abs(b - a).sum(axis=(0, 2, 3)) / np.abs(a).sum(axis=(0, 2, 3))
+    rel_max = np.abs(b - a).max(axis=(0, 2, 3)) / np.abs(a).max(axis=(0, 2, 3))
+    return {"case": "shear layer, 59,392-leaf band mesh, N=3, dynamic AMR every 5 steps (levels 7-10), "
+                    "mixed run replays the FP64 run's flags", "steps": steps,
+            "rel_l1_per_variable": rel_l1.tolist(), "rel_max_per_variable": rel_max.tolist(),
+            "violations": {"fp64": r64["violations"], "mixed": rmx["violations"]},
+            # |change of sum m u| / sum m |u|, per variable
+            "conservation_defect": {"fp64": (np.abs(mass(s64) - mass0) / abs0).tolist(),
+                                    "mixed": (np.abs(mass(smx) - mass0) / abs0).tolist()},
+            "elements_final": s64.E, "elements_max": max(r64["elements"]),
+            "wall_s": {"fp64": r64["wall_s"], "mixed": rmx["wall_s"]}}
+
+
+def training_data(P, blasts=3, shears=2, snaps=6, every=5, seed=0):
+    """(features, modal indicator) pairs on the GPU from seeded plain runs."""
+    import torch
+    from workloads import states
+    from workloads.meshes import config_mesh
+    from workloads.rng import uniform
+    X, Y = [], []
+    log("training data")
+    for k in range(blasts):
+        r = uniform(1000 + seed * 97 + k, np.arange(4, dtype=np.uint64))
+        E0, sig = 0.5 + 1.5 * r[0], 0.04 + 0.04 * r[1]
+        xc, yc = -0.2 + 0.4 * r[2], -0.2 + 0.4 * r[3]
+        s = _solver(P, config_mesh(2))
+        x, y = s.node_coords()
+        s.upload(states.sedov_gaussian(x, y, E0=E0, sigma=sig, xc=xc, yc=yc))
+        for i in range(snaps * every):
+            if i % every == 0:
+                X.append(s.features(device=True))
+                Y.append(s.indicator(P.IND_HENNEMANN, device=True))
+            s.step(0.5, stats=False)
+    for k in range(shears):
+        r = uniform(2000 + seed * 89 + k, np.arange(2, dtype=np.uint64))
+        s = _solver(P, config_mesh(3))
+        x, y = s.node_coords()
+        s.upload(states.shear_layer(x, y, seed=300 + k, amp=0.05 + 0.1 * r[1]))
+        for i in range(snaps * every):
+            if i % every == 0:
+                X.append(s.features(device=True))
+                Y.append(s.indicator(P.IND_HENNEMANN, device=True))
+            s.step(0.5, stats=False)
+    return torch.cat(X), torch.cat(Y)
+
+
+def he_uniform(seed):
+    """He-uniform weights and zero biases, in the library's parameter order
+    W1[64][16], b1, W2[64][64], b2, W3[64], b3."""
+    rng = np.random.default_rng(seed)
+
+    def weights(shape, fan_in):
+        lim = np.sqrt(6.0 / fan_in)
+        return rng.uniform(-lim, lim, shape).ravel()
+
+    parts = [weights((64, 16), 16), np.zeros(64), weights((64, 64), 64), np.zeros(64),
+             weights((64,), 64), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fit(P, X, Y, iters, batch=8192, lr=2e-3, seed=11):
+    """Adam on the GPU with the library's kernels; returns the context."""
+    import torch
+    net = P.Solver(3)
+    net.mlp_set_weights(he_uniform(seed))
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    for _ in range(iters):
+        idx = torch.randint(0, X.shape[0], (batch,), device="cuda", generator=g)
+        net.mlp_train_step(X[idx], Y[idx], lr)
+    return net
+
+
+def run_learned(steps, iters=3000, blasts=3, shears=2, snaps=6):
+    import torch
+    import paper_2607_06045_amd as P
+    from workloads import states
+    from workloads.meshes import config_mesh
+    t0 = time.perf_counter()
+    X, Y = training_data(P, blasts, shears, snaps)
+    n = X.shape[0]
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(0)).cuda()
+    ntr = int(0.9 * n)
+    Xtr, Ytr, Xva, Yva = X[perm[:ntr]], Y[perm[:ntr]], X[perm[ntr:]], Y[perm[ntr:]]
+    t_data = time.perf_counter() - t0
+    log(f"training on {ntr} samples")
+    t0 = time.perf_counter()
+    net = fit(P, Xtr, Ytr, iters)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    w = net.mlp_get_weights()
+    val_mse = ((net.mlp_forward(Xva) - Yva) ** 2).mean().item()
+    val_var = ((Yva - Yva.mean()) ** 2).mean().item()
+
+    spec = config_mesh(2)
+    # levels relative to the 64 x 64 root grid (absolute levels 6 to 9)
+    ctrl = (0, 2, 0.01, 3, 0.1)
+    u_fn = lambda x, y: states.config_state(2, x, y)  # noqa: E731
+
+    def plain(s):
+        return s.indicator(P.IND_HENNEMANN)
+
+    agree = {"n": 0, "same": 0, "refine_recall": [0, 0], "coarsen_recall": [0, 0]}
+
+    def learned(s):
+        if not getattr(s, "_w", False):
+            s.mlp_set_weights(w)
+            s._w = True
+        return s.indicator(P.IND_MLP)
+
+    def compare(s, flags):
+        lv, _, _ = s.mesh()
+        fp = P.amr_flags(plain(s), lv, *ctrl)
+        agree["n"] += len(fp)
+        agree["same"] += int((fp == flags).sum())
+        for key, val in (("refine_recall", 1), ("coarsen_recall", -1)):
+            agree[key][0] += int(((fp == val) & (flags == val)).sum())
+            agree[key][1] += int((fp == val).sum())
+
+    log("plain-indicator run")
+    s_p, r_p = adapt_run(P, spec, u_fn, steps, 5, ctrl, plain)
+    log("learned-indicator run")
+    s_l, r_l = adapt_run(P, spec, u_fn, steps, 5, ctrl, learned, on_adapt=compare)
+    wts = P.host_tables(3)["w"]
+    mp = base_means(s_p, s_p.download(), wts, 0, spec.nx0, spec.ny0)[0]
+    ml = base_means(s_l, s_l.download(), wts, 0, spec.nx0, spec.ny0)[0]
+    # indicator cost on the final state of the plain run
+    s_p.mlp_set_weights(w)
+    for kind in (P.IND_HENNEMANN, P.IND_MLP):
+        s_p.indicator(kind, device=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_ind = {}
+    for name, kind in (("modal", P.IND_HENNEMANN), ("network", P.IND_MLP)):
+        ev0.record()
+        for _ in range(20):
+            s_p.indicator(kind, device=True)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_ind[name] = ev0.elapsed_time(ev1) / 20
+    return {"case": "Sedov blast, 22,156-leaf start mesh, N=3, dynamic AMR every 5 steps (levels 6-9)",
+            "steps": steps,
+            "training": {"samples": n, "train": ntr, "iters": iters, "batch": 8192,
+                         "data_s": t_data, "train_s": t_train, "val_mse": val_mse,
+                         "val_target_variance": val_var},
+            "agreement": agree["same"] / max(agree["n"], 1),
+            "refine_recall": agree["refine_recall"][0] / max(agree["refine_recall"][1], 1),
+            "coarsen_recall": agree["coarsen_recall"][0] / max(agree["coarsen_recall"][1], 1),
+            "elements": {"plain": r_p["elements"], "learned": r_l["elements"]},
+            "violations": {"plain": r_p["violations"], "learned": r_l["violations"]},
+            "l1_density_base_cells": float(np.abs(mp - ml).mean()),
+            "l1_density_scale": float(np.abs(mp).mean()),
+            "wall_s": {"plain": r_p["wall_s"], "learned": r_l["wall_s"]},
+            "indicator_ms": t_ind}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["mixed", "learned"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--iters", type=int, default=3000)
+    a = ap.parse_args(argv)
+    if a.mode == "mixed":
+        out = run_mixed(a.steps or 200)
+    else:
+        out = run_learned(a.steps or 100, iters=a.iters)
+    print(json.dumps(out, default=float), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

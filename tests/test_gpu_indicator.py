@@ -182,3 +182,31 @@ def test_mlp_errors():
         s.mlp_set_weights(bad)
     with pytest.raises(P.DgidpError):
         s.mlp_train_step(np.zeros((4, 16), np.float32), np.zeros(4, np.float32), 0.0)
+
+
+def test_learned_indicator_drives_amr():
+    """The network trained on GPU-generated (features, modal indicator) pairs
+    drives dynamic AMR of the blast: its refine / keep / coarsen decisions agree
+    with the modal indicator's on the same states, and the run stays within
+    the positivity bounds."""
+    from paper_2607_06045_amd import evaluate as EV
+    r = EV.run_learned(steps=40, iters=1500, blasts=2, shears=1, snaps=4)
+    print({k: r[k] for k in ("agreement", "refine_recall", "coarsen_recall", "violations",
+                             "l1_density_base_cells", "indicator_ms")}, flush=True)
+    print("elements plain", r["elements"]["plain"], "learned", r["elements"]["learned"], flush=True)
+    assert r["agreement"] > 0.9 and r["refine_recall"] > 0.9
+    assert r["violations"] == {"plain": 0, "learned": 0}
+    assert r["l1_density_base_cells"] < 1e-2 * r["l1_density_scale"]
+
+
+def test_mixed_precision_amr_run():
+    """Shear layer with dynamic AMR (the mixed run replays the FP64 run's
+    flags): mixed against FP64 within 1e-5 relative L1 per variable, zero
+    violations, and both conserve to round-off across the adaptations."""
+    from paper_2607_06045_amd import evaluate as EV
+    r = EV.run_mixed(40)
+    print(r, flush=True)
+    assert max(r["rel_l1_per_variable"]) < 1e-5
+    assert r["violations"] == {"fp64": 0, "mixed": 0}
+    assert max(r["conservation_defect"]["fp64"]) < 1e-13
+    assert max(r["conservation_defect"]["mixed"]) < 1e-9
