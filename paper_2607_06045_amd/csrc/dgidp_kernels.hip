@@ -974,26 +974,38 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
     double asum = 0.0, thmin = 1.0;
     if (s < M * NS) {
         const int S = s / NS;
+        // every load that needs no other load first: slot factors of the
+        // mortar, this slot's record, its node and its partner
+        const double* R = slot + (size_t)s * kSlotW;
+        const int part = spart[s];
+        const int node = snode[s];
+        double rec[11];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) rec[i] = R[i];
         double t = 1.0;
+#pragma unroll
         for (int j = 0; j < NS; ++j) t = fmin(t, slot[((size_t)S * NS + j) * kSlotW + 8]);
+        const int e = node / NN, q = node - e * NN;
+        double uo[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) uo[v] = uout[((size_t)e * 4 + v) * NN + q];
         if (s == S * NS) {
             asum = 1.0 - t;
             thmin = t;
             nm = 1;
         }
-        const double* R = slot + (size_t)s * kSlotW;
-        const int part = spart[s];
         bool apply = true;
         double corr[4] = {0, 0, 0, 0};
         if (t != 0.0)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) corr[v] = t * R[4 + v];
+            for (int v = 0; v < 4; ++v) corr[v] = t * rec[4 + v];
         if (part >= 0) {
             const int S2 = part / NS;
             if (S2 < S) {
                 apply = false;  // the lower-numbered mortar applies both corrections
             } else {
                 double t2 = 1.0;
+#pragma unroll
                 for (int j = 0; j < NS; ++j) t2 = fmin(t2, slot[((size_t)S2 * NS + j) * kSlotW + 8]);
                 if (t2 != 0.0)
 #pragma unroll
@@ -1001,16 +1013,14 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
             }
         }
         if (apply) {
-            const int node = snode[s];
-            const int e = node / NN, q = node - e * NN;
             double w[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                uout[((size_t)e * 4 + v) * NN + q] += bcoef * corr[v];
-                w[v] = R[v] + corr[v];
+                uout[((size_t)e * 4 + v) * NN + q] = uo[v] + bcoef * corr[v];
+                w[v] = rec[v] + corr[v];
             }
             if (limiter != DGIDP_LIMIT_NONE &&
-                (w[0] < R[9] || pressure(w, gamma) < R[10] || w[0] != w[0]))
+                (w[0] < rec[9] || pressure(w, gamma) < rec[10] || w[0] != w[0]))
                 viol = 1;
         }
     }
