@@ -2,7 +2,7 @@
 
 One step = one SSP-RK3 step of the whole path: the IDP time step, then three
 stages of (high-order and low-order fluxes, volume limiter, mortar limiter, SSP
-combination).  Workload: the Sedov-type blast of the configuration list (2D
+combination).  Workload: the Sedov-type blast "blast22k" (2D
 Euler, gamma = 1.4, [-1,1]^2 periodic, 64^2 base mesh refined by three levels
 inside r <= 0.3 and 2:1 balanced: 22,156 leaves, 552 mortars, N = 3,
 rho = 1, v = 0, p = 1e-5 plus a Gaussian energy bump of width 0.06, positivity
@@ -62,7 +62,7 @@ def cpu_baseline(spec, N, seconds=12.0):
     threads = O.set_threads(cores)
     M = O.Mesh(N, *spec.args())
     x, y, m = M.geometry()
-    u = states.config_state(2, x, y)
+    u = states.workload_state("blast22k", x, y)
     t0 = time.perf_counter()
     steps = 0
     while True:
@@ -94,17 +94,17 @@ def main():
     import torch
     import paper_2607_06045_amd as P
     from workloads import states
-    from workloads.meshes import config_mesh
+    from workloads.meshes import workload_mesh
 
     N = 3
-    spec = config_mesh(2)
+    spec = workload_mesh("blast22k")
 
     def run(precision):
         s = P.Solver(N, gamma=1.4, beta=0.1, precision=precision, dt_mode=P.DT_IDP,
                      limiter=P.LIMIT_POSITIVITY)
         s.set_mesh(*spec.args())
         x, y = s.node_coords()
-        s.upload(states.config_state(2, x, y))
+        s.upload(states.workload_state("blast22k", x, y))
         for _ in range(args.warmup):
             s.step(0.5, stats=False)
         torch.cuda.synchronize()

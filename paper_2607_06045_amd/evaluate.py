@@ -90,8 +90,8 @@ def adapt_run(P, spec, u_fn, steps, every, ctrl, indicator, precision=None, repl
 def run_mixed(steps):
     import paper_2607_06045_amd as P
     from workloads import states
-    from workloads.meshes import config_mesh
-    spec = config_mesh(3)
+    from workloads.meshes import workload_mesh
+    spec = workload_mesh("shear59k")
     # levels relative to the 128 x 128 root grid (absolute levels 7 to 10)
     ctrl = (0, 1, 0.01, 3, 0.1)
     w = P.host_tables(3)["w"]
@@ -110,7 +110,7 @@ def run_mixed(steps):
         h2 = (2.0 / (128 << lv.astype(np.int64))) ** 2
         return ((u * W).sum(axis=(2, 3)) * h2[:, None]).sum(axis=0)
 
-    u_fn = lambda x, y: states.config_state(3, x, y)  # noqa: E731
+    u_fn = lambda x, y: states.workload_state("shear59k", x, y)  # noqa: E731
     log("FP64 run")
     s64, r64 = adapt_run(P, spec, u_fn, steps, 5, ctrl, ind, record=flags)
     log("mixed run")
@@ -137,7 +137,7 @@ def training_data(P, blasts=3, shears=2, snaps=6, every=5, seed=0):
     """(features, modal indicator) pairs on the GPU from seeded plain runs."""
     import torch
     from workloads import states
-    from workloads.meshes import config_mesh
+    from workloads.meshes import workload_mesh
     from workloads.rng import uniform
     X, Y = [], []
     log("training data")
@@ -145,7 +145,7 @@ def training_data(P, blasts=3, shears=2, snaps=6, every=5, seed=0):
         r = uniform(1000 + seed * 97 + k, np.arange(4, dtype=np.uint64))
         E0, sig = 0.5 + 1.5 * r[0], 0.04 + 0.04 * r[1]
         xc, yc = -0.2 + 0.4 * r[2], -0.2 + 0.4 * r[3]
-        s = _solver(P, config_mesh(2))
+        s = _solver(P, workload_mesh("blast22k"))
         x, y = s.node_coords()
         s.upload(states.sedov_gaussian(x, y, E0=E0, sigma=sig, xc=xc, yc=yc))
         for i in range(snaps * every):
@@ -155,7 +155,7 @@ def training_data(P, blasts=3, shears=2, snaps=6, every=5, seed=0):
             s.step(0.5, stats=False)
     for k in range(shears):
         r = uniform(2000 + seed * 89 + k, np.arange(2, dtype=np.uint64))
-        s = _solver(P, config_mesh(3))
+        s = _solver(P, workload_mesh("shear59k"))
         x, y = s.node_coords()
         s.upload(states.shear_layer(x, y, seed=300 + k, amp=0.05 + 0.1 * r[1]))
         for i in range(snaps * every):
@@ -196,7 +196,7 @@ def run_learned(steps, iters=3000, blasts=3, shears=2, snaps=6):
     import torch
     import paper_2607_06045_amd as P
     from workloads import states
-    from workloads.meshes import config_mesh
+    from workloads.meshes import workload_mesh
     t0 = time.perf_counter()
     X, Y = training_data(P, blasts, shears, snaps)
     n = X.shape[0]
@@ -213,10 +213,10 @@ def run_learned(steps, iters=3000, blasts=3, shears=2, snaps=6):
     val_mse = ((net.mlp_forward(Xva) - Yva) ** 2).mean().item()
     val_var = ((Yva - Yva.mean()) ** 2).mean().item()
 
-    spec = config_mesh(2)
+    spec = workload_mesh("blast22k")
     # levels relative to the 64 x 64 root grid (absolute levels 6 to 9)
     ctrl = (0, 2, 0.01, 3, 0.1)
-    u_fn = lambda x, y: states.config_state(2, x, y)  # noqa: E731
+    u_fn = lambda x, y: states.workload_state("blast22k", x, y)  # noqa: E731
 
     def plain(s):
         return s.indicator(P.IND_HENNEMANN)

@@ -4,9 +4,10 @@
       a plain device-to-device copy of known size (calibrates rocprofv3's
       FETCH_SIZE / WRITE_SIZE counters against known bytes)
 
-  python -m paper_2607_06045_amd.probes throughput --config 3 --precision fp64
-      SSP-RK3 steps of one of the synthetic workloads (1, 2, 3: N = 3;
-      5: N = 4) and the stage-kernel time; prints one JSON line
+  python -m paper_2607_06045_amd.probes throughput --workload shear59k --precision fp64
+      SSP-RK3 steps of one of the synthetic workloads (vortex304, blast22k,
+      shear59k: N = 3; quadrants247k: N = 4) and the stage-kernel time;
+      prints one JSON line
 """
 import argparse
 import sys
@@ -17,7 +18,7 @@ def main(argv=None):
     ap.add_argument("mode", choices=["copy", "throughput"])
     ap.add_argument("--mib", type=int, default=512)
     ap.add_argument("--reps", type=int, default=5)
-    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--workload", default="shear59k")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--steps", type=int, default=50)
     a = ap.parse_args(argv)
@@ -41,13 +42,13 @@ def throughput(a):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import paper_2607_06045_amd as P
     from workloads import states
-    from workloads.meshes import config_mesh
-    N = 4 if a.config == 5 else 3
-    spec = config_mesh(a.config)
+    from workloads.meshes import workload_mesh, workload_order
+    N = workload_order(a.workload)
+    spec = workload_mesh(a.workload)
     s = P.Solver(N, precision=P.MIXED if a.precision == "mixed" else P.FP64)
     s.set_mesh(*spec.args())
     x, y = s.node_coords()
-    s.upload(states.config_state(a.config, x, y))
+    s.upload(states.workload_state(a.workload, x, y))
     for _ in range(3):
         s.step(0.5, stats=False)
     torch.cuda.synchronize()
@@ -60,7 +61,7 @@ def throughput(a):
     km = s.time_kernels(reps=20)
     dofs = s.E * (N + 1) ** 2
     alg = (64.0 + 96.0 + 96.0) / 3.0 * dofs
-    print(json.dumps({"config": a.config, "N": N, "precision": a.precision, "elements": s.E,
+    print(json.dumps({"workload": a.workload, "N": N, "precision": a.precision, "elements": s.E,
                       "mortars": s.M, "dof_updates_per_s": dofs * 3 * a.steps / el,
                       "ms_per_step": el / a.steps * 1e3, "stage_ms": km["stage"],
                       "stage_hbm_frac": alg / (km["stage"] * 1e-3) / 8e12,

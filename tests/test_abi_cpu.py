@@ -74,11 +74,11 @@ def test_mesh_validate_matches_oracle(oracle, seed):
     assert n2 == _two_mortar_nodes(M)
 
 
-def test_mesh_validate_config_counts():
+def test_mesh_validate_workload_counts():
     import paper_2607_06045_amd as P
-    from workloads.meshes import config_mesh
-    for k, mortars in ((1, 16), (2, 552), (3, 3584)):
-        spec = config_mesh(k)
+    from workloads.meshes import workload_mesh
+    for k, mortars in (("vortex304", 16), ("blast22k", 552), ("shear59k", 3584)):
+        spec = workload_mesh(k)
         nm, _ = P.validate_mesh(3, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
         assert nm == mortars
 

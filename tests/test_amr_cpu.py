@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from workloads.meshes import config_mesh, random_flags, random_mesh
+from workloads.meshes import workload_mesh, random_flags, random_mesh
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -19,10 +19,10 @@ def test_adapt_leaves_matches_oracle(oracle, seed):
     P.validate_mesh(3, a[0], a[1], a[2], spec.nx0, spec.ny0)
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_adapt_leaves_configs(oracle, k):
+@pytest.mark.parametrize("k", ["vortex304", "blast22k"])
+def test_adapt_leaves_workloads(oracle, k):
     import paper_2607_06045_amd as P
-    spec = config_mesh(k)
+    spec = workload_mesh(k)
     flags = random_flags(spec, 9, p_refine=0.05, p_coarsen=0.5)
     a = P.adapt_leaves(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)
     b = oracle.adapt(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)

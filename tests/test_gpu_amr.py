@@ -7,7 +7,7 @@ import pytest
 
 from parity import state_err
 from workloads import states
-from workloads.meshes import config_mesh, random_flags, random_mesh, to_spec
+from workloads.meshes import workload_mesh, random_flags, random_mesh, to_spec
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -80,8 +80,8 @@ def test_zhang_shu_parity(oracle, N):
 def test_step_after_adaptation(oracle):
     """The adapted mesh has new mortars; stepping on it matches the oracle."""
     import paper_2607_06045_amd as P
-    spec = config_mesh(1)
-    s, M, u = _setup(oracle, spec, 3, lambda x, y: states.config_state(1, x, y))
+    spec = workload_mesh("vortex304")
+    s, M, u = _setup(oracle, spec, 3, lambda x, y: states.workload_state("vortex304", x, y))
     flags = random_flags(spec, 4, p_refine=0.1, p_coarsen=0.7)
     s.refine_coarsen(flags)
     lv, ix, iy = s.mesh()

@@ -14,7 +14,7 @@ import pytest
 from oracle import indicator as IND
 from oracle import mlp as MLP
 from workloads import states
-from workloads.meshes import config_mesh, random_mesh
+from workloads.meshes import workload_mesh, random_mesh
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ def _solver(spec, N, u_fn):
 
 
 CASES = {
-    "blast": (lambda: config_mesh(2), lambda x, y: states.config_state(2, x, y)),
+    "blast": (lambda: workload_mesh("blast22k"), lambda x, y: states.workload_state("blast22k", x, y)),
     "shear": (lambda: random_mesh(2, 8, 2, 0.3, L=2.0, x0=-1.0, y0=-1.0),
               lambda x, y: states.shear_layer(x, y)),
     "random": (lambda: random_mesh(4, 6, 2, 0.4), lambda x, y: states.random_admissible(x, 5)),
@@ -135,8 +135,8 @@ def test_learned_indicator_trains_on_gpu():
     import torch
     xs, ts = [], []
     for k, (mesh_fn, u_fn) in enumerate([
-            (lambda: config_mesh(2), lambda x, y: states.sedov_gaussian(x, y, sigma=0.05)),
-            (lambda: config_mesh(2), lambda x, y: states.sedov_tophat(x, y)),
+            (lambda: workload_mesh("blast22k"), lambda x, y: states.sedov_gaussian(x, y, sigma=0.05)),
+            (lambda: workload_mesh("blast22k"), lambda x, y: states.sedov_tophat(x, y)),
             (lambda: random_mesh(2, 16, 1, 0.3, L=2.0, x0=-1.0, y0=-1.0),
              lambda x, y: states.shear_layer(x, y, seed=7)),
             (lambda: random_mesh(5, 12, 1, 0.3), lambda x, y: states.quadrants(x, y))]):
@@ -162,7 +162,7 @@ def test_learned_indicator_trains_on_gpu():
           f"variance of the target {base:.3e}", flush=True)
     assert full < 0.25 * base
     # the trained network as the context's indicator
-    s, u = _solver(config_mesh(2), 3, lambda x, y: states.config_state(2, x, y))
+    s, u = _solver(workload_mesh("blast22k"), 3, lambda x, y: states.workload_state("blast22k", x, y))
     s.mlp_set_weights(net.mlp_get_weights())
     a = s.indicator(P.IND_MLP)
     assert np.array_equal(a, s.mlp_forward(s.features()))

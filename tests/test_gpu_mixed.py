@@ -15,7 +15,7 @@ import pytest
 
 from parity import rate_err, state_err
 from workloads import states
-from workloads.meshes import config_mesh, random_mesh
+from workloads.meshes import workload_mesh, random_mesh
 
 pytestmark = pytest.mark.gpu
 
@@ -32,13 +32,13 @@ def solver(spec, N, precision, **kw):
 
 
 @pytest.mark.parametrize("N", [3, 4])
-@pytest.mark.parametrize("name", ["config1", "random3"])
+@pytest.mark.parametrize("name", ["vortex304", "random3"])
 def test_mixed_rhs_error_bound(oracle, name, N):
     import paper_2607_06045_amd as P
-    spec = config_mesh(1) if name == "config1" else random_mesh(3, 4, 3, 0.4)
+    spec = workload_mesh("vortex304") if name == "vortex304" else random_mesh(3, 4, 3, 0.4)
     M = oracle.Mesh(N, *spec.args())
     x, y, m = M.geometry()
-    u = states.vortex(x, y) if name == "config1" else states.density_wave(x, y)
+    u = states.vortex(x, y) if name == "vortex304" else states.density_wave(x, y)
     s = solver(spec, N, P.MIXED)
     s.upload(u)
     w0 = oracle.basis(N)[1][0]
@@ -58,10 +58,10 @@ def test_mixed_rhs_error_bound(oracle, name, N):
 @pytest.mark.parametrize("N", [3, 4])
 def test_mixed_step_error_bound(oracle, N):
     import paper_2607_06045_amd as P
-    spec = config_mesh(1)
+    spec = workload_mesh("vortex304")
     M = oracle.Mesh(N, *spec.args())
     x, y, m = M.geometry()
-    u = states.config_state(1, x, y)
+    u = states.workload_state("vortex304", x, y)
     s = solver(spec, N, P.MIXED)
     s.upload(u)
     cfl = 0.5
@@ -87,10 +87,10 @@ def test_mixed_conservation_defect(oracle):
     FP64); only the FP32 mortar projection leaves a defect, of FP32 size."""
     import paper_2607_06045_amd as P
     out = {}
-    for name, spec in (("uniform", random_mesh(5, 12, 0, 0.0)), ("config1", config_mesh(1))):
+    for name, spec in (("uniform", random_mesh(5, 12, 0, 0.0)), ("vortex304", workload_mesh("vortex304"))):
         M = oracle.Mesh(3, *spec.args())
         x, y, m = M.geometry()
-        u = states.vortex(x, y) if name == "uniform" else states.config_state(1, x, y)
+        u = states.vortex(x, y) if name == "uniform" else states.workload_state("vortex304", x, y)
         for prec in (P.FP64, P.MIXED):
             s = solver(spec, 3, prec)
             s.upload(u)
@@ -98,9 +98,9 @@ def test_mixed_conservation_defect(oracle):
             out[name, prec] = _defect(u, s.download(), m)
     print("conservation defect " + ", ".join(f"{k[0]}/{'mixed' if k[1] else 'fp64'} {v:.2e}"
                                               for k, v in out.items()), flush=True)
-    assert out["uniform", P.FP64] < 1e-14 and out["config1", P.FP64] < 1e-14
+    assert out["uniform", P.FP64] < 1e-14 and out["vortex304", P.FP64] < 1e-14
     assert out["uniform", P.MIXED] < 1e-14
-    assert out["config1", P.MIXED] < 2.0 ** -24
+    assert out["vortex304", P.MIXED] < 2.0 ** -24
 
 
 def test_mixed_blast_positivity():
@@ -108,12 +108,12 @@ def test_mixed_blast_positivity():
     benchmark blast for several steps, zero violations, and the mixed solution
     stays close to the FP64 one."""
     import paper_2607_06045_amd as P
-    spec = config_mesh(2)
+    spec = workload_mesh("blast22k")
     res = {}
     for prec in (P.FP64, P.MIXED):
         s = solver(spec, 3, prec)
         x, y = s.node_coords()
-        s.upload(states.config_state(2, x, y))
+        s.upload(states.workload_state("blast22k", x, y))
         viol = inad = 0
         for _ in range(5):
             st = s.step(0.5)

@@ -6,7 +6,7 @@ import pytest
 
 from parity import rate_err, state_err
 from workloads import states
-from workloads.meshes import config_mesh, random_mesh, refined_box_mesh
+from workloads.meshes import workload_mesh, random_mesh, refined_box_mesh
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -22,7 +22,7 @@ def pair(oracle, spec, N=3, gamma=1.4, **kw):
 
 
 MESHES = {
-    "config1": lambda: config_mesh(1),
+    "vortex304": lambda: workload_mesh("vortex304"),
     "random0": lambda: random_mesh(0, 4, 3, 0.4),
     "random3": lambda: random_mesh(3, 4, 3, 0.4),
 }
@@ -41,7 +41,7 @@ def test_rhs_parity(oracle, name, N):
     x, y, m = M.geometry()
     xg, yg = s.node_coords()
     assert np.abs(xg - x).max() < 1e-14 and np.abs(yg - y).max() < 1e-14
-    u = states.vortex(x, y) if name == "config1" else states.density_wave(x, y)
+    u = states.vortex(x, y) if name == "vortex304" else states.density_wave(x, y)
     s.upload(u)
     assert np.array_equal(s.download(), u)
     w0 = oracle.basis(N)[1][0]
@@ -68,11 +68,11 @@ def test_dt_parity(oracle, N):
 
 
 @pytest.mark.parametrize("N", [3, 4])
-@pytest.mark.parametrize("name", ["config1", "random3"])
+@pytest.mark.parametrize("name", ["vortex304", "random3"])
 def test_limited_forward_euler_parity(oracle, name, N):
     s, M = pair(oracle, MESHES[name](), N)
     x, y, m = M.geometry()
-    u = states.vortex(x, y) if name == "config1" else states.density_wave(x, y)
+    u = states.vortex(x, y) if name == "vortex304" else states.density_wave(x, y)
     s.upload(u)
     dt = M.max_dt(u, 0.9)
     st = s.limit(dt)
@@ -141,37 +141,37 @@ def test_isentropic_near_vacuum_parity(oracle):
         assert st["violations"] == 0 and st["fv_inadmissible"] == 0
 
 
-def test_config1_step_parity_and_determinism(oracle):
+def test_vortex304_step_parity_and_determinism(oracle):
     """Workload 1: one RHS and one SSP-RK3 step at CFL 0.5; a rerun is bitwise equal."""
-    spec = config_mesh(1)
+    spec = workload_mesh("vortex304")
     s, M = pair(oracle, spec, 3)
     x, y, m = M.geometry()
-    u = states.config_state(1, x, y)
+    u = states.workload_state("vortex304", x, y)
     s.upload(u)
     st = s.step(0.5)
     g1 = s.download()
     c, sc = M.ssprk3(u, 0.5)
     err = state_err(g1, c)
-    print(f"config1 step err={err:.2e}", flush=True)
+    print(f"vortex304 step err={err:.2e}", flush=True)
     assert err < TOL
     s.upload(u)
     s.step(0.5)
     assert np.array_equal(s.download(), g1)
 
 
-@pytest.mark.parametrize("k", [2, 3])
-def test_full_size_config_step(oracle, k):
-    """Workloads 2 and 3 at full size (22,156 and 59,392 leaves): one SSP-RK3 step
+@pytest.mark.parametrize("k", ["blast22k", "shear59k"])
+def test_full_size_workload_step(oracle, k):
+    """The blast and shear-layer workloads at full size (22,156 and 59,392 leaves): one SSP-RK3 step
     compared with the oracle on every node."""
-    spec = config_mesh(k)
+    spec = workload_mesh(k)
     s, M = pair(oracle, spec, 3)
     x, y, m = M.geometry()
-    u = states.config_state(k, x, y)
+    u = states.workload_state(k, x, y)
     s.upload(u)
     st = s.step(0.5)
     c, sc = M.ssprk3(u, 0.5)
     err = state_err(s.download(), c)
-    print(f"config{k} E={s.E} M={s.M} err={err:.2e} gpu={st} oracle={sc}", flush=True)
+    print(f"{k} E={s.E} M={s.M} err={err:.2e} gpu={st} oracle={sc}", flush=True)
     assert err < TOL
     assert st["violations"] == 0
 
@@ -179,7 +179,7 @@ def test_full_size_config_step(oracle, k):
 def test_error_paths(oracle):
     import paper_2607_06045_amd as P
     s = P.Solver(3)
-    spec = config_mesh(1)
+    spec = workload_mesh("vortex304")
     with pytest.raises(P.DgidpError, match="NO_STATE|NO_MESH"):
         s.step(0.5)
     # unbalanced mesh: a level-2 leaf next to a level-0 leaf
@@ -201,14 +201,14 @@ def test_graph_replay_matches_eager():
     two captured graphs), interleaved with an eager step that returns
     statistics, give bit-identical states to kernel-by-kernel launches."""
     import paper_2607_06045_amd as P
-    spec = config_mesh(2)
+    spec = workload_mesh("blast22k")
     out = []
     for graphs in (True, False):
         s = P.Solver(3)
         s.set_graphs(graphs)
         s.set_mesh(*spec.args())
         x, y = s.node_coords()
-        s.upload(states.config_state(2, x, y))
+        s.upload(states.workload_state("blast22k", x, y))
         for k in range(10):
             s.step(0.5, stats=False)
             if k == 4:
@@ -245,18 +245,18 @@ def test_degenerate_meshes_parity(oracle, N):
         assert err < TOL and st["violations"] == 0
 
 
-def test_full_size_config5_n4(oracle):
+def test_full_size_quadrants247k_n4(oracle):
     """The largest workload (N = 4, 246,736 leaves, 6.2 M nodes, 5,536
     mortars): one SSP-RK3 step compared with the oracle on every node."""
-    spec = config_mesh(5)
+    spec = workload_mesh("quadrants247k")
     s, M = pair(oracle, spec, 4)
     x, y, m = M.geometry()
-    u = states.config_state(5, x, y)
+    u = states.workload_state("quadrants247k", x, y)
     s.upload(u)
     st = s.step(0.5)
     c, sc = M.ssprk3(u, 0.5)
     err = state_err(s.download(), c)
-    print(f"config5 N=4 E={s.E} M={s.M} err={err:.2e} dt gpu {st['dt']!r} oracle {sc['dt']!r}", flush=True)
+    print(f"quadrants247k N=4 E={s.E} M={s.M} err={err:.2e} dt gpu {st['dt']!r} oracle {sc['dt']!r}", flush=True)
     assert err < TOL
     assert st["violations"] == 0
     assert abs(st["dt"] - sc["dt"]) <= 1e-14 * sc["dt"]

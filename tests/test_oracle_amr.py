@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from workloads import states
-from workloads.meshes import config_mesh, random_flags, random_mesh, to_spec
+from workloads.meshes import workload_mesh, random_flags, random_mesh, to_spec
 
 
 def raster(level, ix, iy, nx0, ny0):

@@ -5,7 +5,7 @@ import pytest
 
 from paper_values import tables
 from workloads import states
-from workloads.meshes import config_mesh, random_mesh, refined_box_mesh, uniform_mesh
+from workloads.meshes import workload_mesh, random_mesh, refined_box_mesh, uniform_mesh
 
 T = tables()
 
@@ -15,7 +15,7 @@ def make(oracle, spec, N=3):
 
 
 MESHES = {
-    "config1": lambda: config_mesh(1),
+    "vortex304": lambda: workload_mesh("vortex304"),
     "random0": lambda: random_mesh(0, 4, 3, 0.4),
     "random3": lambda: random_mesh(3, 4, 3, 0.4),
     "uniform": lambda: uniform_mesh(5, 3, Lx=1.0, Ly=0.6),
@@ -102,7 +102,7 @@ def _phys(u, d, g):
     return f, abs(vn) + np.sqrt(g * p / rho)
 
 
-@pytest.mark.parametrize("name", ["random0", "config1"])
+@pytest.mark.parametrize("name", ["random0", "vortex304"])
 def test_low_order_bar_state_form(oracle, name):
     """m_i u_dot_i = sum_j 2 d_ij (ubar_ij - u_i) (eq. barstateform), evaluated from
     the paper's bar states, equals the oracle's low-order residual; also checks

@@ -1,10 +1,10 @@
-"""Seeded synthetic inputs: mesh sizes of the workload configurations, 2:1 balance,
+"""Seeded synthetic inputs: mesh sizes of the named workloads, 2:1 balance,
 RNG determinism, admissible initial states."""
 import numpy as np
 import pytest
 
 from workloads import rng, states
-from workloads.meshes import config_mesh, random_mesh
+from workloads.meshes import workload_mesh, random_mesh
 
 
 def test_splitmix64_reference_values():
@@ -16,22 +16,22 @@ def test_splitmix64_reference_values():
 
 
 @pytest.mark.parametrize("k,E,levels", [
-    (1, 304, {0: 240, 1: 64}),
-    (2, 22156, {0: 3744, 1: 176, 2: 492, 3: 17744}),
-    (3, 59392, {0: 15360, 1: 1024, 2: 2048, 3: 40960}),
+    ("vortex304", 304, {0: 240, 1: 64}),
+    ("blast22k", 22156, {0: 3744, 1: 176, 2: 492, 3: 17744}),
+    ("shear59k", 59392, {0: 15360, 1: 1024, 2: 2048, 3: 40960}),
 ])
-def test_config_meshes(oracle, k, E, levels):
-    m = config_mesh(k)
+def test_workload_meshes(oracle, k, E, levels):
+    m = workload_mesh(k)
     assert m.E == E and m.counts() == levels
     M = oracle.Mesh(3, *m.args())  # tiles the domain and is 2:1 balanced
     assert M.E == E
 
 
-def test_config_states_admissible(oracle):
-    for k in (1, 2, 3):
-        M = oracle.Mesh(3, *config_mesh(k).args())
+def test_workload_states_admissible(oracle):
+    for k in ("vortex304", "blast22k", "shear59k"):
+        M = oracle.Mesh(3, *workload_mesh(k).args())
         x, y, m = M.geometry()
-        u = states.config_state(k, x, y)
+        u = states.workload_state(k, x, y)
         p = 0.4 * (u[:, 3] - 0.5 * (u[:, 1] ** 2 + u[:, 2] ** 2) / u[:, 0])
         assert (u[:, 0] > 0).all() and (p > 0).all()
 

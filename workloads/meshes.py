@@ -116,16 +116,19 @@ def refined_box_mesh(n_base, box_lo, box_hi, x0, y0, L):
                  lambda x, y, l: bx0 < x < bx1 and by0 < y < by1, 1)
 
 
-def config_mesh(k):
-    """Leaf lists of the five synthetic workload configurations."""
-    if k == 1:
+WORKLOADS = ("vortex304", "blast22k", "shear59k", "quadrants247k")
+
+
+def workload_mesh(name):
+    """Leaf lists of the named synthetic workloads (name = initial state + leaf count)."""
+    if name == "vortex304":  # [0,1]^2, 16^2 base, +1 level in [0.375, 0.625]^2
         return refined_box_mesh(16, (0.375, 0.375), (0.625, 0.625), 0.0, 0.0, 1.0)
-    if k == 2:  # blast on [-1,1]^2, 64^2 base, +3 levels where r <= 0.3
+    if name == "blast22k":  # blast on [-1,1]^2, 64^2 base, +3 levels where r <= 0.3
         return build((-1.0, -1.0, 2.0, 2.0, 64, 64), lambda x, y, l: x * x + y * y <= 0.09, 3)
-    if k == 3:  # shear layer on [-1,1]^2, 128^2 base, +3 levels on leaves meeting |(|y| - 0.5)| < 0.0175
+    if name == "shear59k":  # [-1,1]^2, 128^2 base, +3 levels on leaves meeting |(|y| - 0.5)| < 0.0175
         return build((-1.0, -1.0, 2.0, 2.0, 128, 128),
                      lambda x, y, l: abs(abs(y) - 0.5) < 0.0175 + 0.5 * 2.0 / (128 << l), 3)
-    if k == 5:  # four quadrants on [0,1]^2, 256^2 base, +2 levels near x, y in {0, 0.5}
+    if name == "quadrants247k":  # four quadrants on [0,1]^2, 256^2 base, +2 levels near x, y in {0, 0.5}
 
         def near(x, y, l):  # leaf meets the band of half-width 0.022 around a line
             def d(t):
@@ -133,7 +136,12 @@ def config_mesh(k):
             return min(d(x), d(y)) < 0.022 + 0.5 / (256 << l)
 
         return build((0.0, 0.0, 1.0, 1.0, 256, 256), near, 2)
-    raise ValueError(k)
+    raise ValueError(name)
+
+
+def workload_order(name):
+    """Polynomial degree N of a named workload."""
+    return 4 if name == "quadrants247k" else 3
 
 
 def random_mesh(seed, n_base=4, maxlev=2, frac=0.35, L=1.0, x0=0.0, y0=0.0):

@@ -105,14 +105,14 @@ def random_admissible(shape_like, seed, gamma=1.4, rho_range=(0.2, 2.0), p_range
     return conservative(rho, v1, v2, p, gamma)
 
 
-def config_state(k, x, y, seed=None):
-    """Initial state of workload configuration k at the given nodes."""
-    if k == 1:
+def workload_state(name, x, y, seed=None):
+    """Initial state of the named workload at the given nodes."""
+    if name == "vortex304":
         return vortex(x, y, seed=1 if seed is None else seed)
-    if k in (2, 4):
+    if name == "blast22k":
         return sedov_gaussian(x, y)
-    if k == 3:
+    if name == "shear59k":
         return shear_layer(x, y, seed=3 if seed is None else seed)
-    if k == 5:
+    if name == "quadrants247k":
         return quadrants(x, y, seed=5 if seed is None else seed)
-    raise ValueError(k)
+    raise ValueError(name)
