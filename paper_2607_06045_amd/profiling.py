@@ -75,6 +75,29 @@ def traffic(a):
     print(json.dumps(out))
 
 
+def timed_region(a):
+    """Mean duration of the last --tail dispatches of --kernel in the kernel trace
+    (bench.py's kernel-timing region) beside the HIP-event figure that the same
+    profiled bench.py run printed for that kernel."""
+    with open(a.trace_csv) as fh:
+        rows = [r for r in csv.DictReader(fh) if r["Kernel_Name"].startswith("void dgidp::" + a.kernel)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[-a.tail:]]
+    if not d:
+        raise SystemExit(f"no dispatches of {a.kernel!r} in {a.trace_csv}")
+    mean = sum(d) / len(d)
+    out = [f"# {a.kernel}: mean over its last {len(d)} dispatches (bench.py's kernel-timing region): "
+           f"{mean:.2f} us"]
+    if a.bench_log:
+        with open(a.bench_log) as fh:
+            js = [json.loads(l) for l in fh if l.startswith('{"metric"')]
+        if js:
+            live = js[-1]["roofline"]["kernel_ms"] * 1e3
+            out.append(f"# same run, bench.py's HIP-event figure for that kernel: {live:.2f} us "
+                       f"(trace / events = {mean / live:.3f})")
+    return out
+
+
 def stats(a):
     with open(a.csv) as fh:
         rows = list(csv.DictReader(fh))
@@ -85,6 +108,8 @@ def stats(a):
         lines.append(f"{name:60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f} "
                      f"{float(r['Percentage']):6.2f}")
+    if a.trace_csv and a.kernel and a.tail > 0:
+        lines += [""] + timed_region(a)
     text = "\n".join(lines) + "\n"
     with open(a.out, "w") as fh:
         fh.write(text)
@@ -109,6 +134,10 @@ def main(argv=None):
     s.add_argument("--out", required=True)
     s.add_argument("--title", default="rocprofv3 kernel statistics")
     s.add_argument("--command", default="")
+    s.add_argument("--trace-csv", default="")
+    s.add_argument("--kernel", default="")
+    s.add_argument("--tail", type=int, default=0)
+    s.add_argument("--bench-log", default="")
     a = ap.parse_args(argv)
     if a.mode == "traffic":
         traffic(a)
