@@ -20,7 +20,7 @@ _lib = None
 
 RHS_HIGH, RHS_LOW = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
-LIM_NONE, LIM_POSITIVITY = 0, 1
+LIM_NONE, LIM_POSITIVITY, LIM_LOCAL = 0, 1, 2
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
@@ -75,6 +75,12 @@ def lib():
         L.orc_overlap_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         L.orc_theta_pressure.restype = ctypes.c_double
         L.orc_theta_pressure.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double]
+        L.orc_bar_state.argtypes = [_D, _D, ctypes.c_int, ctypes.c_double, _D]
+        L.orc_spec_entropy.restype = ctypes.c_double
+        L.orc_spec_entropy.argtypes = [_D, ctypes.c_double]
+        L.orc_theta_entropy.restype = ctypes.c_double
+        L.orc_theta_entropy.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_local_bounds.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D, _D, _D]
         L.orc_set_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -154,6 +160,28 @@ def theta_pressure(u0, dc, pt, gamma):
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
     dc = np.ascontiguousarray(dc, dtype=np.float64)
     return lib().orc_theta_pressure(_ptr(u0), _ptr(dc), pt, gamma)
+
+
+def bar_state(uL, uR, direction, gamma):
+    """Bar state of the graph edge between uL (low side along direction) and uR."""
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    ub = np.zeros(4)
+    lib().orc_bar_state(_ptr(uL), _ptr(uR), direction, gamma, _ptr(ub))
+    return ub
+
+
+def spec_entropy(u, gamma):
+    """Specific entropy p rho^-gamma (0 outside the admissible set)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().orc_spec_entropy(_ptr(u), gamma)
+
+
+def theta_entropy(u0, dc, st, gamma, thi=1.0):
+    """Largest theta in [0, thi] with p rho^-gamma >= st at u0 + theta dc."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    dc = np.ascontiguousarray(dc, dtype=np.float64)
+    return lib().orc_theta_entropy(_ptr(u0), _ptr(dc), st, gamma, thi)
 
 
 def lagrange(N, k, s):
@@ -240,6 +268,15 @@ class Mesh:
     def max_dt(self, u, cfl, mode=DT_IDP, gamma=1.4):
         u = np.ascontiguousarray(u, dtype=np.float64)
         return lib().orc_max_dt(self._h, _ptr(u), cfl, mode, gamma)
+
+    def local_bounds(self, u, gamma=1.4):
+        """(rho_min, rho_max, s_min), each [E, n, n] (e, b, a), over the bar states
+        of every node's low-order neighbours and the node itself."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        sh = (self.E, self.n, self.n)
+        lo, hi, sm = np.zeros(sh), np.zeros(sh), np.zeros(sh)
+        lib().orc_local_bounds(self._h, _ptr(u), gamma, _ptr(lo), _ptr(hi), _ptr(sm))
+        return lo, hi, sm
 
     def fe_step(self, u, dt, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
         u = np.ascontiguousarray(u, dtype=np.float64)

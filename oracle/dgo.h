@@ -84,7 +84,7 @@ void dgo_mesh_release(dgo_mesh* m);
 /* ---------------- scheme ---------------- */
 typedef struct {
     int64_t fv_inadmissible; /* nodes where the low-order update left the admissible set */
-    int64_t violations;      /* nodes below the rho / p bounds after limiting */
+    int64_t violations;      /* nodes outside the bounds after limiting */
     double theta_vol_min, theta_mort_min;
     double alpha_vol_mean, alpha_mort_mean; /* mean of 1-theta over subcell faces / mortars */
     double dt;
@@ -92,7 +92,7 @@ typedef struct {
 
 enum { RHS_HIGH = 0, RHS_LOW = 1 };
 enum { DT_IDP = 0, DT_LOWORDER = 1 };
-enum { LIM_NONE = 0, LIM_POSITIVITY = 1 };
+enum { LIM_NONE = 0, LIM_POSITIVITY = 1, LIM_LOCAL = 2 };
 
 int dgo_rhs(const dgo_mesh* m, const double* u, int which, double gamma, double* du);
 double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, double gamma);
@@ -101,6 +101,12 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
 int dgo_ssprk3(const dgo_mesh* m, double* u, double cfl, int mode, double gamma, double beta,
                int limiter, dgo_stats* st);
 double dgo_theta_pressure(const double* u0, const double* dc, double pt, double gamma);
+/* local limiting (eq. Bounds_Barstates) */
+void dgo_bar_state(const double* uL, const double* uR, int dir, double gamma, double* ub);
+double dgo_spec_entropy(const double* u, double gamma);
+void dgo_local_bounds(const dgo_mesh* m, const double* u, double gamma, double* rlo, double* rhi,
+                      double* smin);
+double dgo_theta_entropy(const double* u0, const double* dc, double st, double gamma, double thi);
 int dgo_ssprk3_dt(const dgo_mesh* m, double* u, double dt, double gamma, double beta, int limiter,
                   dgo_stats* st);
 

@@ -188,6 +188,23 @@ double orc_theta_pressure(const double* u0, const double* dc, double pt, double 
     return dgo_theta_pressure(u0, dc, pt, gamma);
 }
 
+void orc_bar_state(const double* uL, const double* uR, int dir, double gamma, double* ub)
+{
+    dgo_bar_state(uL, uR, dir, gamma, ub);
+}
+
+double orc_spec_entropy(const double* u, double gamma) { return dgo_spec_entropy(u, gamma); }
+
+double orc_theta_entropy(const double* u0, const double* dc, double st, double gamma, double thi)
+{
+    return dgo_theta_entropy(u0, dc, st, gamma, thi);
+}
+
+void orc_local_bounds(void* h, const double* u, double gamma, double* rlo, double* rhi, double* smin)
+{
+    dgo_local_bounds((dgo_mesh*)h, u, gamma, rlo, rhi, smin);
+}
+
 int orc_set_threads(int t)
 {
 #ifdef _OPENMP

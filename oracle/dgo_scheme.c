@@ -16,7 +16,9 @@
  *  Time step (eq. timestep_restriction; eq. CFLcondition_lowordermethod).
  *  Limiting (Sec. 2.3): low-order update, then the volume correction with one
  *  factor per subcell face, then the mortar correction with one factor per
- *  mortar, against the positivity bounds of eq. Bounds_Positivity.
+ *  mortar, against the positivity bounds of eq. Bounds_Positivity, and with
+ *  local limiting also against the bar-state bounds of eq. Bounds_Barstates
+ *  (density minimum and maximum, minimum of the specific entropy).
  *  Time integration: three-stage SSP Runge-Kutta (Shu & Osher 1988, Sec. 3).
  */
 #include <math.h>
@@ -383,6 +385,11 @@ double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, doub
 /* the limiter aims at the bounds raised by this relative margin, so that the
    rounding of the final sums cannot cross the bounds themselves */
 #define BOUND_MARGIN (1.0 + 0x1p-40)
+#define BOUND_MARGIN_HI (1.0 - 0x1p-40)
+/* local bounds hold only up to rounding for the low-order state itself (it is
+   a convex combination of bar states in exact arithmetic); the bound check
+   allows this relative slack for them */
+#define LOCAL_TOL 1e-12
 
 /* largest theta in [0,1] with rho(u0 + theta dc) > 0 and p(u0 + theta dc) >= pt.
    With rho > 0, p >= pt  <=>  g(theta) = (E - pt/(gamma-1)) rho - |m|^2/2 >= 0,
@@ -412,6 +419,185 @@ double dgo_theta_pressure(const double* u0, const double* dc, double pt, double 
         if (rz < root) root = rz;
     }
     return root < 1.0 ? root : 1.0;
+}
+
+/* ---------------------------------------------------------------------------
+ * local bounds (eq. Bounds_Barstates)
+ * ------------------------------------------------------------------------- */
+
+/* Bar state of the graph edge between uL and uR, uL on the low side along dir
+   (Sec. 2.2, IDP property): (u_i + u_j)/2 - c_ij . (f_j - f_i) / (2 d_ij).
+   With d_ij = |c_ij| lambda_ij and c_ij parallel to the axis, c_ij / d_ij is the
+   unit normal from i to j over lambda_ij, so the bar state is
+   (uL + uR)/2 - (f(uR) - f(uL)) / (2 lambda), whichever end is i. */
+void dgo_bar_state(const double* uL, const double* uR, int dir, double gamma, double* ub)
+{
+    double fL[4], fR[4];
+    dgo_flux_phys(uL, dir, gamma, fL);
+    dgo_flux_phys(uR, dir, gamma, fR);
+    double lam = lam_pair(uL, uR, dir, gamma);
+    for (int v = 0; v < 4; ++v) ub[v] = 0.5 * (uL[v] + uR[v]) - (fR[v] - fL[v]) / (2.0 * lam);
+}
+
+/* specific entropy s = p rho^-gamma; the paper's eta = s / (gamma - 1) orders
+   states the same way.  0 for a state outside the admissible set. */
+double dgo_spec_entropy(const double* u, double gamma)
+{
+    double p = dgo_pressure(u, gamma);
+    if (!(u[0] > 0.0) || !(p > 0.0)) return 0.0;
+    return p * pow(u[0], -gamma);
+}
+
+static void bound_add(const double* ub, double gamma, double* lo, double* hi, double* smin)
+{
+    if (ub[0] < *lo) *lo = ub[0];
+    if (ub[0] > *hi) *hi = ub[0];
+    double s = dgo_spec_entropy(ub, gamma);
+    if (s < *smin) *smin = s;
+}
+
+/* own = this node, o = the other end; own_low: this node on the low side */
+static void bound_edge(const double* own, const double* o, int own_low, int dir, double gamma,
+                       double* lo, double* hi, double* smin)
+{
+    double ub[4];
+    if (own_low) dgo_bar_state(own, o, dir, gamma, ub);
+    else dgo_bar_state(o, own, dir, gamma, ub);
+    bound_add(ub, gamma, lo, hi, smin);
+}
+
+/* Per node i: min and max of the density and min of the specific entropy over
+   the bar states of i and its low-order neighbours N(i) (the node itself is the
+   bar state (i, i)).  N(i): the subcell neighbours inside the element, the
+   matching node across a conforming face, and across a mortar the nodes of the
+   other side whose sparse weight with i is nonzero (Sec. 2.2). */
+void dgo_local_bounds(const dgo_mesh* m, const double* u, double gamma, double* rlo, double* rhi,
+                      double* smin)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    int64_t nn = n * n;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < m->E; ++e)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double ui[4], uo[4];
+                get_node(u, n, e, a, b, ui);
+                double lo = ui[0], hi = ui[0], sm = dgo_spec_entropy(ui, gamma);
+                if (a > 0) { get_node(u, n, e, a - 1, b, uo); bound_edge(ui, uo, 0, 0, gamma, &lo, &hi, &sm); }
+                if (a < N) { get_node(u, n, e, a + 1, b, uo); bound_edge(ui, uo, 1, 0, gamma, &lo, &hi, &sm); }
+                if (b > 0) { get_node(u, n, e, a, b - 1, uo); bound_edge(ui, uo, 0, 1, gamma, &lo, &hi, &sm); }
+                if (b < N) { get_node(u, n, e, a, b + 1, uo); bound_edge(ui, uo, 1, 1, gamma, &lo, &hi, &sm); }
+                for (int f = 0; f < 4; ++f) {
+                    int k = -1;
+                    if (f == 0 && a == 0) k = b;
+                    if (f == 1 && a == N) k = b;
+                    if (f == 2 && b == 0) k = a;
+                    if (f == 3 && b == N) k = a;
+                    if (k < 0) continue;
+                    const dgo_face* F = &m->face[e * 4 + f];
+                    int dir = f / 2, own_low = f & 1;
+                    if (F->type == FACE_CONF) {
+                        int a2, b2;
+                        face_node(f ^ 1, k, N, &a2, &b2);
+                        get_node(u, n, F->nbr, a2, b2, uo);
+                        bound_edge(ui, uo, own_low, dir, gamma, &lo, &hi, &sm);
+                    } else if (F->type == FACE_LARGE) {
+                        const dgo_mortar* M = &m->mort[F->mortar];
+                        for (int h = 0; h < 2; ++h)
+                            for (int l = 0; l < n; ++l) {
+                                if (B->Wt[k][h * n + l] == 0.0) continue;
+                                int a2, b2;
+                                face_node(f ^ 1, l, N, &a2, &b2);
+                                get_node(u, n, M->small[h], a2, b2, uo);
+                                bound_edge(ui, uo, own_low, dir, gamma, &lo, &hi, &sm);
+                            }
+                    } else {
+                        const dgo_mortar* M = &m->mort[F->mortar];
+                        for (int kk = 0; kk < n; ++kk) {
+                            if (B->Wt[kk][F->half * n + k] == 0.0) continue;
+                            int a2, b2;
+                            face_node(M->face, kk, N, &a2, &b2);
+                            get_node(u, n, M->large, a2, b2, uo);
+                            bound_edge(ui, uo, own_low, dir, gamma, &lo, &hi, &sm);
+                        }
+                    }
+                }
+                rlo[e * nn + b * n + a] = lo;
+                rhi[e * nn + b * n + a] = hi;
+                smin[e * nn + b * n + a] = sm;
+            }
+}
+
+/* psi(theta) = p(u0 + theta dc) - st rho(u0 + theta dc)^gamma and its derivative.
+   psi >= 0 with rho > 0 is s >= st; psi is concave along the ray (p is concave
+   in the conserved variables and rho^gamma convex). */
+static double psi_entropy(const double* u0, const double* dc, double th, double st, double gamma,
+                          double* dpsi)
+{
+    double q[4];
+    for (int v = 0; v < 4; ++v) q[v] = u0[v] + th * dc[v];
+    if (!(q[0] > 0.0)) {
+        *dpsi = 0.0;
+        return -INFINITY;
+    }
+    double v1 = q[1] / q[0], v2 = q[2] / q[0];
+    double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * v1 + q[2] * v2));
+    double rg = st * pow(q[0], gamma);
+    double dp = (gamma - 1.0) * (dc[3] - v1 * dc[1] - v2 * dc[2] + 0.5 * (v1 * v1 + v2 * v2) * dc[0]);
+    *dpsi = dp - gamma * rg / q[0] * dc[0];
+    return p - rg;
+}
+
+/* Largest theta in [0, thi] with s(u0 + theta dc) >= st, for a ray on which
+   rho stays positive.  The admissible set of a concave psi with psi(0) >= 0 is
+   an interval [0, theta*]; the root is bracketed from both sides: the chord
+   through a feasible and an infeasible point cuts the axis at or below theta*
+   (concavity), the Newton step from the infeasible end at or above it (the
+   tangent lies above psi).  This is the two-sided iteration used for convex
+   limiting by Guermond, Nazarov, Popov and Tomas (SIAM J. Sci. Comput. 2018).
+   Returns the feasible end once the bracket is below 1e-14 (at most 16
+   rounds); psi(0) <= 0 returns 0. */
+double dgo_theta_entropy(const double* u0, const double* dc, double st, double gamma, double thi)
+{
+    if (!(thi > 0.0)) return 0.0;
+    double dh, dl, dx;
+    double ph = psi_entropy(u0, dc, thi, st, gamma, &dh);
+    if (ph >= 0.0) return thi;
+    double pl = psi_entropy(u0, dc, 0.0, st, gamma, &dl);
+    if (!(pl > 0.0)) return 0.0;
+    double lo = 0.0, hi = thi;
+    for (int it = 0; it < 16 && hi - lo > 1e-14; ++it) {
+        double c = lo + pl * (hi - lo) / (pl - ph);
+        double nw = dh < 0.0 ? hi - ph / dh : hi;
+        if (!(c > lo)) c = lo;
+        if (!(c < hi)) c = hi;
+        if (!(nw < hi)) nw = hi;
+        if (nw < c) nw = c;
+        double pc = psi_entropy(u0, dc, c, st, gamma, &dx);
+        if (pc >= 0.0) {
+            lo = c;
+            pl = pc;
+        } else {
+            hi = c;
+            ph = pc;
+            dh = dx;
+        }
+        if (nw < hi) {
+            double pn = psi_entropy(u0, dc, nw, st, gamma, &dx);
+            if (pn >= 0.0) {
+                if (nw > lo) {
+                    lo = nw;
+                    pl = pn;
+                }
+            } else {
+                hi = nw;
+                ph = pn;
+                dh = dx;
+            }
+        }
+    }
+    return lo;
 }
 
 int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
@@ -446,6 +632,14 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
     double* uFV = (double*)malloc(sizeof(double) * E * 4 * nn);
     double* rmin = (double*)malloc(sizeof(double) * E * nn);
     double* pmin = (double*)malloc(sizeof(double) * E * nn);
+    const int local = limiter == LIM_LOCAL;
+    double *rlo = 0, *rhi = 0, *smin = 0;
+    if (local) {
+        rlo = (double*)malloc(sizeof(double) * E * nn);
+        rhi = (double*)malloc(sizeof(double) * E * nn);
+        smin = (double*)malloc(sizeof(double) * E * nn);
+        dgo_local_bounds(m, u, gamma, rlo, rhi, smin);
+    }
     int64_t nfaces = 0;
     double alpha_sum = 0.0;
     int64_t inadm = 0, viol = 0;
@@ -469,6 +663,10 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 if (!(q[0] > 0.0) || !(p > 0.0)) inadm++;
                 rmin[e * nn + b * n + a] = beta * q[0];
                 pmin[e * nn + b * n + a] = beta * p;
+                /* local limiting keeps the positivity bounds as well: the
+                   density floor is the larger of the two */
+                if (local && rlo[e * nn + b * n + a] > rmin[e * nn + b * n + a])
+                    rmin[e * nn + b * n + a] = rlo[e * nn + b * n + a];
             }
         /* antidiffusive fluxes on interior subcell faces: telescoped high-order
            flux (eq. fluxdifferencingform) minus the low-order subcell flux */
@@ -514,14 +712,24 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 if (b < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ay[a][b][v]; nf++; }
                 double rt = rmin[e * nn + b * n + a] * BOUND_MARGIN;
                 double pt = pmin[e * nn + b * n + a] * BOUND_MARGIN;
-                double P = 0.0;
-                for (int j = 0; j < nf; ++j)
+                /* Zalesak: the sum of the negative (positive) density
+                   increments may use at most the distance to the lower (upper)
+                   bound */
+                double P = 0.0, Pp = 0.0;
+                for (int j = 0; j < nf; ++j) {
                     if (cf[j][0] < 0.0) P += cf[j][0];
+                    if (cf[j][0] > 0.0) Pp += cf[j][0];
+                }
                 double t = 1.0;
                 if (P < 0.0) {
                     double r = (rt - q[0]) / P;
                     t = r < 1.0 ? r : 1.0;
                     if (t < 0.0) t = 0.0;
+                }
+                if (local && Pp > 0.0) {
+                    double r = (rhi[e * nn + b * n + a] * BOUND_MARGIN_HI - q[0]) / Pp;
+                    if (r < 0.0) r = 0.0;
+                    if (r < t) t = r;
                 }
                 for (int j = 0; j < nf; ++j) {
                     double dc[4];
@@ -529,6 +737,13 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                     double tp = dgo_theta_pressure(q, dc, pt, gamma);
                     if (tp < t) t = tp;
                 }
+                /* entropy: per face on [0, t], increments scaled by Gamma = 4 */
+                if (local)
+                    for (int j = 0; j < nf; ++j) {
+                        double dc[4];
+                        for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
+                        t = dgo_theta_entropy(q, dc, smin[e * nn + b * n + a] * BOUND_MARGIN, gamma, t);
+                    }
                 th[b][a] = t;
             }
         /* per-face factor = min of its two nodes; limited volume update */
@@ -604,13 +819,22 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 }
                 double rt = rmin[e * nn + b * n + a] * BOUND_MARGIN;
                 double pt = pmin[e * nn + b * n + a] * BOUND_MARGIN;
+                /* this node's factor, then the minimum over the mortar's nodes */
+                double tn = 1.0;
                 if (dc[0] < 0.0) {
                     double r = (rt - q[0]) / dc[0];
                     if (r < 0.0) r = 0.0;
-                    if (r < t) t = r;
+                    if (r < tn) tn = r;
+                }
+                if (local && dc[0] > 0.0) {
+                    double r = (rhi[e * nn + b * n + a] * BOUND_MARGIN_HI - q[0]) / dc[0];
+                    if (r < 0.0) r = 0.0;
+                    if (r < tn) tn = r;
                 }
                 double tp = dgo_theta_pressure(q, dc, pt, gamma);
-                if (tp < t) t = tp;
+                if (tp < tn) tn = tp;
+                if (local) tn = dgo_theta_entropy(q, dc, smin[e * nn + b * n + a] * BOUND_MARGIN, gamma, tn);
+                if (tn < t) t = tn;
             }
             theta[S] = t;
             tmsum += 1.0 - t;
@@ -662,14 +886,22 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
             for (int a = 0; a < n; ++a) {
                 double q[4];
                 get_node(out, n, e, a, b, q);
-                if (q[0] < rmin[e * nn + b * n + a] || dgo_pressure(q, gamma) < pmin[e * nn + b * n + a] ||
-                    q[0] != q[0])
+                int64_t i = e * nn + b * n + a;
+                if (!local) {
+                    if (q[0] < rmin[i] || dgo_pressure(q, gamma) < pmin[i] || q[0] != q[0]) viol++;
+                } else if (!(q[0] >= rmin[i] * (1.0 - LOCAL_TOL)) || q[0] > rhi[i] * (1.0 + LOCAL_TOL) ||
+                           dgo_pressure(q, gamma) < pmin[i] ||
+                           dgo_spec_entropy(q, gamma) < smin[i] * (1.0 - LOCAL_TOL)) {
                     viol++;
+                }
             }
     st->violations = viol;
     free(uFV);
     free(rmin);
     free(pmin);
+    free(rlo);
+    free(rhi);
+    free(smin);
     free(HO);
     free(LO);
     return st->fv_inadmissible ? 1 : 0;
