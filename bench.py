@@ -99,9 +99,9 @@ def main():
     N = 3
     spec = workload_mesh("blast22k")
 
-    def run(precision):
+    def run(precision, limiter=P.LIMIT_POSITIVITY):
         s = P.Solver(N, gamma=1.4, beta=0.1, precision=precision, dt_mode=P.DT_IDP,
-                     limiter=P.LIMIT_POSITIVITY)
+                     limiter=limiter)
         s.set_mesh(*spec.args())
         x, y = s.node_coords()
         s.upload(states.workload_state("blast22k", x, y))
@@ -149,6 +149,15 @@ def main():
                     "ms_per_step": el_m / args.steps * 1e3, "kernel_ms": kmm["stage"],
                     "dtype": "f64 state and limiter, f32 volume fluxes and mortar projection",
                     "violations": stm["violations"]}
+    # the same workload with local limiting (eq. Bounds_Barstates: bar-state
+    # density and specific-entropy bounds on top of the positivity bounds), FP64
+    sl, el_l = run(P.FP64, P.LIMIT_LOCAL)
+    stl = sl.step(0.5, stats=True)
+    kml = sl.time_kernels(reps=50)
+    out["local"] = {"value": dofs * 3 * args.steps / el_l, "unit": "DOF-updates/s",
+                    "ms_per_step": el_l / args.steps * 1e3, "kernel_ms": kml["stage"],
+                    "dtype": "f64", "violations": stl["violations"],
+                    "alpha_vol_mean": stl["alpha_vol_mean"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, N)
     print(json.dumps(out), flush=True)

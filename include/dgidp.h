@@ -43,7 +43,7 @@ enum {
 
 enum { DGIDP_FP64 = 0, DGIDP_MIXED = 1 };           /* precision of the high-order fluxes */
 enum { DGIDP_DT_IDP = 0, DGIDP_DT_LOWORDER = 1 };   /* time-step rule */
-enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1 };
+enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1, DGIDP_LIMIT_LOCAL = 2 };
 enum { DGIDP_RHS_HIGH = 0, DGIDP_RHS_LOW = 1 };
 
 typedef struct dgidp_ctx dgidp_ctx;
@@ -58,8 +58,14 @@ typedef struct dgidp_ctx dgidp_ctx;
  *  dt_mode    DGIDP_DT_IDP (eq. timestep_restriction) or DGIDP_DT_LOWORDER
  *             (eq. CFLcondition_lowordermethod, constant of the standard
  *             DGSEM estimate: dt = CFL / max_i (N+1)(lambda_1/hx + lambda_2/hy))
- *  limiter    DGIDP_LIMIT_NONE (pure high order) or DGIDP_LIMIT_POSITIVITY
- *             (Sec. 2.3: volume then mortar convex limiting)
+ *  limiter    DGIDP_LIMIT_NONE (pure high order), DGIDP_LIMIT_POSITIVITY
+ *             (Sec. 2.3: volume then mortar convex limiting against
+ *             eq. Bounds_Positivity) or DGIDP_LIMIT_LOCAL (the same, plus the
+ *             local bounds of eq. Bounds_Barstates: per node the minimum and
+ *             maximum density and the minimum specific entropy p rho^-gamma
+ *             over the node and the bar states of its low-order neighbours,
+ *             taken from the stage's input state; the density floor is the
+ *             larger of the local and the positivity floor)
  *  strict_dt  if nonzero, dgidp_limit() rejects a dt above the IDP bound */
 typedef struct {
     int N;
@@ -76,7 +82,10 @@ typedef struct {
  * (Sec. 3 intro: alpha = 1 pure low order). */
 typedef struct {
     int64_t fv_inadmissible; /* nodes whose low-order update left rho > 0, p > 0 */
-    int64_t violations;      /* nodes below the rho / p bounds after limiting (tolerance 0) */
+    int64_t violations;      /* nodes outside the bounds after limiting: the positivity
+                                bounds with tolerance 0; the local bounds within a
+                                relative 1e-12 (the low-order state meets them only
+                                up to rounding) */
     double theta_vol_min;    /* smallest volume blending factor */
     double theta_mort_min;   /* smallest mortar blending factor */
     double alpha_vol_mean;   /* mean of 1 - theta over interior subcell faces */

@@ -386,10 +386,18 @@ double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, doub
    rounding of the final sums cannot cross the bounds themselves */
 #define BOUND_MARGIN (1.0 + 0x1p-40)
 #define BOUND_MARGIN_HI (1.0 - 0x1p-40)
+/* the mortar correction aims at half that margin: a node that the volume
+   limiter left on its target keeps 2^-41 of room, instead of a zero or one
+   mortar factor decided by the sign of a rounding error */
+#define MORTAR_MARGIN (1.0 + 0x1p-41)
+#define MORTAR_MARGIN_HI (1.0 - 0x1p-41)
 /* local bounds hold only up to rounding for the low-order state itself (it is
    a convex combination of bar states in exact arithmetic); the bound check
    allows this relative slack for them */
 #define LOCAL_TOL 1e-12
+/* density increments (per node and step) this small relative to the density are
+   not limited against the local density bounds */
+#define LOCAL_NEGL 1e-14
 
 /* largest theta in [0,1] with rho(u0 + theta dc) > 0 and p(u0 + theta dc) >= pt.
    With rho > 0, p >= pt  <=>  g(theta) = (E - pt/(gamma-1)) rho - |m|^2/2 >= 0,
@@ -556,8 +564,10 @@ static double psi_entropy(const double* u0, const double* dc, double th, double 
    (concavity), the Newton step from the infeasible end at or above it (the
    tangent lies above psi).  This is the two-sided iteration used for convex
    limiting by Guermond, Nazarov, Popov and Tomas (SIAM J. Sci. Comput. 2018).
-   Returns the feasible end once the bracket is below 1e-14 (at most 16
-   rounds); psi(0) <= 0 returns 0. */
+   When the two estimates are within 1e-14 of each other (or cross by rounding)
+   it returns the chord point, theta* up to rounding; otherwise it stops when
+   the bracket is that narrow, at most 16 rounds, and returns the feasible end;
+   psi(0) <= 0 returns 0. */
 double dgo_theta_entropy(const double* u0, const double* dc, double st, double gamma, double thi)
 {
     if (!(thi > 0.0)) return 0.0;
@@ -567,7 +577,7 @@ double dgo_theta_entropy(const double* u0, const double* dc, double st, double g
     double pl = psi_entropy(u0, dc, 0.0, st, gamma, &dl);
     if (!(pl > 0.0)) return 0.0;
     double lo = 0.0, hi = thi;
-    for (int it = 0; it < 16 && hi - lo > 1e-14; ++it) {
+    for (int it = 0; it < 16; ++it) {
         double c = lo + pl * (hi - lo) / (pl - ph);
         double nw = dh < 0.0 ? hi - ph / dh : hi;
         if (!(c > lo)) c = lo;
@@ -583,19 +593,20 @@ double dgo_theta_entropy(const double* u0, const double* dc, double st, double g
             ph = pc;
             dh = dx;
         }
-        if (nw < hi) {
-            double pn = psi_entropy(u0, dc, nw, st, gamma, &dx);
-            if (pn >= 0.0) {
-                if (nw > lo) {
-                    lo = nw;
-                    pl = pn;
-                }
-            } else {
-                hi = nw;
-                ph = pn;
-                dh = dx;
+        // the estimates meet: c is theta* up to rounding
+        if (nw - c <= 1e-14) return c;
+        double pn = psi_entropy(u0, dc, nw, st, gamma, &dx);
+        if (pn >= 0.0) {
+            if (nw > lo) {
+                lo = nw;
+                pl = pn;
             }
+        } else if (nw < hi) {
+            hi = nw;
+            ph = pn;
+            dh = dx;
         }
+        if (hi - lo <= 1e-14) break;
     }
     return lo;
 }
@@ -721,6 +732,12 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                     if (cf[j][0] > 0.0) Pp += cf[j][0];
                 }
                 double t = 1.0;
+                /* local bounds: increments below 1e-14 of the density are
+                   rounding noise and are not limited (a node whose density
+                   interval has zero width would otherwise switch between
+                   theta = 0 and 1 on the sign of a rounding error) */
+                if (local && P > -LOCAL_NEGL * q[0]) P = 0.0;
+                if (local && Pp < LOCAL_NEGL * q[0]) Pp = 0.0;
                 if (P < 0.0) {
                     double r = (rt - q[0]) / P;
                     t = r < 1.0 ? r : 1.0;
@@ -817,23 +834,24 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                     t = 0.0;
                     continue;
                 }
-                double rt = rmin[e * nn + b * n + a] * BOUND_MARGIN;
-                double pt = pmin[e * nn + b * n + a] * BOUND_MARGIN;
+                double rt = rmin[e * nn + b * n + a] * MORTAR_MARGIN;
+                double pt = pmin[e * nn + b * n + a] * MORTAR_MARGIN;
                 /* this node's factor, then the minimum over the mortar's nodes */
                 double tn = 1.0;
-                if (dc[0] < 0.0) {
+                const int negl = local && fabs(dc[0]) <= LOCAL_NEGL * q[0];
+                if (dc[0] < 0.0 && !negl) {
                     double r = (rt - q[0]) / dc[0];
                     if (r < 0.0) r = 0.0;
                     if (r < tn) tn = r;
                 }
-                if (local && dc[0] > 0.0) {
-                    double r = (rhi[e * nn + b * n + a] * BOUND_MARGIN_HI - q[0]) / dc[0];
+                if (local && dc[0] > 0.0 && !negl) {
+                    double r = (rhi[e * nn + b * n + a] * MORTAR_MARGIN_HI - q[0]) / dc[0];
                     if (r < 0.0) r = 0.0;
                     if (r < tn) tn = r;
                 }
                 double tp = dgo_theta_pressure(q, dc, pt, gamma);
                 if (tp < tn) tn = tp;
-                if (local) tn = dgo_theta_entropy(q, dc, smin[e * nn + b * n + a] * BOUND_MARGIN, gamma, tn);
+                if (local) tn = dgo_theta_entropy(q, dc, smin[e * nn + b * n + a] * MORTAR_MARGIN, gamma, tn);
                 if (tn < t) t = tn;
             }
             theta[S] = t;

@@ -384,7 +384,8 @@ int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
     if (!(p->gamma > 1.0) || !(p->beta >= 0.0 && p->beta < 1.0) ||
         (p->precision != DGIDP_FP64 && p->precision != DGIDP_MIXED) ||
         (p->dt_mode != DGIDP_DT_IDP && p->dt_mode != DGIDP_DT_LOWORDER) ||
-        (p->limiter != DGIDP_LIMIT_NONE && p->limiter != DGIDP_LIMIT_POSITIVITY))
+        (p->limiter != DGIDP_LIMIT_NONE && p->limiter != DGIDP_LIMIT_POSITIVITY &&
+         p->limiter != DGIDP_LIMIT_LOCAL))
         return DGIDP_E_INVALID_ARG;
     dgidp_ctx* ctx = new dgidp_ctx();
     ctx->p = *p;

@@ -12,7 +12,7 @@
 namespace dgidp {
 
 constexpr int kMaxN = 4;
-constexpr int kSlotW = 12;  // doubles per mortar slot record
+constexpr int kSlotW = 16;  // doubles per mortar slot record
 // elements per block of the stage kernel (the host orders elements per the
 // kernel's block-to-XCD mapping)
 constexpr int stage_block_elems(int N) { return N == 3 ? 4 : 7; }

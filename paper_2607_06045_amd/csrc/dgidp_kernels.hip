@@ -268,6 +268,129 @@ __device__ __forceinline__ double theta_p(const double* u0, const double* dc, do
 // the limiter aims at the bounds raised by this relative margin so that the
 // rounding of the final sums cannot cross the bounds themselves
 constexpr double kMargin = 1.0 + 0x1p-40;
+constexpr double kMarginHi = 1.0 - 0x1p-40;  // the same for upper bounds
+// the mortar correction aims at half that margin: a node that the volume
+// limiter left on its target keeps 2^-41 of room, instead of a zero or one
+// mortar factor decided by the sign of a rounding error
+constexpr double kMarginMortar = 1.0 + 0x1p-41;
+constexpr double kMarginMortarHi = 1.0 - 0x1p-41;
+// the local bounds hold for the low-order state only up to rounding (it is a
+// convex combination of bar states in exact arithmetic): the bound check allows
+// this relative slack for them
+constexpr double kLocalTol = 1e-12;
+// density increments (per node and step) this small relative to the density are
+// not limited against the local density bounds
+constexpr double kLocalNegl = 1e-14;
+
+// ---------------------------------------------------------------------------
+// local bounds (eq. Bounds_Barstates)
+// ---------------------------------------------------------------------------
+// Density and log specific entropy ln(p rho^-gamma) of the bar state of the
+// low-order graph edge between this element's node `own` and the node `o`
+// across a face of direction d (own_low: `own` on the low side).  The bar state
+// (u_i + u_j)/2 - c_ij . (f_j - f_i) / (2 d_ij) with d_ij = |c_ij| lambda_ij is
+// (u_L + u_R)/2 - (f(u_R) - f(u_L)) / (2 lambda), lambda as in llf_face.  A bar
+// state outside the admissible set (only by rounding) gives -inf: no entropy
+// bound from it.
+__device__ __forceinline__ void bar_bounds(int d, bool own_low, const NodeP& own, const NodeP& o,
+                                           double g, double& rb, double& lsb)
+{
+    const bool dx = d == 0;
+    const double va = dx ? own.v1 : own.v2, vb = dx ? o.v1 : o.v2;
+    const double lam = fmax(fabs(va) + own.c, fabs(vb) + o.c);
+    const double k = (own_low ? 0.5 : -0.5) * frcp(lam);
+    double fa[4], fb[4];
+    fa[0] = own.r * va;
+    fa[1] = own.u[1] * va + (dx ? own.p : 0.0);
+    fa[2] = own.u[2] * va + (dx ? 0.0 : own.p);
+    fa[3] = (own.u[3] + own.p) * va;
+    fb[0] = o.r * vb;
+    fb[1] = o.u[1] * vb + (dx ? o.p : 0.0);
+    fb[2] = o.u[2] * vb + (dx ? 0.0 : o.p);
+    fb[3] = (o.u[3] + o.p) * vb;
+    double ub[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ub[v] = 0.5 * (own.u[v] + o.u[v]) - k * (fb[v] - fa[v]);
+    rb = ub[0];
+    const double pb = (g - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+    lsb = (rb > 0.0 && pb > 0.0) ? log(pb) - g * log(rb) : -__builtin_inf();
+}
+
+// psi(theta) = p(u0 + theta dc) - exp(lst + gamma ln rho(theta)) and its
+// derivative: psi >= 0 with rho > 0 is p rho^-gamma >= exp(lst).  p is concave
+// in the conserved variables and rho^gamma convex, so psi is concave on the ray.
+__device__ __forceinline__ double psi_s(const double* u0, const double* dc, double th, double lst,
+                                        double g, double& dpsi)
+{
+    const double q0 = u0[0] + th * dc[0], q1 = u0[1] + th * dc[1];
+    const double q2 = u0[2] + th * dc[2], q3 = u0[3] + th * dc[3];
+    if (!(q0 > 0.0)) {
+        dpsi = 0.0;
+        return -__builtin_inf();
+    }
+    const double ir = 1.0 / q0;
+    const double v1 = q1 * ir, v2 = q2 * ir;
+    const double p = (g - 1.0) * (q3 - 0.5 * (q1 * v1 + q2 * v2));
+    const double rg = exp(lst + g * log(q0));
+    const double dp = (g - 1.0) * (dc[3] - v1 * dc[1] - v2 * dc[2] + 0.5 * (v1 * v1 + v2 * v2) * dc[0]);
+    dpsi = dp - g * rg * ir * dc[0];
+    return p - rg;
+}
+
+// Largest theta in [0, thi] with p rho^-gamma >= exp(lst) at u0 + theta dc, on
+// a ray where rho stays positive up to thi.  The admissible set of the concave
+// psi is an interval [0, theta*] when psi(0) >= 0.  The root is bracketed from
+// both sides: the chord through the feasible and the infeasible end cuts the
+// axis at or below theta* (concavity), the Newton step from the infeasible end
+// at or above it (the tangent lies above psi); the two-sided iteration of
+// convex limiting (Guermond, Nazarov, Popov and Tomas, SIAM J. Sci. Comput.
+// 2018).  When the two estimates are within 1e-14 (or cross by rounding) it
+// returns the chord point, theta* up to rounding; otherwise it stops when the
+// bracket is that narrow, at most 16 rounds, and returns the feasible end;
+// psi(0) <= 0 returns 0.
+__device__ double theta_s(const double* u0, const double* dc, double lst, double g, double thi)
+{
+    if (!(thi > 0.0)) return 0.0;
+    double dh, dl, dx;
+    double ph = psi_s(u0, dc, thi, lst, g, dh);
+    if (ph >= 0.0) return thi;
+    double pl = psi_s(u0, dc, 0.0, lst, g, dl);
+    if (!(pl > 0.0)) return 0.0;
+    double lo = 0.0, hi = thi;
+#pragma unroll 1
+    for (int it = 0; it < 16; ++it) {
+        double c = lo + pl * (hi - lo) / (pl - ph);
+        double nw = dh < 0.0 ? hi - ph / dh : hi;
+        if (!(c > lo)) c = lo;
+        if (!(c < hi)) c = hi;
+        if (!(nw < hi)) nw = hi;
+        if (nw < c) nw = c;
+        const double pc = psi_s(u0, dc, c, lst, g, dx);
+        if (pc >= 0.0) {
+            lo = c;
+            pl = pc;
+        } else {
+            hi = c;
+            ph = pc;
+            dh = dx;
+        }
+        // the estimates meet: c is theta* up to rounding
+        if (nw - c <= 1e-14) return c;
+        const double pn = psi_s(u0, dc, nw, lst, g, dx);
+        if (pn >= 0.0) {
+            if (nw > lo) {
+                lo = nw;
+                pl = pn;
+            }
+        } else if (nw < hi) {
+            hi = nw;
+            ph = pn;
+            dh = dx;
+        }
+        if (hi - lo <= 1e-14) break;
+    }
+    return lo;
+}
 
 // ---------------------------------------------------------------------------
 // statistics
@@ -400,7 +523,7 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
         X.c = sR[le][4][qq];                              \
     } while (0)
 
-template <int N, int MODE, bool MIXED>
+template <int N, int MODE, bool MIXED, bool LOC>
 __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
 {
     using G = Geo<N>;
@@ -441,6 +564,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     // until phase 5 frees sU, which then carries it to the node's own thread
     double fterm[4] = {0, 0, 0, 0};
     bool blk_mortar = false;
+    // local bounds: own log entropy; for face lanes the density range and the
+    // smallest log entropy of the bar states across this lane's face node
+    double ls_own = 0.0;
+    double fb_lo = __builtin_inf(), fb_hi = -__builtin_inf(), fb_ls = __builtin_inf();
     const double dtpart =
         A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
     // Sbar of this thread's volume pairs, loaded with the state so that the
@@ -484,7 +611,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
         sR[le][4][q] = me.c;
         sR[le][5][q] = lr;
         sR[le][6][q] = z;
-        sR[le][7][q] = MIXED ? (double)__logf((float)z) : log(z);
+        const double lz = MIXED ? (double)__logf((float)z) : log(z);
+        sR[le][7][q] = lz;
+        // ln(p rho^-gamma) of the node itself, the bar state (i, i)
+        if (LOC) ls_own = MIXED ? log(me.p) - g * log(me.r) : (1.0 - g) * lr - lz;
         if (fnode) {
             fcode_f = fcode[ff];
             if (fcode_f < 0) {
@@ -539,6 +669,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             make_node(o, g);
             double F[4];
             llf_face(dff, lowf, own, o, F);
+            if (LOC) {
+                bar_bounds(dff, lowf, own, o, g, fb_lo, fb_ls);
+                fb_hi = fb_lo;
+            }
             const double W = sgf * pick(tb.w, fk) * hff * 0.5;
 #pragma unroll
             for (int v = 0; v < 4; ++v) fterm[v] = W * F[v];
@@ -587,6 +721,13 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                     make_node(us, g);
                     double Gf[4];
                     llf_face(dff, lowf, own, us, Gf);
+                    if (LOC) {
+                        double rb, lb;
+                        bar_bounds(dff, lowf, own, us, g, rb, lb);
+                        fb_lo = fmin(fb_lo, rb);
+                        fb_hi = fmax(fb_hi, rb);
+                        fb_ls = fmin(fb_ls, lb);
+                    }
                     const double W = sgf * wt * hff * 0.5;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
@@ -626,6 +767,13 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                 make_node(uj, g);
                 double Gf[4];
                 llf_face(dff, lowf, own, uj, Gf);
+                if (LOC) {
+                    double rb, lb;
+                    bar_bounds(dff, lowf, own, uj, g, rb, lb);
+                    fb_lo = fmin(fb_lo, rb);
+                    fb_hi = fmax(fb_hi, rb);
+                    fb_ls = fmin(fb_ls, lb);
+                }
                 const double W = sgf * wt * hff;  // wt * h_L / 2 with h_L = 2 h
 #pragma unroll
                 for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
@@ -734,6 +882,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
 
     // ---- phase 5: subcell faces owned by this node: x (a|a+1) and y (b|b+1) ----
     double FVo[2][4], Ao[2][4];
+    double brb[2] = {0.0, 0.0}, bls[2] = {0.0, 0.0};  // bar state of each owned subcell face
     if (act) {
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
@@ -756,6 +905,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             LDS_NODE(me, q);
             double F[4];
             llf_face(d, true, me, o, F);
+            if (LOC) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
             const double hs = 0.5 * (d == 0 ? hy : hx), wl = pick(tb.w, line);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -787,6 +937,24 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     if (fnode) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) sU[le][v][q] = fterm[v];
+    }
+    // sR rows 1..7 are no longer read: rows 1-4 take the bar states of the
+    // subcell faces owned by this node (x: density, log entropy; y: the same),
+    // rows 5-7 the face lanes' bar-state range across the element face
+    if (LOC && act) {
+        if (a < N) {
+            sR[le][1][q] = brb[0];
+            sR[le][2][q] = bls[0];
+        }
+        if (b < N) {
+            sR[le][3][q] = brb[1];
+            sR[le][4][q] = bls[1];
+        }
+        if (fnode) {
+            sR[le][5][q] = fb_lo;
+            sR[le][6][q] = fb_hi;
+            sR[le][7][q] = fb_ls;
+        }
     }
     __syncthreads();
 
@@ -854,6 +1022,7 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
     const double dtm = dt * im;
     double uFV[4], cf[4][4];
     double rmin = 0.0, pmin = 0.0, th = 1.0;
+    double rhi = 0.0, lsm = 0.0;  // local bounds: density maximum, log entropy minimum
     unsigned long long inad = 0;
     if (act) {
 #pragma unroll
@@ -862,6 +1031,41 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
         if (!(uFV[0] > 0.0) || !(pFV > 0.0)) inad = 1;
         rmin = A.beta * uFV[0];
         pmin = A.beta * pFV;
+        if (LOC) {
+            // bounds over the node and the bar states of its low-order neighbours
+            double rlo = u0[0];
+            rhi = u0[0];
+            lsm = ls_own;
+            if (a > 0) {
+                rlo = fmin(rlo, sR[le][1][q - 1]);
+                rhi = fmax(rhi, sR[le][1][q - 1]);
+                lsm = fmin(lsm, sR[le][2][q - 1]);
+            }
+            if (a < N) {
+                rlo = fmin(rlo, sR[le][1][q]);
+                rhi = fmax(rhi, sR[le][1][q]);
+                lsm = fmin(lsm, sR[le][2][q]);
+            }
+            if (b > 0) {
+                rlo = fmin(rlo, sR[le][3][q - n]);
+                rhi = fmax(rhi, sR[le][3][q - n]);
+                lsm = fmin(lsm, sR[le][4][q - n]);
+            }
+            if (b < N) {
+                rlo = fmin(rlo, sR[le][3][q]);
+                rhi = fmax(rhi, sR[le][3][q]);
+                lsm = fmin(lsm, sR[le][4][q]);
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                if (!onf[f]) continue;
+                rlo = fmin(rlo, sR[le][5][fnq[f]]);
+                rhi = fmax(rhi, sR[le][6][fnq[f]]);
+                lsm = fmin(lsm, sR[le][7][fnq[f]]);
+            }
+            // the positivity floor stays: the density floor is the larger one
+            rmin = fmax(rmin, rlo);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             cf[0][v] = a > 0 ? dtm * sPair[le][v][NF + fxl] : 0.0;
@@ -872,16 +1076,37 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
         if (A.limiter != DGIDP_LIMIT_NONE) {
             // Zalesak-type factor for the density: sum of the negative increments
             const double rt = rmin * kMargin, pt = pmin * kMargin;
-            double P = 0.0;
+            double P = 0.0, Pp = 0.0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) P += fmin(cf[j][0], 0.0);
+            for (int j = 0; j < 4; ++j) {
+                P += fmin(cf[j][0], 0.0);
+                if (LOC) Pp += fmax(cf[j][0], 0.0);
+            }
+            // local bounds: increments below kLocalNegl of the density are rounding
+            // noise and are not limited (a node whose density interval has zero
+            // width would otherwise switch between theta = 0 and 1 on the sign of
+            // a rounding error)
+            if (LOC && P > -kLocalNegl * uFV[0]) P = 0.0;
+            if (LOC && Pp < kLocalNegl * uFV[0]) Pp = 0.0;
             if (P < 0.0) th = fmax(fmin((rt - uFV[0]) / P, 1.0), 0.0);
+            // and the sum of the positive ones at most the distance to the maximum
+            if (LOC && Pp > 0.0) th = fmin(th, fmax((rhi * kMarginHi - uFV[0]) / Pp, 0.0));
             // pressure: each face's increment scaled by Gamma = 2d = 4
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
                 if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
                 th = fmin(th, theta_p(uFV, dc, pt, ig1));
+            }
+            // specific entropy: per face on [0, th], increments scaled by Gamma = 4
+            if (LOC) {
+                const double lst = lsm + 0x1p-40;  // ln(s_min (1 + 2^-40))
+#pragma unroll 1
+                for (int j = 0; j < 4; ++j) {
+                    const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
+                    if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
+                    th = theta_s(uFV, dc, lst, g, th);
+                }
             }
         }
         sTh(q) = th;
@@ -919,11 +1144,17 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
             A.uout[idx] = r;
         }
         if (nmf == 0) {
-            if (A.limiter != DGIDP_LIMIT_NONE &&
-                (uvol[0] < rmin || pressure(uvol, g) < pmin || uvol[0] != uvol[0]))
+            if (LOC) {
+                if (A.st && (!(uvol[0] >= rmin * (1.0 - kLocalTol)) || uvol[0] > rhi * (1.0 + kLocalTol) ||
+                             pressure(uvol, g) < pmin ||
+                             !(log(pressure(uvol, g)) - g * log(uvol[0]) >= lsm - kLocalTol)))
+                    viol = 1;
+            } else if (A.limiter != DGIDP_LIMIT_NONE &&
+                       (uvol[0] < rmin || pressure(uvol, g) < pmin || uvol[0] != uvol[0])) {
                 viol = 1;
+            }
         } else {
-            const double rt = rmin * kMargin, pt = pmin * kMargin;
+            const double rt = rmin * kMarginMortar, pt = pmin * kMarginMortar;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (j >= nmf) break;
@@ -942,8 +1173,11 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                     if (!fin) {
                         ts = 0.0;
                     } else {
-                        if (dc[0] < 0.0) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
+                        const bool negl = LOC && fabs(dc[0]) <= kLocalNegl * uvol[0];
+                        if (dc[0] < 0.0 && !negl) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
+                        if (LOC && dc[0] > 0.0 && !negl) ts = fmin(ts, fmax((rhi * kMarginMortarHi - uvol[0]) / dc[0], 0.0));
                         ts = fmin(ts, theta_p(uvol, dc, pt, ig1));
+                        if (LOC) ts = theta_s(uvol, dc, lsm + 0x1p-41, g, ts);
                     }
                 }
                 double* S = A.slot + (size_t)(j == 0 ? slot0 : slot1) * kSlotW;
@@ -955,6 +1189,10 @@ __global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
                 S[8] = ts;
                 S[9] = rmin;
                 S[10] = pmin;
+                if (LOC) {
+                    S[11] = rhi;
+                    S[12] = lsm;
+                }
             }
         }
     }
@@ -1022,9 +1260,16 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
                 uout[((size_t)e * 4 + v) * NN + q] = uo[v] + bcoef * corr[v];
                 w[v] = rec[v] + corr[v];
             }
-            if (limiter != DGIDP_LIMIT_NONE &&
-                (w[0] < rec[9] || pressure(w, gamma) < rec[10] || w[0] != w[0]))
+            if (limiter == DGIDP_LIMIT_LOCAL) {
+                const double rhi = R[11], lsm = R[12];
+                const double pw = pressure(w, gamma);
+                if (!(w[0] >= rec[9] * (1.0 - kLocalTol)) || w[0] > rhi * (1.0 + kLocalTol) ||
+                    pw < rec[10] || !(log(pw) - gamma * log(w[0]) >= lsm - kLocalTol))
+                    viol = 1;
+            } else if (limiter != DGIDP_LIMIT_NONE &&
+                       (w[0] < rec[9] || pressure(w, gamma) < rec[10] || w[0] != w[0])) {
                 viol = 1;
+            }
         }
     }
     if (st) push_stats(st, 0, viol, thmin, asum, nm, true);
@@ -1510,14 +1755,20 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     const int grid = (m.E + G::EPB - 1) / G::EPB;
     const bool mixed = kp.precision == DGIDP_MIXED;
     const dim3 blk(G::BS);
+    const bool loc = kp.limiter == DGIDP_LIMIT_LOCAL;
     if (mode == MODE_STAGE) {
-        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true>), dim3(grid), blk, 0, s, A);
-        else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false>), dim3(grid), blk, 0, s, A);
+        if (loc) {
+            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, true>), dim3(grid), blk, 0, s, A);
+            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, true>), dim3(grid), blk, 0, s, A);
+        } else {
+            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, false>), dim3(grid), blk, 0, s, A);
+            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, false>), dim3(grid), blk, 0, s, A);
+        }
     } else if (mode == MODE_RHS_HIGH) {
-        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true>), dim3(grid), blk, 0, s, A);
-        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false>), dim3(grid), blk, 0, s, A);
+        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true, false>), dim3(grid), blk, 0, s, A);
+        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false, false>), dim3(grid), blk, 0, s, A);
     } else {
-        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false>), dim3(grid), blk, 0, s, A);
+        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false, false>), dim3(grid), blk, 0, s, A);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
