@@ -524,7 +524,10 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
     } while (0)
 
 template <int N, int MODE, bool MIXED, bool LOC>
-__global__ __launch_bounds__(Geo<N>::BS) void k_stage(StageArgs A)
+// at least three waves per SIMD: the local-limiting variant would otherwise
+// take 172 registers and run two (63.3 against 67.7 us on the 22,156-leaf
+// blast with a few spilled registers; the other variants fit anyway)
+__global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
 {
     using G = Geo<N>;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
