@@ -20,7 +20,7 @@ _lib = None
 
 RHS_HIGH, RHS_LOW = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
-LIM_NONE, LIM_POSITIVITY, LIM_LOCAL = 0, 1, 2
+LIM_NONE, LIM_POSITIVITY, LIM_LOCAL, LIM_COMBINED = 0, 1, 2, 3
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
@@ -81,6 +81,9 @@ def lib():
         L.orc_theta_entropy.restype = ctypes.c_double
         L.orc_theta_entropy.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_local_bounds.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D, _D, _D]
+        L.orc_shock_indicator.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D]
+        L.orc_fe_step_ind.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, _D, _D, _D]
         L.orc_set_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -278,11 +281,26 @@ class Mesh:
         lib().orc_local_bounds(self._h, _ptr(u), gamma, _ptr(lo), _ptr(hi), _ptr(sm))
         return lo, hi, sm
 
-    def fe_step(self, u, dt, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
+    def shock_indicator(self, u, gamma=1.4):
+        """Per-element Hennemann indicator on the pressure, in [0, 1] (the weight of
+        the local factors in combined limiting)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        out = np.zeros(self.E)
+        lib().orc_shock_indicator(self._h, _ptr(u), gamma, _ptr(out))
+        return out
+
+    def fe_step(self, u, dt, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY, indicator=None):
+        """One limited forward-Euler step; for LIM_COMBINED `indicator` (per
+        element) replaces the computed shock indicator when given."""
         u = np.ascontiguousarray(u, dtype=np.float64)
         out = np.zeros_like(u)
         st = np.zeros(len(STAT_KEYS))
-        rc = lib().orc_fe_step(self._h, _ptr(u), dt, gamma, beta, limiter, _ptr(out), _ptr(st))
+        if indicator is not None:
+            ind = np.ascontiguousarray(indicator, dtype=np.float64)
+            rc = lib().orc_fe_step_ind(self._h, _ptr(u), dt, gamma, beta, limiter, _ptr(ind),
+                                       _ptr(out), _ptr(st))
+        else:
+            rc = lib().orc_fe_step(self._h, _ptr(u), dt, gamma, beta, limiter, _ptr(out), _ptr(st))
         d = _stats(st)
         d["rc"] = rc
         return out, d

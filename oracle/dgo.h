@@ -92,7 +92,7 @@ typedef struct {
 
 enum { RHS_HIGH = 0, RHS_LOW = 1 };
 enum { DT_IDP = 0, DT_LOWORDER = 1 };
-enum { LIM_NONE = 0, LIM_POSITIVITY = 1, LIM_LOCAL = 2 };
+enum { LIM_NONE = 0, LIM_POSITIVITY = 1, LIM_LOCAL = 2, LIM_COMBINED = 3 };
 
 int dgo_rhs(const dgo_mesh* m, const double* u, int which, double gamma, double* du);
 double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, double gamma);
@@ -107,6 +107,12 @@ double dgo_spec_entropy(const double* u, double gamma);
 void dgo_local_bounds(const dgo_mesh* m, const double* u, double gamma, double* rlo, double* rhi,
                       double* smin);
 double dgo_theta_entropy(const double* u0, const double* dc, double st, double gamma, double thi);
+/* combined limiting (eq. combination_posLim_local): per-element shock
+   indicator on the pressure in [0, 1]; a FE step with the indicator given
+   (NULL: computed from u) */
+void dgo_shock_indicator(const dgo_mesh* m, const double* u, double gamma, double* ind);
+int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
+                    int limiter, const double* ind, double* out, dgo_stats* st);
 int dgo_ssprk3_dt(const dgo_mesh* m, double* u, double dt, double gamma, double beta, int limiter,
                   dgo_stats* st);
 

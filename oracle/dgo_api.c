@@ -205,6 +205,20 @@ void orc_local_bounds(void* h, const double* u, double gamma, double* rlo, doubl
     dgo_local_bounds((dgo_mesh*)h, u, gamma, rlo, rhi, smin);
 }
 
+void orc_shock_indicator(void* h, const double* u, double gamma, double* ind)
+{
+    dgo_shock_indicator((dgo_mesh*)h, u, gamma, ind);
+}
+
+int orc_fe_step_ind(void* h, const double* u, double dt, double gamma, double beta, int limiter,
+                    const double* ind, double* out, double* stats)
+{
+    dgo_stats s;
+    int rc = dgo_fe_step_ind((dgo_mesh*)h, u, dt, gamma, beta, limiter, ind, out, &s);
+    pack(&s, stats);
+    return rc;
+}
+
 int orc_set_threads(int t)
 {
 #ifdef _OPENMP

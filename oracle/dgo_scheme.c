@@ -18,7 +18,9 @@
  *  factor per subcell face, then the mortar correction with one factor per
  *  mortar, against the positivity bounds of eq. Bounds_Positivity, and with
  *  local limiting also against the bar-state bounds of eq. Bounds_Barstates
- *  (density minimum and maximum, minimum of the specific entropy).
+ *  (density minimum and maximum, minimum of the specific entropy), and with
+ *  combined limiting (eq. combination_posLim_local) both factor sets blended
+ *  per element by a shock indicator on the pressure.
  *  Time integration: three-stage SSP Runge-Kutta (Shu & Osher 1988, Sec. 3).
  */
 #include <math.h>
@@ -611,8 +613,152 @@ double dgo_theta_entropy(const double* u0, const double* dc, double st, double g
     return lo;
 }
 
+/* ---------------------------------------------------------------------------
+ * shock indicator for combined limiting (Sec. 3.5, eq. combination_posLim_local)
+ * ------------------------------------------------------------------------- */
+
+/* Per element: the Hennemann indicator on the pressure.  The nodal pressure is
+   expanded in orthonormal Legendre modes m_ij (the inverse of interpolation at
+   the LGL nodes); energy = max of the energy fractions of the highest mode
+   shell and of the second-highest shell within the modes up to N-1; alpha =
+   1 / (1 + exp(-(s/T)(energy - T))), T = 0.5 10^(-1.8 (N+1)^(1/4)),
+   s = ln(9999); values below 1e-3 become 0.  Not capped: alpha in [0, 1]. */
+void dgo_shock_indicator(const dgo_mesh* m, const double* u, double gamma, double* ind)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    /* V[a][i] = sqrt((2i+1)/2) L_i(xi_a); Vi = V^-1 by Gauss-Jordan elimination */
+    double V[DGO_NMAX][2 * DGO_NMAX], Vi[DGO_NMAX][DGO_NMAX];
+    for (int a = 0; a < n; ++a)
+        for (int i = 0; i < 2 * n; ++i)
+            V[a][i] = i < n ? sqrt((2.0 * i + 1.0) / 2.0) * dgo_legendre(i, B->xi[a]) : (i - n == a ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(V[r][c]) > fabs(V[piv][c])) piv = r;
+        for (int k = 0; k < 2 * n; ++k) {
+            double t = V[c][k];
+            V[c][k] = V[piv][k];
+            V[piv][k] = t;
+        }
+        double d = V[c][c];
+        for (int k = 0; k < 2 * n; ++k) V[c][k] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double f = V[r][c];
+            for (int k = 0; k < 2 * n; ++k) V[r][k] -= f * V[c][k];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < n; ++a) Vi[i][a] = V[i][n + a];
+    double T = 0.5 * pow(10.0, -1.8 * pow(N + 1.0, 0.25));
+    double sharp = log((1.0 - 1e-4) / 1e-4);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < m->E; ++e) {
+        double pq[DGO_NMAX][DGO_NMAX]; /* [b][a] */
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double q[4];
+                get_node(u, n, e, a, b, q);
+                pq[b][a] = dgo_pressure(q, gamma);
+            }
+        double all = 0.0, low1 = 0.0, low2 = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double mij = 0.0;
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) mij += Vi[i][a] * Vi[j][b] * pq[b][a];
+                double m2 = mij * mij;
+                all += m2;
+                if (i < N && j < N) low1 += m2;
+                if (i < N - 1 && j < N - 1) low2 += m2;
+            }
+        double en1 = (all - low1) / all, en2 = (low1 - low2) / low1;
+        double en = en1 > en2 ? en1 : en2;
+        double al = 1.0 / (1.0 + exp(-(sharp / T) * (en - T)));
+        ind[e] = al < 1e-3 ? 0.0 : al;
+    }
+}
+
+/* Node factor of the volume limiter from the node's face increments cf (nf of
+   them, dt/m_i-scaled): Zalesak factors for the density floor (and, with loc,
+   the ceiling), the pressure root per face and, with loc, the entropy root per
+   face, the last two on Gamma = 4-scaled increments. */
+static double volume_node_factor(const double* q, double cf[4][4], int nf, double rfloor, double pfloor,
+                                 int loc, double rceil, double sm, double gamma)
+{
+    double rt = rfloor * BOUND_MARGIN, pt = pfloor * BOUND_MARGIN;
+    /* Zalesak: the sum of the negative (positive) density increments may use
+       at most the distance to the lower (upper) bound */
+    double P = 0.0, Pp = 0.0;
+    for (int j = 0; j < nf; ++j) {
+        if (cf[j][0] < 0.0) P += cf[j][0];
+        if (cf[j][0] > 0.0) Pp += cf[j][0];
+    }
+    double t = 1.0;
+    /* local bounds: increments below 1e-14 of the density are rounding noise
+       and are not limited (a node whose density interval has zero width would
+       otherwise switch between theta = 0 and 1 on the sign of a rounding error) */
+    if (loc && P > -LOCAL_NEGL * q[0]) P = 0.0;
+    if (loc && Pp < LOCAL_NEGL * q[0]) Pp = 0.0;
+    if (P < 0.0) {
+        double r = (rt - q[0]) / P;
+        t = r < 1.0 ? r : 1.0;
+        if (t < 0.0) t = 0.0;
+    }
+    if (loc && Pp > 0.0) {
+        double r = (rceil * BOUND_MARGIN_HI - q[0]) / Pp;
+        if (r < 0.0) r = 0.0;
+        if (r < t) t = r;
+    }
+    for (int j = 0; j < nf; ++j) {
+        double dc[4];
+        for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
+        double tp = dgo_theta_pressure(q, dc, pt, gamma);
+        if (tp < t) t = tp;
+    }
+    /* entropy: per face on [0, t] */
+    if (loc)
+        for (int j = 0; j < nf; ++j) {
+            double dc[4];
+            for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
+            t = dgo_theta_entropy(q, dc, sm * BOUND_MARGIN, gamma, t);
+        }
+    return t;
+}
+
+/* Factor of one mortar node with its n_i-scaled increment dc: density floor
+   (and ceiling), pressure root, entropy root, against half the volume margin. */
+static double mortar_node_factor(const double* q, const double* dc, double rfloor, double pfloor, int loc,
+                                 double rceil, double sm, double gamma)
+{
+    double rt = rfloor * MORTAR_MARGIN, pt = pfloor * MORTAR_MARGIN;
+    double tn = 1.0;
+    const int negl = loc && fabs(dc[0]) <= LOCAL_NEGL * q[0];
+    if (dc[0] < 0.0 && !negl) {
+        double r = (rt - q[0]) / dc[0];
+        if (r < 0.0) r = 0.0;
+        if (r < tn) tn = r;
+    }
+    if (loc && dc[0] > 0.0 && !negl) {
+        double r = (rceil * MORTAR_MARGIN_HI - q[0]) / dc[0];
+        if (r < 0.0) r = 0.0;
+        if (r < tn) tn = r;
+    }
+    double tp = dgo_theta_pressure(q, dc, pt, gamma);
+    if (tp < tn) tn = tp;
+    if (loc) tn = dgo_theta_entropy(q, dc, sm * MORTAR_MARGIN, gamma, tn);
+    return tn;
+}
+
 int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
                 int limiter, double* out, dgo_stats* st)
+{
+    return dgo_fe_step_ind(m, u, dt, gamma, beta, limiter, 0, out, st);
+}
+
+int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
+                    int limiter, const double* ind_in, double* out, dgo_stats* st)
 {
     const dgo_basis* B = &m->B;
     int N = B->N, n = B->n;
@@ -643,13 +789,21 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
     double* uFV = (double*)malloc(sizeof(double) * E * 4 * nn);
     double* rmin = (double*)malloc(sizeof(double) * E * nn);
     double* pmin = (double*)malloc(sizeof(double) * E * nn);
-    const int local = limiter == LIM_LOCAL;
-    double *rlo = 0, *rhi = 0, *smin = 0;
+    /* local: local bounds enforced; comb: positivity and local factors both
+       computed and blended per element with the shock indicator */
+    const int comb = limiter == LIM_COMBINED;
+    const int local = limiter == LIM_LOCAL || comb;
+    double *rlo = 0, *rhi = 0, *smin = 0, *ind = 0;
     if (local) {
         rlo = (double*)malloc(sizeof(double) * E * nn);
         rhi = (double*)malloc(sizeof(double) * E * nn);
         smin = (double*)malloc(sizeof(double) * E * nn);
         dgo_local_bounds(m, u, gamma, rlo, rhi, smin);
+    }
+    if (comb) {
+        ind = (double*)malloc(sizeof(double) * (E > 0 ? E : 1));
+        if (ind_in) memcpy(ind, ind_in, sizeof(double) * E);
+        else dgo_shock_indicator(m, u, gamma, ind);
     }
     int64_t nfaces = 0;
     double alpha_sum = 0.0;
@@ -674,10 +828,10 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 if (!(q[0] > 0.0) || !(p > 0.0)) inadm++;
                 rmin[e * nn + b * n + a] = beta * q[0];
                 pmin[e * nn + b * n + a] = beta * p;
-                /* local limiting keeps the positivity bounds as well: the
+                /* local limiting keeps the positivity bounds as well: its
                    density floor is the larger of the two */
-                if (local && rlo[e * nn + b * n + a] > rmin[e * nn + b * n + a])
-                    rmin[e * nn + b * n + a] = rlo[e * nn + b * n + a];
+                if (local && rlo[e * nn + b * n + a] < rmin[e * nn + b * n + a])
+                    rlo[e * nn + b * n + a] = rmin[e * nn + b * n + a];
             }
         /* antidiffusive fluxes on interior subcell faces: telescoped high-order
            flux (eq. fluxdifferencingform) minus the low-order subcell flux */
@@ -708,8 +862,8 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                     }
                 }
             }
-        /* per-node factors: Zalesak for rho, per-face pressure root with Gamma = 4 */
-        double th[DGO_NMAX][DGO_NMAX]; /* [b][a] */
+        /* per-node factors (positivity, local, or both for the blend) */
+        double th[DGO_NMAX][DGO_NMAX], thl[DGO_NMAX][DGO_NMAX]; /* [b][a] */
         for (int b = 0; b < n; ++b)
             for (int a = 0; a < n; ++a) {
                 double mi = mass(m, e, a, b);
@@ -721,48 +875,22 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 if (a < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ax[b][a][v]; nf++; }
                 if (b > 0) { for (int v = 0; v < 4; ++v) cf[nf][v] = dt / mi * Ay[a][b - 1][v]; nf++; }
                 if (b < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ay[a][b][v]; nf++; }
-                double rt = rmin[e * nn + b * n + a] * BOUND_MARGIN;
-                double pt = pmin[e * nn + b * n + a] * BOUND_MARGIN;
-                /* Zalesak: the sum of the negative (positive) density
-                   increments may use at most the distance to the lower (upper)
-                   bound */
-                double P = 0.0, Pp = 0.0;
-                for (int j = 0; j < nf; ++j) {
-                    if (cf[j][0] < 0.0) P += cf[j][0];
-                    if (cf[j][0] > 0.0) Pp += cf[j][0];
+                int64_t i = e * nn + b * n + a;
+                if (limiter == LIM_LOCAL) {
+                    th[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
+                } else {
+                    th[b][a] = volume_node_factor(q, cf, nf, rmin[i], pmin[i], 0, 0.0, 0.0, gamma);
+                    if (comb)
+                        thl[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
                 }
-                double t = 1.0;
-                /* local bounds: increments below 1e-14 of the density are
-                   rounding noise and are not limited (a node whose density
-                   interval has zero width would otherwise switch between
-                   theta = 0 and 1 on the sign of a rounding error) */
-                if (local && P > -LOCAL_NEGL * q[0]) P = 0.0;
-                if (local && Pp < LOCAL_NEGL * q[0]) Pp = 0.0;
-                if (P < 0.0) {
-                    double r = (rt - q[0]) / P;
-                    t = r < 1.0 ? r : 1.0;
-                    if (t < 0.0) t = 0.0;
-                }
-                if (local && Pp > 0.0) {
-                    double r = (rhi[e * nn + b * n + a] * BOUND_MARGIN_HI - q[0]) / Pp;
-                    if (r < 0.0) r = 0.0;
-                    if (r < t) t = r;
-                }
-                for (int j = 0; j < nf; ++j) {
-                    double dc[4];
-                    for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
-                    double tp = dgo_theta_pressure(q, dc, pt, gamma);
-                    if (tp < t) t = tp;
-                }
-                /* entropy: per face on [0, t], increments scaled by Gamma = 4 */
-                if (local)
-                    for (int j = 0; j < nf; ++j) {
-                        double dc[4];
-                        for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
-                        t = dgo_theta_entropy(q, dc, smin[e * nn + b * n + a] * BOUND_MARGIN, gamma, t);
-                    }
-                th[b][a] = t;
             }
+        /* face factor: the smaller node factor of its two nodes, combined:
+           (1 - w) theta_pos + w theta_local with the element's indicator w */
+        const double w = comb ? ind[e] : 0.0;
+#define FACE_T(b1, a1, b2, a2)                                                                 \
+    (comb ? (1.0 - w) * (th[b1][a1] < th[b2][a2] ? th[b1][a1] : th[b2][a2]) +                 \
+                w * (thl[b1][a1] < thl[b2][a2] ? thl[b1][a1] : thl[b2][a2])                   \
+          : (th[b1][a1] < th[b2][a2] ? th[b1][a1] : th[b2][a2]))
         /* per-face factor = min of its two nodes; limited volume update */
         for (int b = 0; b < n; ++b)
             for (int a = 0; a < n; ++a) {
@@ -770,22 +898,22 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 double acc[4];
                 for (int v = 0; v < 4; ++v) acc[v] = uFV[IDX(e, v, b, a)];
                 if (a > 0) {
-                    double t = th[b][a - 1] < th[b][a] ? th[b][a - 1] : th[b][a];
+                    double t = FACE_T(b, a - 1, b, a);
                     for (int v = 0; v < 4; ++v) acc[v] += t * dt / mi * Ax[b][a - 1][v];
                 }
                 if (a < N) {
-                    double t = th[b][a] < th[b][a + 1] ? th[b][a] : th[b][a + 1];
+                    double t = FACE_T(b, a, b, a + 1);
                     for (int v = 0; v < 4; ++v) acc[v] -= t * dt / mi * Ax[b][a][v];
                     nfaces++;
                     alpha_sum += 1.0 - t;
                     if (t < thmin) thmin = t;
                 }
                 if (b > 0) {
-                    double t = th[b - 1][a] < th[b][a] ? th[b - 1][a] : th[b][a];
+                    double t = FACE_T(b - 1, a, b, a);
                     for (int v = 0; v < 4; ++v) acc[v] += t * dt / mi * Ay[a][b - 1][v];
                 }
                 if (b < N) {
-                    double t = th[b][a] < th[b + 1][a] ? th[b][a] : th[b + 1][a];
+                    double t = FACE_T(b, a, b + 1, a);
                     for (int v = 0; v < 4; ++v) acc[v] -= t * dt / mi * Ay[a][b][v];
                     nfaces++;
                     alpha_sum += 1.0 - t;
@@ -793,6 +921,7 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 }
                 for (int v = 0; v < 4; ++v) out[IDX(e, v, b, a)] = acc[v];
             }
+#undef FACE_T
     }
     st->fv_inadmissible = inadm;
     st->theta_vol_min = thmin;
@@ -806,7 +935,7 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
 #pragma omp parallel for schedule(static) reduction(+ : tmsum) reduction(min : tmmin)
         for (int64_t S = 0; S < m->M; ++S) {
             const dgo_mortar* M = &m->mort[S];
-            double t = 1.0;
+            double t = 1.0, tl = 1.0; /* positivity (or local) factor; local factor of the blend */
             for (int s = 0; s < 3 * n; ++s) {
                 int64_t e;
                 int f, k;
@@ -831,28 +960,27 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                    vacuum that state can leave the admissible set and the flux is
                    not defined: the mortar then keeps the low-order flux (Sec. 3.2) */
                 if (!(isfinite(dc[0]) && isfinite(dc[1]) && isfinite(dc[2]) && isfinite(dc[3]))) {
-                    t = 0.0;
+                    t = tl = 0.0;
                     continue;
                 }
-                double rt = rmin[e * nn + b * n + a] * MORTAR_MARGIN;
-                double pt = pmin[e * nn + b * n + a] * MORTAR_MARGIN;
                 /* this node's factor, then the minimum over the mortar's nodes */
-                double tn = 1.0;
-                const int negl = local && fabs(dc[0]) <= LOCAL_NEGL * q[0];
-                if (dc[0] < 0.0 && !negl) {
-                    double r = (rt - q[0]) / dc[0];
-                    if (r < 0.0) r = 0.0;
-                    if (r < tn) tn = r;
-                }
-                if (local && dc[0] > 0.0 && !negl) {
-                    double r = (rhi[e * nn + b * n + a] * MORTAR_MARGIN_HI - q[0]) / dc[0];
-                    if (r < 0.0) r = 0.0;
-                    if (r < tn) tn = r;
-                }
-                double tp = dgo_theta_pressure(q, dc, pt, gamma);
-                if (tp < tn) tn = tp;
-                if (local) tn = dgo_theta_entropy(q, dc, smin[e * nn + b * n + a] * MORTAR_MARGIN, gamma, tn);
+                int64_t i = e * nn + b * n + a;
+                double tn = limiter == LIM_LOCAL
+                                ? mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma)
+                                : mortar_node_factor(q, dc, rmin[i], pmin[i], 0, 0.0, 0.0, gamma);
                 if (tn < t) t = tn;
+                if (comb) {
+                    double tnl = mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
+                    if (tnl < tl) tl = tnl;
+                }
+            }
+            /* combined: the mortar's weight is the largest indicator of its
+               three elements */
+            if (comb) {
+                double w = ind[M->large];
+                if (ind[M->small[0]] > w) w = ind[M->small[0]];
+                if (ind[M->small[1]] > w) w = ind[M->small[1]];
+                t = (1.0 - w) * t + w * tl;
             }
             theta[S] = t;
             tmsum += 1.0 - t;
@@ -905,9 +1033,10 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
                 double q[4];
                 get_node(out, n, e, a, b, q);
                 int64_t i = e * nn + b * n + a;
-                if (!local) {
+                /* combined limiting guarantees the positivity bounds only */
+                if (limiter != LIM_LOCAL) {
                     if (q[0] < rmin[i] || dgo_pressure(q, gamma) < pmin[i] || q[0] != q[0]) viol++;
-                } else if (!(q[0] >= rmin[i] * (1.0 - LOCAL_TOL)) || q[0] > rhi[i] * (1.0 + LOCAL_TOL) ||
+                } else if (!(q[0] >= rlo[i] * (1.0 - LOCAL_TOL)) || q[0] > rhi[i] * (1.0 + LOCAL_TOL) ||
                            dgo_pressure(q, gamma) < pmin[i] ||
                            dgo_spec_entropy(q, gamma) < smin[i] * (1.0 - LOCAL_TOL)) {
                     viol++;
@@ -920,6 +1049,7 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
     free(rlo);
     free(rhi);
     free(smin);
+    free(ind);
     free(HO);
     free(LO);
     return st->fv_inadmissible ? 1 : 0;

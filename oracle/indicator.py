@@ -7,7 +7,8 @@ orthonormal Legendre polynomials Lt_i = sqrt((2i+1)/2) L_i on [-1, 1].  m is
 the inverse of that interpolation, one direction at a time.
 
 Hennemann indicator (Hennemann, Rueda-Ramirez, Hindenlang, Gassner 2021; the
-paper uses it as its AMR indicator for shocks, Sec. 3.3 to 3.6), on q = rho p:
+paper uses it as its AMR indicator for shocks, Sec. 3.3 to 3.6, on q = rho p,
+and, on q = p without the cap, as the weight of combined limiting, Sec. 3.5):
   E_all   = sum of m_ij^2 over all modes,
   E_low1  = sum over i, j <= N-1,   E_low2 = sum over i, j <= N-2,
   energy  = max((E_all - E_low1) / E_all, (E_low1 - E_low2) / E_low1),
@@ -64,9 +65,9 @@ def prims(u, gamma=1.4):
     return rho, p
 
 
-def hennemann_energy(u, N, gamma=1.4):
+def hennemann_energy(u, N, gamma=1.4, quantity="rho_p"):
     rho, p = prims(u, gamma)
-    m2 = modal(rho * p, N) ** 2
+    m2 = modal(rho * p if quantity == "rho_p" else p, N) ** 2
     e_all = m2.sum(axis=(-2, -1))
     e_l1 = m2[..., :N, :N].sum(axis=(-2, -1))
     e_l2 = m2[..., :N - 1, :N - 1].sum(axis=(-2, -1))
@@ -77,17 +78,23 @@ def threshold(N):
     return 0.5 * 10.0 ** (-1.8 * (N + 1) ** 0.25)
 
 
-def hennemann_alpha_of_energy(energy, N):
+def hennemann_alpha_of_energy(energy, N, alpha_max=ALPHA_MAX):
     T = threshold(N)
     s = np.log((1.0 - 1e-4) / 1e-4)
     a = 1.0 / (1.0 + np.exp(-(s / T) * (energy - T)))
     a = np.where(a < ALPHA_MIN, 0.0, a)
-    return np.minimum(a, ALPHA_MAX)
+    return np.minimum(a, alpha_max)
 
 
 def hennemann(u, N, gamma=1.4):
     """Per-element indicator alpha in [0, alpha_max], FP64."""
     return hennemann_alpha_of_energy(hennemann_energy(u, N, gamma), N)
+
+
+def shock_indicator(u, N, gamma=1.4):
+    """The indicator of combined limiting (Sec. 3.5): the same logistic on the
+    pressure's modal energy, not capped (alpha in [0, 1])."""
+    return hennemann_alpha_of_energy(hennemann_energy(u, N, gamma, quantity="p"), N, alpha_max=1.0)
 
 
 def features(u, N, gamma=1.4):
