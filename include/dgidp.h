@@ -43,7 +43,7 @@ enum {
 
 enum { DGIDP_FP64 = 0, DGIDP_MIXED = 1 };           /* precision of the high-order fluxes */
 enum { DGIDP_DT_IDP = 0, DGIDP_DT_LOWORDER = 1 };   /* time-step rule */
-enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1, DGIDP_LIMIT_LOCAL = 2 };
+enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1, DGIDP_LIMIT_LOCAL = 2, DGIDP_LIMIT_COMBINED = 3 };
 enum { DGIDP_RHS_HIGH = 0, DGIDP_RHS_LOW = 1 };
 
 typedef struct dgidp_ctx dgidp_ctx;
@@ -65,7 +65,13 @@ typedef struct dgidp_ctx dgidp_ctx;
  *             maximum density and the minimum specific entropy p rho^-gamma
  *             over the node and the bar states of its low-order neighbours,
  *             taken from the stage's input state; the density floor is the
- *             larger of the local and the positivity floor)
+ *             larger of the local and the positivity floor), or
+ *             DGIDP_LIMIT_COMBINED (Sec. 3.5, eq. combination_posLim_local:
+ *             per subcell face alpha = (1 - w) alpha_pos + w alpha_local with w
+ *             the element's Hennemann indicator on the pressure in [0, 1],
+ *             computed from each stage's input; per mortar w is the largest
+ *             indicator of its three elements; only the positivity bounds
+ *             are guaranteed)
  *  strict_dt  if nonzero, dgidp_limit() rejects a dt above the IDP bound */
 typedef struct {
     int N;

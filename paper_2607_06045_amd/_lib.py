@@ -19,7 +19,7 @@ if not os.path.exists(LIB_PATH):
 
 FP64, MIXED = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
-LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL = 0, 1, 2
+LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED = 0, 1, 2, 3
 RHS_HIGH, RHS_LOW = 0, 1
 IND_HENNEMANN, IND_MLP = 0, 1
 MLP_NPARAM = 5313

@@ -93,6 +93,7 @@ void free_mesh(dgidp_ctx* c)
     dfree(c->dm.slot_partner);
     dfree(c->dm.slot);
     dfree(c->dm.perm);
+    dfree(c->dm.shock_ind);
     dfree(c->U);
     dfree(c->W1);
     dfree(c->W2);
@@ -363,6 +364,10 @@ int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, dou
           DevStats* st, const DtSource& dt)
 {
     const KernelParams kp = kparams(ctx);
+    // combined limiting weighs its factors with the indicator of the stage's input
+    if (kp.limiter == DGIDP_LIMIT_COMBINED &&
+        launch_shock_indicator(ctx->p.N, ctx->dm, uin, kp.gamma, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
     if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
     if (launch_mortar(ctx->p.N, ctx->dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
@@ -385,7 +390,7 @@ int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
         (p->precision != DGIDP_FP64 && p->precision != DGIDP_MIXED) ||
         (p->dt_mode != DGIDP_DT_IDP && p->dt_mode != DGIDP_DT_LOWORDER) ||
         (p->limiter != DGIDP_LIMIT_NONE && p->limiter != DGIDP_LIMIT_POSITIVITY &&
-         p->limiter != DGIDP_LIMIT_LOCAL))
+         p->limiter != DGIDP_LIMIT_LOCAL && p->limiter != DGIDP_LIMIT_COMBINED))
         return DGIDP_E_INVALID_ARG;
     dgidp_ctx* ctx = new dgidp_ctx();
     ctx->p = *p;
@@ -479,6 +484,7 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
         return rc;
     const size_t sz = (size_t)E * 4 * NN * sizeof(double);
     HIPCHK(hipMalloc((void**)&ctx->dm.slot, std::max<size_t>(1, (size_t)M * 3 * n) * kSlotW * sizeof(double)));
+    HIPCHK(hipMalloc((void**)&ctx->dm.shock_ind, std::max<size_t>(1, (size_t)E) * sizeof(double)));
     HIPCHK(hipMalloc((void**)&ctx->U, sz));
     HIPCHK(hipMalloc((void**)&ctx->W1, sz));
     HIPCHK(hipMalloc((void**)&ctx->W2, sz));
@@ -787,6 +793,9 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     int rc = host_dt(ctx, 0.5, ctx->p.dt_mode, &dt);
     if (rc) return rc;
     if (launch_set_double(ctx->dt_dev, dt, ctx->stream)) return fail(ctx, DGIDP_E_DEVICE, "launch failed");
+    if (kp.limiter == DGIDP_LIMIT_COMBINED &&
+        launch_shock_indicator(ctx->p.N, ctx->dm, ctx->U, kp.gamma, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
     for (int r = 0; r < reps; ++r)
         if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->U, nullptr, ctx->W1, 0.0, 1.0, stored_dt(ctx), nullptr,

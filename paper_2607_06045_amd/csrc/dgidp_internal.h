@@ -61,6 +61,7 @@ struct DevMesh {
     int* slot_partner = nullptr;  // [M*3n] slot of the other mortar of a node on two mortars, or -1
     double* slot = nullptr;     // [M*3n*kSlotW]
     int* perm = nullptr;        // [E] external index of internal element e
+    double* shock_ind = nullptr;  // [E] shock indicator of combined limiting (internal order)
 };
 
 struct KernelParams {
@@ -134,6 +135,8 @@ int launch_rhs(int N, const DevMesh& m, const KernelParams& kp, const double* u,
                double* du, hipStream_t s);
 int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st, hipStream_t s,
                   double gamma, int limiter);
+// per-element shock indicator on the pressure of u into m.shock_ind (combined limiting)
+int launch_shock_indicator(int N, const DevMesh& m, const double* u, double gamma, hipStream_t s);
 // max over nodes of the dt denominator, atomically merged into the accumulator
 // set acc (all zero on entry); the set other is cleared for the next step
 int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, int mode,

@@ -392,6 +392,70 @@ __device__ double theta_s(const double* u0, const double* dc, double lst, double
     return lo;
 }
 
+// Node factor of the volume limiter from the node's four face increments cf
+// (dt/m_i-scaled, zero for missing faces): Zalesak factors for the density
+// floor rfl (and, with local bounds, the ceiling rce), the pressure root per
+// face and, with local bounds, the entropy root per face on [0, theta] (log
+// entropy floor lsm); the last two on Gamma = 4-scaled increments.
+template <bool LOCB>
+__device__ __forceinline__ double volume_factor(const double* uFV, const double (&cf)[4][4], double rfl,
+                                                double pfl, double rce, double lsm, double g, double ig1)
+{
+    const double rt = rfl * kMargin, pt = pfl * kMargin;
+    // Zalesak: the sum of the negative (positive) density increments may use at
+    // most the distance to the floor (ceiling)
+    double P = 0.0, Pp = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        P += fmin(cf[j][0], 0.0);
+        if (LOCB) Pp += fmax(cf[j][0], 0.0);
+    }
+    // local bounds: increments below kLocalNegl of the density are rounding
+    // noise and are not limited (a node whose density interval has zero width
+    // would otherwise switch between theta = 0 and 1 on the sign of a rounding
+    // error)
+    if (LOCB && P > -kLocalNegl * uFV[0]) P = 0.0;
+    if (LOCB && Pp < kLocalNegl * uFV[0]) Pp = 0.0;
+    double th = 1.0;
+    if (P < 0.0) th = fmax(fmin((rt - uFV[0]) / P, 1.0), 0.0);
+    if (LOCB && Pp > 0.0) th = fmin(th, fmax((rce * kMarginHi - uFV[0]) / Pp, 0.0));
+    // pressure: each face's increment scaled by Gamma = 2d = 4
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
+        if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
+        th = fmin(th, theta_p(uFV, dc, pt, ig1));
+    }
+    // specific entropy: per face on [0, th]
+    if (LOCB) {
+        const double lst = lsm + 0x1p-40;  // ln(s_min (1 + 2^-40))
+#pragma unroll 1
+        for (int j = 0; j < 4; ++j) {
+            const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
+            if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
+            th = theta_s(uFV, dc, lst, g, th);
+        }
+    }
+    return th;
+}
+
+// Factor of one mortar node for its n_i-scaled increment dc on top of u^vol:
+// density floor (and ceiling), pressure root, entropy root, all against half
+// the volume margin.
+template <bool LOCB>
+__device__ __forceinline__ double mortar_factor(const double* uvol, const double* dc, double rfl, double pfl,
+                                                double rce, double lsm, double g, double ig1)
+{
+    const double rt = rfl * kMarginMortar, pt = pfl * kMarginMortar;
+    double ts = 1.0;
+    const bool negl = LOCB && fabs(dc[0]) <= kLocalNegl * uvol[0];
+    if (dc[0] < 0.0 && !negl) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
+    if (LOCB && dc[0] > 0.0 && !negl) ts = fmin(ts, fmax((rce * kMarginMortarHi - uvol[0]) / dc[0], 0.0));
+    ts = fmin(ts, theta_p(uvol, dc, pt, ig1));
+    if (LOCB) ts = theta_s(uvol, dc, lsm + 0x1p-41, g, ts);
+    return ts;
+}
+
 // ---------------------------------------------------------------------------
 // statistics
 // ---------------------------------------------------------------------------
@@ -458,6 +522,7 @@ struct StageArgs {
     double* uout;
     double a, b;
     const double* dt;
+    const double* ind;  // combined limiting: shock indicator per element, in [0, 1]
     // when set, dt = cfl / max over the accumulator set dtmax (bits of
     // non-negative doubles); block 0 stores it in dt_out
     const unsigned long long* dtmax;
@@ -523,13 +588,16 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
         X.c = sR[le][4][qq];                              \
     } while (0)
 
-template <int N, int MODE, bool MIXED, bool LOC>
+// LIMK: 0 positivity (or none, at run time), 1 local bounds, 2 the blend of
+// the two by the per-element shock indicator A.ind (eq. combination_posLim_local)
+template <int N, int MODE, bool MIXED, int LIMK>
 // at least three waves per SIMD: the local-limiting variant would otherwise
 // take 172 registers and run two (63.3 against 67.7 us on the 22,156-leaf
 // blast with a few spilled registers; the other variants fit anyway)
 __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
 {
     using G = Geo<N>;
+    constexpr bool LOC = LIMK >= 1, COMB = LIMK == 2;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN;
     static_assert(NP % NN == 0, "pair split");
@@ -570,6 +638,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // local bounds: own log entropy; for face lanes the density range and the
     // smallest log entropy of the bar states across this lane's face node
     double ls_own = 0.0;
+    double w_e = 0.0;  // combined limiting: weight of the local factors
     double fb_lo = __builtin_inf(), fb_hi = -__builtin_inf(), fb_ls = __builtin_inf();
     const double dtpart =
         A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
@@ -598,6 +667,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         load_node<N>(A.uin, e, q, me, g);
         hx = A.h[2 * e];
         hy = A.h[2 * e + 1];
+        if (COMB) w_e = A.ind[e];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             sU[le][v][q] = me.u[v];
@@ -1025,7 +1095,9 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     const double dtm = dt * im;
     double uFV[4], cf[4][4];
     double rmin = 0.0, pmin = 0.0, th = 1.0;
-    double rhi = 0.0, lsm = 0.0;  // local bounds: density maximum, log entropy minimum
+    // local bounds: density floor (the larger of the local and the positivity
+    // floor), ceiling, log entropy floor; thl the local node factor of the blend
+    double rlf = 0.0, rhi = 0.0, lsm = 0.0, thl = 1.0;
     unsigned long long inad = 0;
     if (act) {
 #pragma unroll
@@ -1067,7 +1139,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 lsm = fmin(lsm, sR[le][7][fnq[f]]);
             }
             // the positivity floor stays: the density floor is the larger one
-            rmin = fmax(rmin, rlo);
+            rlf = fmax(rmin, rlo);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -1077,42 +1149,19 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             cf[3][v] = b < N ? -dtm * sPair[le][v][NF + fyt] : 0.0;
         }
         if (A.limiter != DGIDP_LIMIT_NONE) {
-            // Zalesak-type factor for the density: sum of the negative increments
-            const double rt = rmin * kMargin, pt = pmin * kMargin;
-            double P = 0.0, Pp = 0.0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                P += fmin(cf[j][0], 0.0);
-                if (LOC) Pp += fmax(cf[j][0], 0.0);
-            }
-            // local bounds: increments below kLocalNegl of the density are rounding
-            // noise and are not limited (a node whose density interval has zero
-            // width would otherwise switch between theta = 0 and 1 on the sign of
-            // a rounding error)
-            if (LOC && P > -kLocalNegl * uFV[0]) P = 0.0;
-            if (LOC && Pp < kLocalNegl * uFV[0]) Pp = 0.0;
-            if (P < 0.0) th = fmax(fmin((rt - uFV[0]) / P, 1.0), 0.0);
-            // and the sum of the positive ones at most the distance to the maximum
-            if (LOC && Pp > 0.0) th = fmin(th, fmax((rhi * kMarginHi - uFV[0]) / Pp, 0.0));
-            // pressure: each face's increment scaled by Gamma = 2d = 4
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
-                if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
-                th = fmin(th, theta_p(uFV, dc, pt, ig1));
-            }
-            // specific entropy: per face on [0, th], increments scaled by Gamma = 4
-            if (LOC) {
-                const double lst = lsm + 0x1p-40;  // ln(s_min (1 + 2^-40))
-#pragma unroll 1
-                for (int j = 0; j < 4; ++j) {
-                    const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
-                    if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
-                    th = theta_s(uFV, dc, lst, g, th);
-                }
+            if (LIMK == 1) {
+                th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
+            } else {
+                th = volume_factor<false>(uFV, cf, rmin, pmin, 0.0, 0.0, g, ig1);
+                if (COMB) thl = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
             }
         }
+    }
+    // the blend keeps the local node factors in row 1, read above for the bounds
+    if (COMB) __syncthreads();
+    if (act) {
         sTh(q) = th;
+        if (COMB) sR[le][1][q] = thl;
     }
     __syncthreads();
 
@@ -1122,10 +1171,20 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     if (act) {
         double uvol[4];
         double tf[4];
-        tf[0] = a > 0 ? fmin(th, sTh(q - 1)) : 0.0;
-        tf[1] = a < N ? fmin(th, sTh(q + 1)) : 0.0;
-        tf[2] = b > 0 ? fmin(th, sTh(q - n)) : 0.0;
-        tf[3] = b < N ? fmin(th, sTh(q + n)) : 0.0;
+        // face factor: the smaller of its two node factors; blended:
+        // (1 - w) theta_pos + w theta_local
+        const int qn4[4] = {q - 1, q + 1, q - n, q + n};
+        const bool has[4] = {a > 0, a < N, b > 0, b < N};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!has[j]) {
+                tf[j] = 0.0;
+            } else if (COMB) {
+                tf[j] = (1.0 - w_e) * fmin(th, sTh(qn4[j])) + w_e * fmin(thl, sR[le][1][qn4[j]]);
+            } else {
+                tf[j] = fmin(th, sTh(qn4[j]));
+            }
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             uvol[v] = uFV[v] + tf[0] * cf[0][v] + tf[1] * cf[1][v] + tf[2] * cf[2][v] + tf[3] * cf[3][v];
@@ -1147,8 +1206,8 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             A.uout[idx] = r;
         }
         if (nmf == 0) {
-            if (LOC) {
-                if (A.st && (!(uvol[0] >= rmin * (1.0 - kLocalTol)) || uvol[0] > rhi * (1.0 + kLocalTol) ||
+            if (LIMK == 1) {
+                if (A.st && (!(uvol[0] >= rlf * (1.0 - kLocalTol)) || uvol[0] > rhi * (1.0 + kLocalTol) ||
                              pressure(uvol, g) < pmin ||
                              !(log(pressure(uvol, g)) - g * log(uvol[0]) >= lsm - kLocalTol)))
                     viol = 1;
@@ -1157,7 +1216,6 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 viol = 1;
             }
         } else {
-            const double rt = rmin * kMarginMortar, pt = pmin * kMarginMortar;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (j >= nmf) break;
@@ -1170,17 +1228,16 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     dc[v] = nmf * c[v];
                     fin = fin && isfinite(dc[v]);
                 }
-                double ts = 1.0;
+                double ts = 1.0, tsl = 1.0;
                 if (A.limiter != DGIDP_LIMIT_NONE) {
                     // an undefined high-order mortar flux keeps the low-order flux
                     if (!fin) {
-                        ts = 0.0;
+                        ts = tsl = 0.0;
+                    } else if (LIMK == 1) {
+                        ts = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, g, ig1);
                     } else {
-                        const bool negl = LOC && fabs(dc[0]) <= kLocalNegl * uvol[0];
-                        if (dc[0] < 0.0 && !negl) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
-                        if (LOC && dc[0] > 0.0 && !negl) ts = fmin(ts, fmax((rhi * kMarginMortarHi - uvol[0]) / dc[0], 0.0));
-                        ts = fmin(ts, theta_p(uvol, dc, pt, ig1));
-                        if (LOC) ts = theta_s(uvol, dc, lsm + 0x1p-41, g, ts);
+                        ts = mortar_factor<false>(uvol, dc, rmin, pmin, 0.0, 0.0, g, ig1);
+                        if (COMB) tsl = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, g, ig1);
                     }
                 }
                 double* S = A.slot + (size_t)(j == 0 ? slot0 : slot1) * kSlotW;
@@ -1190,11 +1247,15 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     S[4 + v] = c[v];
                 }
                 S[8] = ts;
-                S[9] = rmin;
+                S[9] = LIMK == 1 ? rlf : rmin;
                 S[10] = pmin;
-                if (LOC) {
+                if (LIMK == 1) {
                     S[11] = rhi;
                     S[12] = lsm;
+                }
+                if (COMB) {
+                    S[13] = tsl;
+                    S[14] = w_e;
                 }
             }
         }
@@ -1205,6 +1266,26 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
 // ---------------------------------------------------------------------------
 // mortar kernel: one thread per slot
 // ---------------------------------------------------------------------------
+// factor of mortar S: the minimum of its slots' node factors; combined
+// limiting blends the positivity and the local minimum with the largest
+// indicator of the mortar's three elements
+template <int N>
+__device__ __forceinline__ double mortar_theta(const double* __restrict__ slot, int S, int limiter)
+{
+    constexpr int NS = 3 * (N + 1);
+    double t = 1.0, tl = 1.0, w = 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double* R = slot + ((size_t)S * NS + j) * kSlotW;
+        t = fmin(t, R[8]);
+        if (limiter == DGIDP_LIMIT_COMBINED) {
+            tl = fmin(tl, R[13]);
+            w = fmax(w, R[14]);
+        }
+    }
+    return limiter == DGIDP_LIMIT_COMBINED ? (1.0 - w) * t + w * tl : t;
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
                                                 const int* __restrict__ snode,
@@ -1226,9 +1307,7 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
         double rec[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) rec[i] = R[i];
-        double t = 1.0;
-#pragma unroll
-        for (int j = 0; j < NS; ++j) t = fmin(t, slot[((size_t)S * NS + j) * kSlotW + 8]);
+        double t = mortar_theta<N>(slot, S, limiter);
         const int e = node / NN, q = node - e * NN;
         double uo[4];
 #pragma unroll
@@ -1248,9 +1327,7 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
             if (S2 < S) {
                 apply = false;  // the lower-numbered mortar applies both corrections
             } else {
-                double t2 = 1.0;
-#pragma unroll
-                for (int j = 0; j < NS; ++j) t2 = fmin(t2, slot[((size_t)S2 * NS + j) * kSlotW + 8]);
+                const double t2 = mortar_theta<N>(slot, S2, limiter);
                 if (t2 != 0.0)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) corr[v] += t2 * slot[(size_t)part * kSlotW + 4 + v];
@@ -1521,6 +1598,70 @@ int launch_indicator(int N, int E, const double* u, const int* perm, double gamm
 }
 
 // ---------------------------------------------------------------------------
+// shock indicator of combined limiting (Sec. 3.5): the Hennemann indicator on
+// the pressure, not capped, FP64, one value per element in internal order.
+// One thread per node stages p, one thread per mode (i, j) forms its squared
+// orthonormal-Legendre coefficient, thread 0 of the element reduces.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(128) void k_shock_indicator(const double* __restrict__ u, int E, double gamma,
+                                                         double* __restrict__ ind)
+{
+    constexpr int n = N + 1, NN = n * n, EPB = 128 / NN;
+    __shared__ double sP[EPB][NN];
+    __shared__ double sM2[EPB][NN];
+    const Tab<N>& tb = T<N>();
+    const int tid = threadIdx.x;
+    const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = tid < EPB * NN && e < E;
+    if (act) {
+        double w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
+        sP[le][q] = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+    }
+    __syncthreads();
+    if (act) {
+        double m = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < n; ++bb) {
+            double r = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < n; ++aa) r += tb.Vinv[a][aa] * sP[le][bb * n + aa];
+            m += tb.Vinv[b][bb] * r;
+        }
+        sM2[le][q] = m * m;
+    }
+    __syncthreads();
+    if (!act || q != 0) return;
+    double all = 0.0, low1 = 0.0, low2 = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            const double m2 = sM2[le][j * n + i];
+            all += m2;
+            if (i < N && j < N) low1 += m2;
+            if (i < N - 1 && j < N - 1) low2 += m2;
+        }
+    const double en = fmax((all - low1) / all, (low1 - low2) / low1);
+    const double T = 0.5 * pow(10.0, -1.8 * sqrt(sqrt((double)(N + 1))));
+    const double s = log((1.0 - 1e-4) / 1e-4);
+    const double al = 1.0 / (1.0 + exp(-(s / T) * (en - T)));
+    ind[e] = al < 1e-3 ? 0.0 : al;
+}
+
+int launch_shock_indicator(int N, const DevMesh& m, const double* u, double gamma, hipStream_t s)
+{
+    if (m.E <= 0) return 0;
+    const int EPB = 128 / ((N + 1) * (N + 1));
+    const int grid = (m.E + EPB - 1) / EPB;
+    if (N == 3) hipLaunchKernelGGL(k_shock_indicator<3>, dim3(grid), dim3(128), 0, s, u, m.E, gamma, m.shock_ind);
+    else if (N == 4) hipLaunchKernelGGL(k_shock_indicator<4>, dim3(grid), dim3(128), 0, s, u, m.E, gamma, m.shock_ind);
+    else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------------
 // solution transfer between meshes (Sec. 2.4): one thread per new node.
 // Children take the parent polynomial at their nodes (tensor product of the
 // mortar interpolation matrices); a new parent takes the exact L2 projection
@@ -1741,6 +1882,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.a = a;
     A.b = b;
     A.dt = dt.dt;
+    A.ind = m.shock_ind;
     A.dtmax = dt.dtmax;
     A.cfl = dt.cfl;
     A.dt_out = dt.dt_out;
@@ -1758,20 +1900,23 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     const int grid = (m.E + G::EPB - 1) / G::EPB;
     const bool mixed = kp.precision == DGIDP_MIXED;
     const dim3 blk(G::BS);
-    const bool loc = kp.limiter == DGIDP_LIMIT_LOCAL;
+    const int lk = kp.limiter == DGIDP_LIMIT_LOCAL ? 1 : (kp.limiter == DGIDP_LIMIT_COMBINED ? 2 : 0);
     if (mode == MODE_STAGE) {
-        if (loc) {
-            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, true>), dim3(grid), blk, 0, s, A);
-            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, true>), dim3(grid), blk, 0, s, A);
+        if (lk == 1) {
+            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 1>), dim3(grid), blk, 0, s, A);
+            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 1>), dim3(grid), blk, 0, s, A);
+        } else if (lk == 2) {
+            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 2>), dim3(grid), blk, 0, s, A);
+            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 2>), dim3(grid), blk, 0, s, A);
         } else {
-            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, false>), dim3(grid), blk, 0, s, A);
-            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, false>), dim3(grid), blk, 0, s, A);
+            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 0>), dim3(grid), blk, 0, s, A);
+            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 0>), dim3(grid), blk, 0, s, A);
         }
     } else if (mode == MODE_RHS_HIGH) {
-        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true, false>), dim3(grid), blk, 0, s, A);
-        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false, false>), dim3(grid), blk, 0, s, A);
+        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true, 0>), dim3(grid), blk, 0, s, A);
+        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false, 0>), dim3(grid), blk, 0, s, A);
     } else {
-        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false, false>), dim3(grid), blk, 0, s, A);
+        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false, 0>), dim3(grid), blk, 0, s, A);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

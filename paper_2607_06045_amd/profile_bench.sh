@@ -33,11 +33,11 @@ pmc copywrite WRITE_SIZE $CP || exit 1
 STATS=$(find "$OUT/trace" -name '*kernel_stats.csv' | head -1)
 python3 -m paper_2607_06045_amd.profiling stats --csv "$STATS" \
     --out "$OUT/summary/kernels_k_stage_blast22k.txt" \
-    --title "kernel durations, bench.py workload (Sedov blast, 22,156 leaves, N=3; 20 steps + kernel timing, FP64 then mixed; k_stage<3, 0, false, false> is the FP64 stage kernel, <3, 0, true, false> the mixed one)" \
+    --title "kernel durations, bench.py workload (Sedov blast, 22,156 leaves, N=3; 20 steps + kernel timing, FP64 then mixed; k_stage<3, 0, false, 0> is the FP64 stage kernel, <3, 0, true, 0> the mixed one)" \
     --command "$CMD" --trace-csv "$(find "$OUT/trace" -name '*kernel_trace.csv' | head -1)" \
-    --kernel "k_stage<3, 0, false, false>" --tail 150 --bench-log "$OUT/trace.log" || exit 1
+    --kernel "k_stage<3, 0, false, 0>" --tail 150 --bench-log "$OUT/trace.log" || exit 1
 python3 -m paper_2607_06045_amd.profiling traffic --fetch "$OUT/fetch" --write "$OUT/write" \
-    --copy-fetch "$OUT/copyfetch" --copy-write "$OUT/copywrite" --copy-mib 512 --kernel "k_stage<3, 0, false, false>" \
+    --copy-fetch "$OUT/copyfetch" --copy-write "$OUT/copywrite" --copy-mib 512 --kernel "k_stage<3, 0, false, 0>" \
     --workload "Sedov blast, 22,156 leaves, N=3, FP64; mean over the three stage configurations" \
     --dofs 354496 --algorithmic-bytes-per-node 85.33333333333333 \
     --out "$OUT/summary/traffic_k_stage_blast22k.json" --command "$CMD" || exit 1
