@@ -158,6 +158,15 @@ def main():
                     "ms_per_step": el_l / args.steps * 1e3, "kernel_ms": kml["stage"],
                     "dtype": "f64", "violations": stl["violations"],
                     "alpha_vol_mean": stl["alpha_vol_mean"]}
+    # combined limiting (eq. combination_posLim_local): local factors where the
+    # pressure shock indicator fires, positivity factors elsewhere, FP64
+    sc, el_c = run(P.FP64, P.LIMIT_COMBINED)
+    stc = sc.step(0.5, stats=True)
+    kmc = sc.time_kernels(reps=50)
+    out["combined"] = {"value": dofs * 3 * args.steps / el_c, "unit": "DOF-updates/s",
+                       "ms_per_step": el_c / args.steps * 1e3, "kernel_ms": kmc["stage"],
+                       "dtype": "f64", "violations": stc["violations"],
+                       "alpha_vol_mean": stc["alpha_vol_mean"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, N)
     print(json.dumps(out), flush=True)

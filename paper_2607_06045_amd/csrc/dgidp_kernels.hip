@@ -639,6 +639,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // smallest log entropy of the bar states across this lane's face node
     double ls_own = 0.0;
     double w_e = 0.0;  // combined limiting: weight of the local factors
+    bool need_loc = false;  // this element computes bounds and local factors (uniform per element)
     double fb_lo = __builtin_inf(), fb_hi = -__builtin_inf(), fb_ls = __builtin_inf();
     const double dtpart =
         A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
@@ -686,8 +687,12 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         sR[le][6][q] = z;
         const double lz = MIXED ? (double)__logf((float)z) : log(z);
         sR[le][7][q] = lz;
+        // the blend needs local factors only where the indicator fires, and at
+        // mortar nodes (their mortar may blend with another element's weight)
+        need_loc = LOC && (!COMB || w_e > 0.0 || fcode[0] >= 0 || fcode[1] >= 0 || fcode[2] >= 0 ||
+                           fcode[3] >= 0);
         // ln(p rho^-gamma) of the node itself, the bar state (i, i)
-        if (LOC) ls_own = MIXED ? log(me.p) - g * log(me.r) : (1.0 - g) * lr - lz;
+        if (need_loc) ls_own = MIXED ? log(me.p) - g * log(me.r) : (1.0 - g) * lr - lz;
         if (fnode) {
             fcode_f = fcode[ff];
             if (fcode_f < 0) {
@@ -742,7 +747,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             make_node(o, g);
             double F[4];
             llf_face(dff, lowf, own, o, F);
-            if (LOC) {
+            if (need_loc) {
                 bar_bounds(dff, lowf, own, o, g, fb_lo, fb_ls);
                 fb_hi = fb_lo;
             }
@@ -794,7 +799,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     make_node(us, g);
                     double Gf[4];
                     llf_face(dff, lowf, own, us, Gf);
-                    if (LOC) {
+                    if (need_loc) {
                         double rb, lb;
                         bar_bounds(dff, lowf, own, us, g, rb, lb);
                         fb_lo = fmin(fb_lo, rb);
@@ -840,7 +845,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 make_node(uj, g);
                 double Gf[4];
                 llf_face(dff, lowf, own, uj, Gf);
-                if (LOC) {
+                if (need_loc) {
                     double rb, lb;
                     bar_bounds(dff, lowf, own, uj, g, rb, lb);
                     fb_lo = fmin(fb_lo, rb);
@@ -978,7 +983,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             LDS_NODE(me, q);
             double F[4];
             llf_face(d, true, me, o, F);
-            if (LOC) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
+            if (need_loc) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
             const double hs = 0.5 * (d == 0 ? hy : hx), wl = pick(tb.w, line);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1014,7 +1019,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // sR rows 1..7 are no longer read: rows 1-4 take the bar states of the
     // subcell faces owned by this node (x: density, log entropy; y: the same),
     // rows 5-7 the face lanes' bar-state range across the element face
-    if (LOC && act) {
+    if (need_loc) {
         if (a < N) {
             sR[le][1][q] = brb[0];
             sR[le][2][q] = bls[0];
@@ -1106,7 +1111,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         if (!(uFV[0] > 0.0) || !(pFV > 0.0)) inad = 1;
         rmin = A.beta * uFV[0];
         pmin = A.beta * pFV;
-        if (LOC) {
+        if (need_loc) {
             // bounds over the node and the bar states of its low-order neighbours
             double rlo = u0[0];
             rhi = u0[0];
@@ -1153,7 +1158,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
             } else {
                 th = volume_factor<false>(uFV, cf, rmin, pmin, 0.0, 0.0, g, ig1);
-                if (COMB) thl = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
+                if (COMB && need_loc) thl = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
             }
         }
     }
