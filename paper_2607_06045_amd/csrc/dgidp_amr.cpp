@@ -19,29 +19,17 @@
 #include <vector>
 
 #include "dgidp_internal.h"
+#include "dgidp_leaves.h"
 
 namespace dgidp {
 
 namespace {
 
-struct LeafIndex {
-    std::unordered_map<uint64_t, int64_t> at;
-    static uint64_t key(int l, int64_t i, int64_t j)
-    {
-        return ((uint64_t)(uint32_t)l << 58) | ((uint64_t)i << 29) | (uint64_t)j;
-    }
-    int64_t get(int l, int64_t i, int64_t j) const
-    {
-        auto it = at.find(key(l, i, j));
-        return it == at.end() ? -1 : it->second;
-    }
-};
-
 inline int64_t pmod(int64_t a, int64_t m) { return ((a % m) + m) % m; }
 
 // leaves across face f of leaf e (one same-level or coarser leaf, or up to two
 // finer ones); returns the count
-int across(const LeafIndex& L, const int8_t* lev, const int32_t* ix, const int32_t* iy, int nx0,
+int across(const LeafLookup& L, const int8_t* lev, const int32_t* ix, const int32_t* iy, int nx0,
            int ny0, int64_t e, int f, int64_t out[2])
 {
     const int l = lev[e];
@@ -76,15 +64,13 @@ int adapt_leaves(int64_t E, const int8_t* lev, const int32_t* ix, const int32_t*
         err = "invalid adaptation arguments";
         return DGIDP_E_INVALID_ARG;
     }
-    LeafIndex L;
-    L.at.reserve((size_t)E * 2);
-    for (int64_t e = 0; e < E; ++e) {
+    for (int64_t e = 0; e < E; ++e)
         if (lev[e] >= 20 && flags[e] > 0) {
             err = "refinement beyond level 20";
             return DGIDP_E_INVALID_ARG;
         }
-        L.at.emplace(LeafIndex::key(lev[e], ix[e], iy[e]), e);
-    }
+    LeafLookup L;
+    L.build(E, lev, ix, iy, nx0, ny0);
     // rules 1-2
     std::vector<char> ref((size_t)E, 0);
     std::vector<int64_t> work;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "dgidp_internal.h"
+#include "dgidp_leaves.h"
 
 namespace dgidp {
 int build_and_upload_tables(int N, std::vector<double>* nodes);
@@ -172,8 +173,6 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         err = "invalid mesh arguments";
         return DGIDP_E_INVALID_ARG;
     }
-    std::unordered_map<uint64_t, int> find;
-    find.reserve((size_t)E * 2);
     double area = 0.0;
     int lmax = 0;
     for (int64_t e = 0; e < E; ++e) {
@@ -183,19 +182,21 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
             err = "leaf " + std::to_string(e) + " outside the root grid";
             return DGIDP_E_MESH_GAP_OR_OVERLAP;
         }
-        if (!find.emplace(key_of(l, ix[e], iy[e]), (int)e).second) {
-            err = "duplicate leaf " + std::to_string(e);
-            return DGIDP_E_MESH_GAP_OR_OVERLAP;
-        }
         area += std::ldexp(1.0, -2 * l);
         lmax = std::max(lmax, l);
+    }
+    LeafLookup find;
+    const int64_t dup = find.build(E, level, ix, iy, nx0, ny0);
+    if (dup >= 0) {
+        err = "duplicate leaf " + std::to_string(dup);
+        return DGIDP_E_MESH_GAP_OR_OVERLAP;
     }
     for (int64_t e = 0; e < E; ++e) {
         int64_t cx = ix[e], cy = iy[e];
         for (int l = level[e] - 1; l >= 0; --l) {
             cx >>= 1;
             cy >>= 1;
-            if (find.count(key_of(l, cx, cy))) {
+            if (find.get(l, cx, cy) >= 0) {
                 err = "leaf " + std::to_string(e) + " overlaps a coarser leaf";
                 return DGIDP_E_MESH_GAP_OR_OVERLAP;
             }
@@ -205,14 +206,7 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         err = "leaves do not tile the domain";
         return DGIDP_E_MESH_GAP_OR_OVERLAP;
     }
-    auto lookup = [&](int l, int64_t i, int64_t j) -> int {
-        if (l < 0 || l > 20) return -1;
-        const int64_t nx = (int64_t)nx0 << l, ny = (int64_t)ny0 << l;
-        i = ((i % nx) + nx) % nx;
-        j = ((j % ny) + ny) % ny;
-        auto it = find.find(key_of(l, i, j));
-        return it == find.end() ? -1 : it->second;
-    };
+    auto lookup = [&](int l, int64_t i, int64_t j) -> int { return (int)find.get_wrapped(l, i, j); };
     // internal order: Morton order of the leaves on the finest grid, cut into
     // the eight contiguous ranges that the stage kernel hands to the eight
     // XCDs; inside each range the leaves with a nonconforming face come first.
@@ -312,7 +306,10 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
     hm.snode.assign((size_t)M * NS, 0);
     hm.spart.assign((size_t)M * NS, -1);
     auto fq = [&](int f, int k) { return f == 0 ? k * n : (f == 1 ? k * n + N : (f == 2 ? k : N * n + k)); };
-    std::unordered_map<int, int> first;
+    // first slot of each node, -1 elsewhere; the buffer persists between calls
+    // (the entries used are reset below), so its pages are touched once
+    static thread_local std::vector<int> first;
+    if (first.size() < (size_t)E * NN) first.resize((size_t)E * NN, -1);
     for (int S = 0; S < M; ++S) {
         const int L = hm.mort[S * 4], f = hm.mort[S * 4 + 1];
         for (int j = 0; j < NS; ++j) {
@@ -329,15 +326,15 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
             const int node = e * NN + fq(ff, k);
             const int sid = S * NS + j;
             hm.snode[sid] = node;
-            auto it = first.find(node);
-            if (it == first.end()) {
+            if (first[node] < 0) {
                 first[node] = sid;
             } else {
-                hm.spart[sid] = it->second;
-                hm.spart[it->second] = sid;
+                hm.spart[sid] = first[node];
+                hm.spart[first[node]] = sid;
             }
         }
     }
+    for (size_t sid = 0; sid < hm.snode.size(); ++sid) first[hm.snode[sid]] = -1;
     hm.M = M;
     return 0;
 }

@@ -15,6 +15,13 @@
       indicators on the learned run's states, the element counts over time,
       the L1 density difference of the two runs (base-cell means) and wall times
 
+  python -m paper_2607_06045_amd.evaluate scale [--steps 500]
+      four-quadrant states on the 246,736-leaf mesh (N = 4) with dynamic AMR
+      every 5 steps: the plain FP64 method with the modal indicator against
+      the mixed-precision method with the learned indicator; reports
+      throughput (with and without the adaptation time), element counts,
+      sampled bound violations and the L1 density difference of the two runs
+
 Prints one JSON object.  All inputs are seeded and synthetic.
 """
 import argparse
@@ -274,14 +281,108 @@ def run_learned(steps, iters=3000, blasts=3, shears=2, snaps=6):
             "indicator_ms": t_ind}
 
 
+def run_scale(steps, iters=2000, seeds=2, snaps=3):
+    """Four-quadrant states on the 246,736-leaf mesh, N = 4, dynamic AMR every 5
+    steps up to level 2: the plain FP64 method with the modal indicator against
+    the mixed-precision method with the learned indicator (trained on the GPU
+    from N = 4 (features, modal indicator) pairs of other seeds)."""
+    import torch
+    import paper_2607_06045_amd as P
+    from workloads import states
+    from workloads.meshes import workload_mesh
+    spec = workload_mesh("quadrants247k")
+    N, n = 4, 5
+    ctrl = (0, 1, 0.01, 2, 0.1)  # levels relative to the 256 x 256 root grid
+    # training data: seeds other than the evaluated state's
+    X, Y = [], []
+    t0 = time.perf_counter()
+    for k in range(seeds):
+        s = _solver(P, spec, N)
+        x, y = s.node_coords()
+        s.upload(states.quadrants(x, y, seed=100 + k))
+        for i in range(snaps * 5):
+            if i % 5 == 0:
+                X.append(s.features(device=True))
+                Y.append(s.indicator(P.IND_HENNEMANN, device=True))
+            s.step(0.5, stats=False)
+        s.close()
+    X, Y = torch.cat(X), torch.cat(Y)
+    t_data = time.perf_counter() - t0
+    log(f"training on {X.shape[0]} samples")
+    t0 = time.perf_counter()
+    net = fit(P, X, Y, iters)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    w = net.mlp_get_weights()
+    u_fn = lambda x, y: states.workload_state("quadrants247k", x, y)  # noqa: E731
+
+    def plain(s):
+        return s.indicator(P.IND_HENNEMANN)
+
+    def learned(s):
+        if not getattr(s, "_w", False):
+            s.mlp_set_weights(w)
+            s._w = True
+        return s.indicator(P.IND_MLP)
+
+    def adapt_run_n4(indicator, precision):
+        s = P.Solver(N, precision=precision)
+        s.set_mesh(*spec.args())
+        x, y = s.node_coords()
+        s.upload(u_fn(x, y))
+        counts, viol, dof_updates, t_adapt = [], 0, 0, 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(steps):
+            if it % 5 == 0:
+                # steps are queued asynchronously: the adaptation interval
+                # starts when the queued steps have finished
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                lv, _, _ = s.mesh()
+                s.refine_coarsen(P.amr_flags(indicator(s), lv, *ctrl))
+                torch.cuda.synchronize()
+                t_adapt += time.perf_counter() - ta
+                counts.append(s.E)
+                if it % 100 == 0:
+                    log(f"  step {it}: {s.E} leaves")
+            st = s.step(0.5, stats=(it % 25 == 0))
+            if st:
+                viol += st["violations"]
+            dof_updates += 3 * s.E * n * n
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return s, {"wall_s": wall, "adapt_s": t_adapt, "dof_updates_per_s": dof_updates / wall,
+                   "dof_updates_per_s_steps_only": dof_updates / (wall - t_adapt),
+                   "elements_first_last_max": [counts[0], counts[-1], max(counts)],
+                   "violations_sampled": int(viol)}
+
+    log("plain FP64 run, modal indicator")
+    s_p, r_p = adapt_run_n4(plain, P.FP64)
+    log("mixed-precision run, learned indicator")
+    s_l, r_l = adapt_run_n4(learned, P.MIXED)
+    wts = P.host_tables(N)["w"]
+    mp = base_means(s_p, s_p.download(), wts, 0, spec.nx0, spec.ny0)[0]
+    ml = base_means(s_l, s_l.download(), wts, 0, spec.nx0, spec.ny0)[0]
+    return {"case": "four quadrant states (seed 5), 246,736-leaf start mesh, N=4, dynamic AMR every "
+                    "5 steps (levels 8-10)", "steps": steps,
+            "training": {"samples": int(X.shape[0]), "iters": iters, "data_s": t_data,
+                         "train_s": t_train},
+            "plain_fp64": r_p, "mixed_learned": r_l,
+            "l1_density_base_cells": float(np.abs(mp - ml).mean()),
+            "l1_density_scale": float(np.abs(mp).mean())}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["mixed", "learned"])
+    ap.add_argument("mode", choices=["mixed", "learned", "scale"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=3000)
     a = ap.parse_args(argv)
     if a.mode == "mixed":
         out = run_mixed(a.steps or 200)
+    elif a.mode == "scale":
+        out = run_scale(a.steps or 500, iters=a.iters)
     else:
         out = run_learned(a.steps or 100, iters=a.iters)
     print(json.dumps(out, default=float), flush=True)
