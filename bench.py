@@ -52,6 +52,27 @@ def measured_traffic(name):
     return d.get("bytes_per_launch")
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Measured device-to-device copy bandwidth (read + write bytes per second,
+    GB/s) of a plain torch copy in this process: the practical HBM ceiling that
+    the stage kernel's algorithmic bandwidth is also compared with."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) * 1e-3 / reps
+    del x, y
+    return 2.0 * mib * (1 << 20) / sec / 1e9
+
+
 def cpu_baseline(spec, N, seconds=12.0):
     """The oracle as it stands, timed on this host's cores on a bounded sample
     of the same workload (whole SSP-RK3 steps of the same mesh and state)."""
@@ -128,6 +149,9 @@ def main():
             "traffic": measured_traffic("traffic_k_stage_blast22k.json"),
             "kernel": "k_stage<3>", "kernel_ms": km["stage"], "bytes_per_launch": stage_bytes,
             "other_kernels_ms": {"k_mortar": km["mortar"], "k_dt": km["dt"]}}
+    copy_gbs = copy_bandwidth()
+    roof["copy_gbs_measured"] = copy_gbs
+    roof["frac_of_measured_copy"] = achieved / copy_gbs
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
