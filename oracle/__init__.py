@@ -45,6 +45,7 @@ def lib():
         L.orc_mesh_free.argtypes = [ctypes.c_void_p]
         L.orc_mesh_num_mortars.restype = ctypes.c_int64
         L.orc_mesh_num_mortars.argtypes = [ctypes.c_void_p]
+        L.orc_mesh_set_volume_flux.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_mesh_faces.argtypes = [ctypes.c_void_p, _I64]
         L.orc_mesh_mortars.argtypes = [ctypes.c_void_p, _I64]
         L.orc_mesh_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D]
@@ -196,8 +197,8 @@ def legendre(m, s):
 
 
 def flux(kind, uL, uR, direction, gamma):
-    """kind: 'phys', 'llf', 'ranocha'."""
-    k = {"phys": 0, "llf": 1, "ranocha": 2}[kind]
+    """kind: 'phys', 'llf', 'ranocha', 'chandrashekar'."""
+    k = {"phys": 0, "llf": 1, "ranocha": 2, "chandrashekar": 3}[kind]
     uL = np.ascontiguousarray(uL, dtype=np.float64)
     uR = np.ascontiguousarray(uR, dtype=np.float64)
     f = np.zeros(4)
@@ -223,7 +224,7 @@ def _stats(a):
 class Mesh:
     """A periodic quadtree mesh in the oracle, leaves given as (level, ix, iy)."""
 
-    def __init__(self, N, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0):
+    def __init__(self, N, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0, volume_flux="ranocha"):
         self.N, self.n = N, N + 1
         self.level = np.ascontiguousarray(level, dtype=np.int8)
         self.ix = np.ascontiguousarray(ix, dtype=np.int32)
@@ -236,6 +237,7 @@ class Mesh:
         if not self._h:
             raise ValueError(err.value.decode())
         self.M = lib().orc_mesh_num_mortars(self._h)
+        lib().orc_mesh_set_volume_flux(self._h, {"ranocha": 0, "chandrashekar": 1}[volume_flux])
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -41,6 +41,8 @@ void dgo_prim(const double* u, double gamma, double* rho, double* v1, double* v2
 void dgo_flux_phys(const double* u, int dir, double gamma, double* f);
 void dgo_flux_llf(const double* uL, const double* uR, int dir, double gamma, double* f);
 void dgo_flux_ranocha(const double* uL, const double* uR, int dir, double gamma, double* f);
+void dgo_flux_chandrashekar(const double* uL, const double* uR, int dir, double gamma, double* f);
+void dgo_flux_volume(int kind, const double* uL, const double* uR, int dir, double gamma, double* f);
 double dgo_lnmean(double x, double y);
 double dgo_pressure(const double* u, double gamma);
 double dgo_wavespeed(const double* u, int dir, double gamma);
@@ -74,6 +76,7 @@ typedef struct {
     dgo_face* face; /* [E][4] */
     int64_t M;
     dgo_mortar* mort;
+    int vflux; /* volume flux: 0 Ranocha, 1 Chandrashekar (Sec. 3.6) */
 } dgo_mesh;
 
 int dgo_mesh_build(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int32_t* ix,

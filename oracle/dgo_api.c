@@ -57,7 +57,8 @@ void orc_flux(int kind, const double* uL, const double* uR, int dir, double gamm
 {
     if (kind == 0) dgo_flux_phys(uL, dir, gamma, f);
     else if (kind == 1) dgo_flux_llf(uL, uR, dir, gamma, f);
-    else dgo_flux_ranocha(uL, uR, dir, gamma, f);
+    else if (kind == 2) dgo_flux_ranocha(uL, uR, dir, gamma, f);
+    else dgo_flux_chandrashekar(uL, uR, dir, gamma, f);
 }
 
 double orc_lnmean(double x, double y) { return dgo_lnmean(x, y); }
@@ -84,6 +85,8 @@ void orc_mesh_free(void* h)
 }
 
 int64_t orc_mesh_num_mortars(void* h) { return ((dgo_mesh*)h)->M; }
+
+void orc_mesh_set_volume_flux(void* h, int kind) { ((dgo_mesh*)h)->vflux = kind; }
 
 /* face table: [E][4] of (type, nbr, mortar, half) */
 void orc_mesh_faces(void* h, int64_t* out)

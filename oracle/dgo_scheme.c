@@ -197,10 +197,10 @@ static void volume_high(const dgo_mesh* m, const double* u, double gamma, int64_
             get_node(u, n, e, a, b, ui);
             for (int k = 0; k < n; ++k) {
                 get_node(u, n, e, k, b, uk);
-                dgo_flux_ranocha(ui, uk, 0, gamma, fs);
+                dgo_flux_volume(m->vflux, ui, uk, 0, gamma, fs);
                 for (int v = 0; v < 4; ++v) acc[v] -= B->w[b] * B->S[a][k] * (hy / 2.0) * fs[v];
                 get_node(u, n, e, a, k, uk);
-                dgo_flux_ranocha(ui, uk, 1, gamma, fs);
+                dgo_flux_volume(m->vflux, ui, uk, 1, gamma, fs);
                 for (int v = 0; v < 4; ++v) acc[v] -= B->w[a] * B->S[b][k] * (hx / 2.0) * fs[v];
             }
             for (int v = 0; v < 4; ++v) R[(v * n + b) * n + a] += acc[v];
@@ -851,7 +851,7 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
                                 get_node(u, n, e, line, l, ul);
                                 get_node(u, n, e, line, k, uk);
                             }
-                            dgo_flux_ranocha(ul, uk, dir, gamma, fs);
+                            dgo_flux_volume(m->vflux, ul, uk, dir, gamma, fs);
                             for (int v = 0; v < 4; ++v) fho[v] += B->S[l][k] * s * fs[v];
                         }
                     fv_face_flux(m, u, gamma, e, dir, line, a, ffv);
