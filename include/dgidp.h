@@ -45,6 +45,7 @@ enum { DGIDP_FP64 = 0, DGIDP_MIXED = 1 };           /* precision of the high-ord
 enum { DGIDP_DT_IDP = 0, DGIDP_DT_LOWORDER = 1 };   /* time-step rule */
 enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1, DGIDP_LIMIT_LOCAL = 2, DGIDP_LIMIT_COMBINED = 3 };
 enum { DGIDP_RHS_HIGH = 0, DGIDP_RHS_LOW = 1 };
+enum { DGIDP_FLUX_RANOCHA = 0, DGIDP_FLUX_CHANDRASHEKAR = 1 };  /* two-point volume flux */
 
 typedef struct dgidp_ctx dgidp_ctx;
 
@@ -72,7 +73,11 @@ typedef struct dgidp_ctx dgidp_ctx;
  *             computed from each stage's input; per mortar w is the largest
  *             indicator of its three elements; only the positivity bounds
  *             are guaranteed)
- *  strict_dt  if nonzero, dgidp_limit() rejects a dt above the IDP bound */
+ *  strict_dt  if nonzero, dgidp_limit() rejects a dt above the IDP bound
+ *  volume_flux  two-point flux of the volume flux differencing:
+ *             DGIDP_FLUX_RANOCHA (Ranocha's entropy-conserving, kinetic-energy-
+ *             preserving flux, Sec. 3 intro; 0, the default of a zeroed struct)
+ *             or DGIDP_FLUX_CHANDRASHEKAR (Chandrashekar's, Sec. 3.6) */
 typedef struct {
     int N;
     double gamma;
@@ -81,6 +86,7 @@ typedef struct {
     int dt_mode;
     int limiter;
     int strict_dt;
+    int volume_flux;
 } dgidp_params;
 
 /* Statistics of one limited forward-Euler step or one SSP-RK3 step (summed or

@@ -2,6 +2,7 @@
 
 The compute path is libdgidp.so (include/dgidp.h); this package only binds it.
 """
-from ._lib import (FP64, MIXED, DT_IDP, DT_LOWORDER, LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED,  # noqa: F401
+from ._lib import (FP64, MIXED, DT_IDP, DT_LOWORDER, LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED,
+                   FLUX_RANOCHA, FLUX_CHANDRASHEKAR,  # noqa: F401
                    RHS_HIGH, RHS_LOW, DgidpError, Solver, host_tables, exported_symbols,
                    validate_mesh, adapt_leaves, amr_flags, IND_HENNEMANN, IND_MLP, MLP_NPARAM)

@@ -20,6 +20,7 @@ if not os.path.exists(LIB_PATH):
 FP64, MIXED = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
 LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED = 0, 1, 2, 3
+FLUX_RANOCHA, FLUX_CHANDRASHEKAR = 0, 1
 RHS_HIGH, RHS_LOW = 0, 1
 IND_HENNEMANN, IND_MLP = 0, 1
 MLP_NPARAM = 5313
@@ -35,7 +36,8 @@ ERRORS = {
 class Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("dt_mode", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("strict_dt", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("strict_dt", ctypes.c_int),
+                ("volume_flux", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -181,12 +183,12 @@ class Solver:
     """One dgidp context: a mesh, a state on the GPU and the stepping entry points."""
 
     def __init__(self, N=3, gamma=1.4, beta=0.1, precision=FP64, dt_mode=DT_IDP,
-                 limiter=LIMIT_POSITIVITY, strict_dt=False, stream=None):
+                 limiter=LIMIT_POSITIVITY, strict_dt=False, stream=None, volume_flux=FLUX_RANOCHA):
         if not torch.cuda.is_available():
             raise DgidpError("dgidp needs a ROCm GPU; none is visible")
         self.N, self.n = N, N + 1
         self.gamma = gamma
-        self.params = Params(N, gamma, beta, precision, dt_mode, limiter, int(strict_dt))
+        self.params = Params(N, gamma, beta, precision, dt_mode, limiter, int(strict_dt), volume_flux)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _vp()
         rc = _lib.dgidp_create(ctypes.byref(self.params), _vp(self.stream.cuda_stream),

@@ -346,6 +346,7 @@ KernelParams kparams(const dgidp_ctx* c)
     k.beta = c->p.beta;
     k.limiter = c->p.limiter;
     k.precision = c->p.precision;
+    k.vflux = c->p.volume_flux;
     return k;
 }
 
@@ -387,7 +388,8 @@ int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
         (p->precision != DGIDP_FP64 && p->precision != DGIDP_MIXED) ||
         (p->dt_mode != DGIDP_DT_IDP && p->dt_mode != DGIDP_DT_LOWORDER) ||
         (p->limiter != DGIDP_LIMIT_NONE && p->limiter != DGIDP_LIMIT_POSITIVITY &&
-         p->limiter != DGIDP_LIMIT_LOCAL && p->limiter != DGIDP_LIMIT_COMBINED))
+         p->limiter != DGIDP_LIMIT_LOCAL && p->limiter != DGIDP_LIMIT_COMBINED) ||
+        (p->volume_flux != DGIDP_FLUX_RANOCHA && p->volume_flux != DGIDP_FLUX_CHANDRASHEKAR))
         return DGIDP_E_INVALID_ARG;
     dgidp_ctx* ctx = new dgidp_ctx();
     ctx->p = *p;

@@ -68,6 +68,7 @@ struct KernelParams {
     double gamma, beta;
     int limiter;
     int precision;
+    int vflux;
 };
 
 // the dt maximum is merged into kDtSpread accumulators kDtStride words apart

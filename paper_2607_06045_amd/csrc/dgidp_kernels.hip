@@ -537,6 +537,7 @@ struct StageArgs {
     int E;
     double gamma, beta;
     int limiter;
+    int vflux;  // two-point volume flux: DGIDP_FLUX_RANOCHA or DGIDP_FLUX_CHANDRASHEKAR
     DevStats* st;
 };
 
@@ -934,10 +935,21 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 const double fr = rho_ln * 0.5 * (vnL + vnR);
                 const double pa = 0.5 * (L[3] + R[3]);
                 f[0] = fr;
-                f[1] = fr * 0.5 * (L[1] + R[1]) + (d == 0 ? pa : 0.0);
-                f[2] = fr * 0.5 * (L[2] + R[2]) + (d == 1 ? pa : 0.0);
-                f[3] = fr * (0.5 * (L[1] * R[1] + L[2] * R[2]) + ig1 * iz_ln) +
-                       0.5 * (L[3] * vnR + R[3] * vnL);
+                if (A.vflux == DGIDP_FLUX_CHANDRASHEKAR) {
+                    // Chandrashekar: beta = z / 2, so p~ = rho-bar / (2 beta-bar) =
+                    // (rho_L + rho_R) / (z_L + z_R) and 1 / (2 beta^ln) = 1 / z^ln
+                    const double pt = (L[0] + R[0]) / (L[6] + R[6]);
+                    const double v1a = 0.5 * (L[1] + R[1]), v2a = 0.5 * (L[2] + R[2]);
+                    f[1] = fr * v1a + (d == 0 ? pt : 0.0);
+                    f[2] = fr * v2a + (d == 1 ? pt : 0.0);
+                    f[3] = fr * (ig1 * iz_ln - 0.25 * (L[1] * L[1] + L[2] * L[2] + R[1] * R[1] + R[2] * R[2])) +
+                           v1a * f[1] + v2a * f[2];
+                } else {
+                    f[1] = fr * 0.5 * (L[1] + R[1]) + (d == 0 ? pa : 0.0);
+                    f[2] = fr * 0.5 * (L[2] + R[2]) + (d == 1 ? pa : 0.0);
+                    f[3] = fr * (0.5 * (L[1] * R[1] + L[2] * R[2]) + ig1 * iz_ln) +
+                           0.5 * (L[3] * vnR + R[3] * vnL);
+                }
             } else {
                 const float rho_ln = lnmeanf((float)L[0], (float)R[0], (float)L[5], (float)R[5]);
                 const float iz_ln = inv_lnmeanf((float)L[6], (float)R[6], (float)L[7], (float)R[7]);
@@ -947,10 +959,19 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 const float fr = rho_ln * 0.5f * (vnL + vnR);
                 const float pa = 0.5f * (pL + pR);
                 f[0] = fr;
-                f[1] = fr * 0.5f * (v1L + v1R) + (d == 0 ? pa : 0.0f);
-                f[2] = fr * 0.5f * (v2L + v2R) + (d == 1 ? pa : 0.0f);
-                f[3] = fr * (0.5f * (v1L * v1R + v2L * v2R) + (float)ig1 * iz_ln) +
-                       0.5f * (pL * vnR + pR * vnL);
+                if (A.vflux == DGIDP_FLUX_CHANDRASHEKAR) {
+                    const float pt = ((float)L[0] + (float)R[0]) / ((float)L[6] + (float)R[6]);
+                    const float v1a = 0.5f * (v1L + v1R), v2a = 0.5f * (v2L + v2R);
+                    f[1] = fr * v1a + (d == 0 ? pt : 0.0f);
+                    f[2] = fr * v2a + (d == 1 ? pt : 0.0f);
+                    f[3] = fr * ((float)ig1 * iz_ln - 0.25f * (v1L * v1L + v2L * v2L + v1R * v1R + v2R * v2R)) +
+                           v1a * (float)f[1] + v2a * (float)f[2];
+                } else {
+                    f[1] = fr * 0.5f * (v1L + v1R) + (d == 0 ? pa : 0.0f);
+                    f[2] = fr * 0.5f * (v2L + v2R) + (d == 1 ? pa : 0.0f);
+                    f[3] = fr * (0.5f * (v1L * v1R + v2L * v2R) + (float)ig1 * iz_ln) +
+                           0.5f * (pL * vnR + pR * vnL);
+                }
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) sPair[le][v][p] = scale * f[v];
@@ -1901,6 +1922,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.gamma = kp.gamma;
     A.beta = kp.beta;
     A.limiter = kp.limiter;
+    A.vflux = kp.vflux;
     A.st = st;
     const int grid = (m.E + G::EPB - 1) / G::EPB;
     const bool mixed = kp.precision == DGIDP_MIXED;
