@@ -21,6 +21,7 @@ _lib = None
 RHS_HIGH, RHS_LOW = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
 LIM_NONE, LIM_POSITIVITY, LIM_LOCAL, LIM_COMBINED = 0, 1, 2, 3
+BC_PERIODIC, BC_WALL, BC_CHARACTERISTIC, BC_OUTFLOW = 0, 1, 2, 3
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
@@ -42,6 +43,15 @@ def lib():
                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_char_p, ctypes.c_int]
+        L.orc_mesh_new_bc.restype = ctypes.c_void_p
+        L.orc_mesh_new_bc.argtypes = L.orc_mesh_new.argtypes[:11] + [ctypes.c_void_p, ctypes.c_void_p,
+                                                                     ctypes.c_char_p, ctypes.c_int]
+        L.orc_mesh_num_bnodes.restype = ctypes.c_int64
+        L.orc_mesh_num_bnodes.argtypes = [ctypes.c_void_p]
+        L.orc_mesh_boundary_nodes.argtypes = [ctypes.c_void_p, _I64]
+        L.orc_mesh_set_boundary_states.restype = ctypes.c_int
+        L.orc_mesh_set_boundary_states.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _D]
+        L.orc_boundary_ghost.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_double, _D]
         L.orc_mesh_free.argtypes = [ctypes.c_void_p]
         L.orc_mesh_num_mortars.restype = ctypes.c_int64
         L.orc_mesh_num_mortars.argtypes = [ctypes.c_void_p]
@@ -175,6 +185,15 @@ def bar_state(uL, uR, direction, gamma):
     return ub
 
 
+def boundary_ghost(kind, ext, ui, face, gamma=1.4):
+    """Ghost state of a boundary node with interior state ui on face 0..3."""
+    ext = np.ascontiguousarray(ext, dtype=np.float64)
+    ui = np.ascontiguousarray(ui, dtype=np.float64)
+    ug = np.zeros(4)
+    lib().orc_boundary_ghost(kind, _ptr(ext), _ptr(ui), face, gamma, _ptr(ug))
+    return ug
+
+
 def spec_entropy(u, gamma):
     """Specific entropy p rho^-gamma (0 outside the admissible set)."""
     u = np.ascontiguousarray(u, dtype=np.float64)
@@ -222,9 +241,14 @@ def _stats(a):
 
 
 class Mesh:
-    """A periodic quadtree mesh in the oracle, leaves given as (level, ix, iy)."""
+    """A quadtree mesh in the oracle, leaves given as (level, ix, iy).  bc gives
+    the condition of the sides (x-, x+, y-, y+), each BC_PERIODIC (default),
+    BC_WALL, BC_CHARACTERISTIC or BC_OUTFLOW, and ext [4, 4] each side's
+    exterior state (conservative); set_boundary_states overrides both per
+    boundary node."""
 
-    def __init__(self, N, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0, volume_flux="ranocha"):
+    def __init__(self, N, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0, volume_flux="ranocha",
+                 bc=None, ext=None):
         self.N, self.n = N, N + 1
         self.level = np.ascontiguousarray(level, dtype=np.int8)
         self.ix = np.ascontiguousarray(ix, dtype=np.int32)
@@ -232,11 +256,16 @@ class Mesh:
         self.E = len(self.level)
         self.box = (x0, y0, Lx, Ly, nx0, ny0)
         err = ctypes.create_string_buffer(256)
-        self._h = lib().orc_mesh_new(N, self.E, self.level.ctypes.data, self.ix.ctypes.data,
-                                     self.iy.ctypes.data, x0, y0, Lx, Ly, nx0, ny0, err, 256)
+        self._bc = None if bc is None else np.ascontiguousarray(bc, dtype=np.int32)
+        self._ext = None if ext is None else np.ascontiguousarray(ext, dtype=np.float64).reshape(4, 4)
+        self._h = lib().orc_mesh_new_bc(
+            N, self.E, self.level.ctypes.data, self.ix.ctypes.data, self.iy.ctypes.data, x0, y0, Lx,
+            Ly, nx0, ny0, None if self._bc is None else self._bc.ctypes.data,
+            None if self._ext is None else self._ext.ctypes.data, err, 256)
         if not self._h:
             raise ValueError(err.value.decode())
         self.M = lib().orc_mesh_num_mortars(self._h)
+        self.NB = lib().orc_mesh_num_bnodes(self._h)
         lib().orc_mesh_set_volume_flux(self._h, {"ranocha": 0, "chandrashekar": 1}[volume_flux])
 
     def __del__(self):
@@ -248,6 +277,20 @@ class Mesh:
         out = np.zeros((self.E, 4, 4), dtype=np.int64)
         lib().orc_mesh_faces(self._h, _ptr(out, _I64))
         return out
+
+    def boundary_nodes(self):
+        """[NB, 3] (element, face, node along the face) of every boundary node,
+        in the order of set_boundary_states."""
+        out = np.zeros((max(self.NB, 1), 3), dtype=np.int64)
+        lib().orc_mesh_boundary_nodes(self._h, _ptr(out, _I64))
+        return out[: self.NB]
+
+    def set_boundary_states(self, kind, ext):
+        kind = np.ascontiguousarray(kind, dtype=np.int8)
+        ext = np.ascontiguousarray(ext, dtype=np.float64)
+        assert kind.shape == (self.NB,) and ext.shape == (self.NB, 4)
+        if lib().orc_mesh_set_boundary_states(self._h, kind.ctypes.data, _ptr(ext)):
+            raise ValueError("boundary condition out of range")
 
     def mortars(self):
         out = np.zeros((max(self.M, 1), 4), dtype=np.int64)

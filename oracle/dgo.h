@@ -48,13 +48,18 @@ double dgo_pressure(const double* u, double gamma);
 double dgo_wavespeed(const double* u, int dir, double gamma);
 
 /* ---------------- mesh ---------------- */
-enum { FACE_CONF = 0, FACE_SMALL = 1, FACE_LARGE = 2 };
+enum { FACE_CONF = 0, FACE_SMALL = 1, FACE_LARGE = 2, FACE_BOUNDARY = 3 };
+/* boundary conditions of the domain sides (x-, x+, y-, y+) and of boundary nodes:
+   reflecting slip wall, characteristic inflow/outflow against an exterior state,
+   and plain outflow (the exterior state is the interior one) */
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_CHARACTERISTIC = 2, BC_OUTFLOW = 3 };
 
 typedef struct {
     int type;       /* FACE_CONF / FACE_SMALL / FACE_LARGE */
     int64_t nbr;    /* conforming neighbour element (FACE_CONF) or large element (FACE_SMALL) */
     int64_t mortar; /* mortar id (FACE_SMALL / FACE_LARGE), else -1 */
     int half;       /* FACE_SMALL: 0 = lower half of the large face, 1 = upper */
+    int64_t bnode;  /* FACE_BOUNDARY: index of its node 0 among the boundary nodes */
 } dgo_face;
 
 typedef struct {
@@ -77,11 +82,26 @@ typedef struct {
     int64_t M;
     dgo_mortar* mort;
     int vflux; /* volume flux: 0 Ranocha, 1 Chandrashekar (Sec. 3.6) */
+    int bc[4];      /* per domain side; x- and x+ (y- and y+) periodic together */
+    /* boundary nodes, numbered by (element, face, node along the face): the
+       condition of each and its exterior state (conservative) */
+    int64_t NB;
+    int8_t* bkind;
+    double* bext; /* [NB][4] */
 } dgo_mesh;
 
 int dgo_mesh_build(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int32_t* ix,
                    const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
                    int ny0, char* err, int errlen);
+/* the same with boundary conditions bc[4] per side (NULL: all periodic) and
+   an exterior state ext[4][4] per side (NULL: zero); every boundary node starts
+   with its side's condition and exterior state */
+int dgo_mesh_build_bc(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int32_t* ix,
+                      const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
+                      int ny0, const int* bc, const double* ext, char* err, int errlen);
+/* the ghost state of a boundary node with interior state ui on face f */
+void dgo_boundary_ghost(int kind, const double* ext, const double* ui, int f, double gamma,
+                        double* ug);
 void dgo_mesh_release(dgo_mesh* m);
 
 /* ---------------- scheme ---------------- */

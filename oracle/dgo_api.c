@@ -84,7 +84,58 @@ void orc_mesh_free(void* h)
     free(m);
 }
 
+void* orc_mesh_new_bc(int N, int64_t E, const int8_t* level, const int32_t* ix, const int32_t* iy,
+                      double x0, double y0, double Lx, double Ly, int nx0, int ny0, const int* bc,
+                      const double* ext, char* err, int errlen)
+{
+    dgo_mesh* m = (dgo_mesh*)malloc(sizeof(dgo_mesh));
+    if (dgo_mesh_build_bc(m, N, E, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0, bc, ext, err, errlen)) {
+        dgo_mesh_release(m);
+        free(m);
+        return 0;
+    }
+    return m;
+}
+
 int64_t orc_mesh_num_mortars(void* h) { return ((dgo_mesh*)h)->M; }
+
+int64_t orc_mesh_num_bnodes(void* h) { return ((dgo_mesh*)h)->NB; }
+
+/* boundary nodes: [NB][3] of (element, face, node along the face) */
+void orc_mesh_boundary_nodes(void* h, int64_t* out)
+{
+    dgo_mesh* m = (dgo_mesh*)h;
+    for (int64_t e = 0; e < m->E; ++e)
+        for (int f = 0; f < 4; ++f) {
+            const dgo_face* F = &m->face[e * 4 + f];
+            if (F->type != FACE_BOUNDARY) continue;
+            for (int k = 0; k < m->B.n; ++k) {
+                out[(F->bnode + k) * 3 + 0] = e;
+                out[(F->bnode + k) * 3 + 1] = f;
+                out[(F->bnode + k) * 3 + 2] = k;
+            }
+        }
+}
+
+/* per boundary node condition (BC_WALL, BC_CHARACTERISTIC, BC_OUTFLOW) and
+   exterior state; -1 if a condition is out of range */
+int orc_mesh_set_boundary_states(void* h, const int8_t* kind, const double* ext)
+{
+    dgo_mesh* m = (dgo_mesh*)h;
+    for (int64_t j = 0; j < m->NB; ++j)
+        if (kind[j] < BC_WALL || kind[j] > BC_OUTFLOW) return -1;
+    for (int64_t j = 0; j < m->NB; ++j) {
+        m->bkind[j] = kind[j];
+        for (int v = 0; v < 4; ++v) m->bext[j * 4 + v] = ext[j * 4 + v];
+    }
+    return 0;
+}
+
+void orc_boundary_ghost(int kind, const double* ext, const double* ui, int f, double gamma,
+                        double* ug)
+{
+    dgo_boundary_ghost(kind, ext, ui, f, gamma, ug);
+}
 
 void orc_mesh_set_volume_flux(void* h, int kind) { ((dgo_mesh*)h)->vflux = kind; }
 

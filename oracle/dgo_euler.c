@@ -120,3 +120,45 @@ void dgo_flux_volume(int kind, const double* uL, const double* uR, int dir, doub
     if (kind == 1) dgo_flux_chandrashekar(uL, uR, dir, gamma, f);
     else dgo_flux_ranocha(uL, uR, dir, gamma, f);
 }
+
+/* Ghost state of a boundary node; the double Mach reflection and the jet of
+   Sec. 3.6 use slip walls and characteristic inflow/outflow.  Face f is 0 x-,
+   1 x+, 2 y-, 3 y+; the outward normal is the axis of direction f / 2, negated
+   on the even faces.
+   - slip wall: the interior state with its normal momentum reversed (the LLF
+     flux against it carries no mass and no energy through the face);
+   - characteristic: chosen by the outward normal velocity vn and the sound
+     speed c of the interior state: vn <= -c (supersonic inflow) the exterior
+     state; -c < vn <= 0 (subsonic inflow) the exterior density and velocity
+     with the interior pressure; 0 < vn < c (subsonic outflow) the interior
+     density and velocity with the exterior pressure; vn >= c (supersonic
+     outflow) the interior state;
+   - outflow: the interior state. */
+void dgo_boundary_ghost(int kind, const double* ext, const double* ui, int f, double gamma,
+                        double* ug)
+{
+    int dir = f / 2;
+    for (int v = 0; v < 4; ++v) ug[v] = ui[v];
+    if (kind == BC_WALL) {
+        ug[1 + dir] = -ui[1 + dir];
+        return;
+    }
+    if (kind != BC_CHARACTERISTIC) return;
+    double r, v1, v2, p;
+    dgo_prim(ui, gamma, &r, &v1, &v2, &p);
+    double vn = (dir == 0 ? v1 : v2) * ((f & 1) ? 1.0 : -1.0);
+    double c = sqrt(gamma * p / r);
+    if (vn >= c) return;
+    double re, v1e, v2e, pe;
+    dgo_prim(ext, gamma, &re, &v1e, &v2e, &pe);
+    if (vn <= -c) {
+        for (int v = 0; v < 4; ++v) ug[v] = ext[v];
+    } else if (vn <= 0.0) { /* exterior density and velocity, interior pressure */
+        ug[0] = re;
+        ug[1] = re * v1e;
+        ug[2] = re * v2e;
+        ug[3] = p / (gamma - 1.0) + 0.5 * re * (v1e * v1e + v2e * v2e);
+    } else { /* interior density and velocity, exterior pressure */
+        ug[3] = pe / (gamma - 1.0) + 0.5 * r * (v1 * v1 + v2 * v2);
+    }
+}

@@ -5,8 +5,9 @@
  * root grid covers [x0 + ix Lx/(nx0 2^l), x0 + (ix+1) Lx/(nx0 2^l)] x [...]
  * (Sec. 3.1: quadtree with leaves as elements).  Neighbouring leaves differ by
  * at most one level across a face (Sec. 2.2: 2-to-1 nonconforming interfaces).
- * Every face is classified as conforming, small side of a mortar, or large side
- * of a mortar; mortars are numbered in order of (large element, face).
+ * Every face is classified as conforming, small side of a mortar, large side
+ * of a mortar, or (on a non-periodic domain side) boundary; mortars are
+ * numbered in order of (large element, face).
  */
 #include <stdio.h>
 #include <stdlib.h>
@@ -51,7 +52,28 @@ int dgo_mesh_build(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int
                    const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
                    int ny0, char* err, int errlen)
 {
+    return dgo_mesh_build_bc(m, N, E, level, ix, iy, x0, y0, Lx, Ly, nx0, ny0, 0, 0, err, errlen);
+}
+
+int dgo_mesh_build_bc(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int32_t* ix,
+                      const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
+                      int ny0, const int* bc, const double* ext, char* err, int errlen)
+{
     memset(m, 0, sizeof(*m));
+    if (bc) {
+        for (int f = 0; f < 4; ++f) {
+            if (bc[f] < BC_PERIODIC || bc[f] > BC_OUTFLOW) {
+                snprintf(err, errlen, "unknown boundary condition %d", bc[f]);
+                return -1;
+            }
+            m->bc[f] = bc[f];
+        }
+        if ((m->bc[0] == BC_PERIODIC) != (m->bc[1] == BC_PERIODIC) ||
+            (m->bc[2] == BC_PERIODIC) != (m->bc[3] == BC_PERIODIC)) {
+            snprintf(err, errlen, "opposite sides must both be periodic or both not");
+            return -1;
+        }
+    }
     if (dgo_basis_init(&m->B, N)) {
         snprintf(err, errlen, "unsupported N=%d", N);
         return -1;
@@ -131,6 +153,14 @@ int dgo_mesh_build(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int
             int dx = f == 0 ? -1 : (f == 1 ? 1 : 0);
             int dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
             int64_t nx = (int64_t)ix[e] + dx, ny = (int64_t)iy[e] + dy;
+            /* a face on a non-periodic domain side */
+            if (m->bc[f] != BC_PERIODIC &&
+                (nx < 0 || ny < 0 || nx >= ((int64_t)nx0 << l) || ny >= ((int64_t)ny0 << l))) {
+                F->type = FACE_BOUNDARY;
+                F->bnode = m->NB;
+                m->NB += N + 1;
+                continue;
+            }
             int64_t g = find(&L, l, nx, ny);
             if (g >= 0) {
                 F->type = FACE_CONF;
@@ -171,6 +201,18 @@ int dgo_mesh_build(dgo_mesh* m, int N, int64_t E, const int8_t* level, const int
         }
     }
     m->M = nmort;
+    m->bkind = (int8_t*)malloc(m->NB > 0 ? m->NB : 1);
+    m->bext = (double*)calloc((m->NB > 0 ? m->NB : 1) * 4, sizeof(double));
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f) {
+            const dgo_face* F = &m->face[e * 4 + f];
+            if (F->type != FACE_BOUNDARY) continue;
+            for (int k = 0; k <= N; ++k) {
+                m->bkind[F->bnode + k] = (int8_t)m->bc[f];
+                if (ext)
+                    for (int v = 0; v < 4; ++v) m->bext[(F->bnode + k) * 4 + v] = ext[f * 4 + v];
+            }
+        }
     m->mort = (dgo_mortar*)malloc((nmort > 0 ? nmort : 1) * sizeof(dgo_mortar));
     for (int64_t e = 0; e < E; ++e)
         for (int f = 0; f < 4; ++f) {
@@ -217,5 +259,7 @@ void dgo_mesh_release(dgo_mesh* m)
     free(m->hy);
     free(m->face);
     free(m->mort);
+    free(m->bkind);
+    free(m->bext);
     memset(m, 0, sizeof(*m));
 }

@@ -121,6 +121,8 @@ static void mortar_contrib(const dgo_mesh* m, const double* u, double gamma, int
             }
 }
 
+static int is_mortar(int type) { return type == FACE_SMALL || type == FACE_LARGE; }
+
 /* slot of node k along face f of element e, or -1 if that face is not a mortar */
 static int64_t face_slot(const dgo_mesh* m, int64_t e, int f, int k)
 {
@@ -131,19 +133,34 @@ static int64_t face_slot(const dgo_mesh* m, int64_t e, int f, int k)
     return -1;
 }
 
-/* conforming face contribution to R of node k of face f of element e */
+/* the state across face f at node k of element e, whose own state is ui: the
+   matching node of the neighbour (conforming face) or the ghost state of the
+   node's boundary condition (boundary face) */
+static void across_node(const dgo_mesh* m, const double* u, double gamma, int64_t e, int f, int k,
+                        const double* ui, double* uo)
+{
+    const dgo_face* F = &m->face[e * 4 + f];
+    if (F->type == FACE_BOUNDARY) {
+        int64_t j = F->bnode + k;
+        dgo_boundary_ghost(m->bkind[j], m->bext + j * 4, ui, f, gamma, uo);
+        return;
+    }
+    int a2, b2;
+    face_node(f ^ 1, k, m->B.N, &a2, &b2);
+    get_node(u, m->B.n, F->nbr, a2, b2, uo);
+}
+
+/* conforming or boundary face contribution to R of node k of face f of element e */
 static void conf_face(const dgo_mesh* m, const double* u, double gamma, int64_t e, int f, int k,
                       double* r)
 {
     const dgo_basis* B = &m->B;
     int N = B->N, n = B->n;
-    const dgo_face* F = &m->face[e * 4 + f];
-    int a, b, a2, b2;
+    int a, b;
     face_node(f, k, N, &a, &b);
-    face_node(f ^ 1, k, N, &a2, &b2);
     double ui[4], uo[4], Fl[4];
     get_node(u, n, e, a, b, ui);
-    get_node(u, n, F->nbr, a2, b2, uo);
+    across_node(m, u, gamma, e, f, k, ui, uo);
     int dir = f / 2;
     double W = B->w[k] * face_len(m, e, f) / 2.0;
     if (f & 1) { /* element on the low side */
@@ -166,7 +183,7 @@ static void add_surface(const dgo_mesh* m, const double* u, double gamma, const 
             int a, b;
             face_node(f, k, N, &a, &b);
             double r[4];
-            if (F->type == FACE_CONF) {
+            if (F->type == FACE_CONF || F->type == FACE_BOUNDARY) {
                 conf_face(m, u, gamma, e, f, k, r);
             } else {
                 int64_t s = face_slot(m, e, f, k);
@@ -337,11 +354,9 @@ double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, doub
                 face_node(f, k, N, &a, &b);
                 double ui[4];
                 get_node(u, n, e, a, b, ui);
-                if (F->type == FACE_CONF) {
-                    int a2, b2;
-                    face_node(f ^ 1, k, N, &a2, &b2);
+                if (F->type == FACE_CONF || F->type == FACE_BOUNDARY) {
                     double uo[4];
-                    get_node(u, n, F->nbr, a2, b2, uo);
+                    across_node(m, u, gamma, e, f, k, ui, uo);
                     sum[b * n + a] += 2 * B->w[k] * face_len(m, e, f) / 4.0 * lam_pair(ui, uo, dir, gamma);
                 } else if (F->type == FACE_LARGE) {
                     const dgo_mortar* M = &m->mort[F->mortar];
@@ -507,10 +522,8 @@ void dgo_local_bounds(const dgo_mesh* m, const double* u, double gamma, double* 
                     if (k < 0) continue;
                     const dgo_face* F = &m->face[e * 4 + f];
                     int dir = f / 2, own_low = f & 1;
-                    if (F->type == FACE_CONF) {
-                        int a2, b2;
-                        face_node(f ^ 1, k, N, &a2, &b2);
-                        get_node(u, n, F->nbr, a2, b2, uo);
+                    if (F->type == FACE_CONF || F->type == FACE_BOUNDARY) {
+                        across_node(m, u, gamma, e, f, k, ui, uo);
                         bound_edge(ui, uo, own_low, dir, gamma, &lo, &hi, &sm);
                     } else if (F->type == FACE_LARGE) {
                         const dgo_mortar* M = &m->mort[F->mortar];
@@ -944,10 +957,10 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
                 int a, b;
                 face_node(f, k, N, &a, &b);
                 int ni = 0;
-                if (a == 0 && m->face[e * 4 + 0].type != FACE_CONF) ni++;
-                if (a == N && m->face[e * 4 + 1].type != FACE_CONF) ni++;
-                if (b == 0 && m->face[e * 4 + 2].type != FACE_CONF) ni++;
-                if (b == N && m->face[e * 4 + 3].type != FACE_CONF) ni++;
+                if (a == 0 && is_mortar(m->face[e * 4 + 0].type)) ni++;
+                if (a == N && is_mortar(m->face[e * 4 + 1].type)) ni++;
+                if (b == 0 && is_mortar(m->face[e * 4 + 2].type)) ni++;
+                if (b == N && is_mortar(m->face[e * 4 + 3].type)) ni++;
                 double mi = mass(m, e, a, b);
                 double q[4], dc[4];
                 const double* ho = HO + (S * 3 * n + s) * 4;
