@@ -46,6 +46,8 @@ enum { DGIDP_DT_IDP = 0, DGIDP_DT_LOWORDER = 1 };   /* time-step rule */
 enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1, DGIDP_LIMIT_LOCAL = 2, DGIDP_LIMIT_COMBINED = 3 };
 enum { DGIDP_RHS_HIGH = 0, DGIDP_RHS_LOW = 1 };
 enum { DGIDP_FLUX_RANOCHA = 0, DGIDP_FLUX_CHANDRASHEKAR = 1 };  /* two-point volume flux */
+/* boundary condition of a domain side or boundary node */
+enum { DGIDP_BC_PERIODIC = 0, DGIDP_BC_WALL = 1, DGIDP_BC_CHARACTERISTIC = 2, DGIDP_BC_OUTFLOW = 3 };
 
 typedef struct dgidp_ctx dgidp_ctx;
 
@@ -115,7 +117,8 @@ int dgidp_set_stream(dgidp_ctx* ctx, void* stream);
 int dgidp_synchronize(dgidp_ctx* ctx);
 
 /* Upload a quadtree mesh (Sec. 3.1: leaves are the elements).  The root grid
- * is nx0 x ny0 on [x0, x0+Lx] x [y0, y0+Ly], periodic in both directions; leaf
+ * is nx0 x ny0 on [x0, x0+Lx] x [y0, y0+Ly], periodic in both directions
+ * unless dgidp_set_boundaries said otherwise; leaf
  * e covers cell (ix[e], iy[e]) of the (nx0 2^level[e]) x (ny0 2^level[e]) grid.
  * Neighbours across a face may differ by one level (Sec. 2.2: 2-to-1
  * nonconforming interfaces).  Host arrays, copied.  Replaces any previous mesh
@@ -124,12 +127,46 @@ int dgidp_synchronize(dgidp_ctx* ctx);
 int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t n_leaves, const int8_t* level, const int32_t* ix,
                       const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
                       int ny0);
-/* Host-only: validate a leaf list like dgidp_mesh_upload (same errors, message
- * in msg) without a context or GPU; returns the number of mortars and of nodes
- * that lie on two mortars.  Output pointers may be NULL. */
+/* Host-only: validate a leaf list like dgidp_mesh_upload on a periodic domain
+ * (same errors, message in msg) without a context or GPU; returns the number
+ * of mortars and of nodes that lie on two mortars.  Output pointers may be
+ * NULL. */
 int dgidp_mesh_validate(int N, int64_t n_leaves, const int8_t* level, const int32_t* ix,
                         const int32_t* iy, int nx0, int ny0, int64_t* n_mortars,
                         int64_t* n_two_mortar_nodes, char* msg, int msglen);
+/* Boundary conditions of the domain sides, in the order x-, x+, y-, y+ (the
+ * double Mach reflection and the jet of Sec. 3.6 use slip walls and
+ * characteristic inflow/outflow).  bc[4]: DGIDP_BC_PERIODIC, DGIDP_BC_WALL
+ * (reflecting slip wall), DGIDP_BC_CHARACTERISTIC (inflow/outflow against an
+ * exterior state) or DGIDP_BC_OUTFLOW (the exterior state is the interior
+ * one); opposite sides are periodic together or not at all.  ext: host array
+ * [4][4], the conservative exterior state of each side (read for
+ * characteristic sides, which need it admissible; may be NULL if there are
+ * none).  A boundary node's surface flux, low-order flux, bar state and local
+ * bounds use the LLF flux against its ghost state: a wall mirrors the normal
+ * momentum; a characteristic node, by the outward normal velocity vn and the
+ * sound speed c of its interior state, takes the exterior state (vn <= -c),
+ * the exterior density and velocity with the interior pressure (-c < vn <= 0),
+ * the interior density and velocity with the exterior pressure (0 < vn < c),
+ * or the interior state (vn >= c).  Call before dgidp_mesh_upload; the
+ * setting holds for later uploads and adaptations of this context (default:
+ * periodic).  Mesh adaptation balances leaves as on a periodic domain, which
+ * can refine a few leaves more than needed next to a boundary.  Errors:
+ * DGIDP_E_INVALID_ARG (unknown condition, mixed periodicity, inadmissible
+ * exterior state, a mesh already uploaded). */
+int dgidp_set_boundaries(dgidp_ctx* ctx, const int* bc, const double* ext);
+/* Boundary nodes of the uploaded mesh: *n_nodes, and if nodes is not NULL the
+ * host array [n_nodes][3] of (element, face, node along the face), numbered by
+ * element (external order), then face, then node (in the direction of the
+ * face's coordinate).  Errors: DGIDP_E_NO_MESH. */
+int dgidp_boundary_nodes(dgidp_ctx* ctx, int64_t* n_nodes, int64_t* nodes);
+/* Per boundary node condition (DGIDP_BC_WALL, _CHARACTERISTIC or _OUTFLOW) and
+ * conservative exterior state, host arrays [n_nodes] and [n_nodes][4] in the
+ * numbering of dgidp_boundary_nodes; copied to the device after the stream's
+ * pending work.  A mesh upload or adaptation resets them to the side settings.
+ * Errors: DGIDP_E_NO_MESH, DGIDP_E_INVALID_ARG (unknown condition,
+ * inadmissible exterior state of a characteristic node; nothing is changed). */
+int dgidp_set_boundary_states(dgidp_ctx* ctx, const int8_t* kind, const double* ext);
 /* Number of elements and of mortars (nonconforming faces) of the mesh. */
 int dgidp_mesh_info(dgidp_ctx* ctx, int64_t* n_elements, int64_t* n_mortars);
 /* Physical node coordinates, host arrays [E][N+1][N+1] (external order). */

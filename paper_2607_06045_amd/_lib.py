@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
 LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED = 0, 1, 2, 3
 FLUX_RANOCHA, FLUX_CHANDRASHEKAR = 0, 1
+BC_PERIODIC, BC_WALL, BC_CHARACTERISTIC, BC_OUTFLOW = 0, 1, 2, 3
 RHS_HIGH, RHS_LOW = 0, 1
 IND_HENNEMANN, IND_MLP = 0, 1
 MLP_NPARAM = 5313
@@ -69,6 +70,9 @@ _SIGS = {
     "dgidp_synchronize": (_i, [_vp]),
     "dgidp_mesh_upload": (_i, [_vp, ctypes.c_int64, _vp, _vp, _vp, _d, _d, _d, _d, _i, _i]),
     "dgidp_mesh_info": (_i, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "dgidp_set_boundaries": (_i, [_vp, _vp, _vp]),
+    "dgidp_boundary_nodes": (_i, [_vp, ctypes.POINTER(ctypes.c_int64), _vp]),
+    "dgidp_set_boundary_states": (_i, [_vp, _vp, _vp]),
     "dgidp_node_coords": (_i, [_vp, _vp, _vp]),
     "dgidp_state_upload": (_i, [_vp, _vp, _i]),
     "dgidp_state_download": (_i, [_vp, _vp, _i]),
@@ -183,7 +187,8 @@ class Solver:
     """One dgidp context: a mesh, a state on the GPU and the stepping entry points."""
 
     def __init__(self, N=3, gamma=1.4, beta=0.1, precision=FP64, dt_mode=DT_IDP,
-                 limiter=LIMIT_POSITIVITY, strict_dt=False, stream=None, volume_flux=FLUX_RANOCHA):
+                 limiter=LIMIT_POSITIVITY, strict_dt=False, stream=None, volume_flux=FLUX_RANOCHA,
+                 bc=None, ext=None):
         if not torch.cuda.is_available():
             raise DgidpError("dgidp needs a ROCm GPU; none is visible")
         self.N, self.n = N, N + 1
@@ -196,7 +201,13 @@ class Solver:
         if rc:
             raise DgidpError(f"dgidp_create: {ERRORS.get(rc, rc)}")
         self._h = h
-        self.E = self.M = 0
+        self.E = self.M = self.NB = 0
+        if bc is not None:
+            b = np.ascontiguousarray(bc, dtype=np.int32)
+            x = None if ext is None else np.ascontiguousarray(ext, dtype=np.float64).reshape(4, 4)
+            self._check(_lib.dgidp_set_boundaries(self._h, b.ctypes.data,
+                                                  None if x is None else x.ctypes.data),
+                        "dgidp_set_boundaries")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -223,6 +234,25 @@ class Solver:
         self._check(_lib.dgidp_mesh_info(self._h, ctypes.byref(E), ctypes.byref(M)),
                     "dgidp_mesh_info")
         self.E, self.M = E.value, M.value
+        nb = ctypes.c_int64()
+        self._check(_lib.dgidp_boundary_nodes(self._h, ctypes.byref(nb), None), "dgidp_boundary_nodes")
+        self.NB = nb.value
+
+    def boundary_nodes(self):
+        """[NB, 3] (element, face, node along the face) of every boundary node."""
+        out = np.zeros((max(self.NB, 1), 3), dtype=np.int64)
+        nb = ctypes.c_int64()
+        self._check(_lib.dgidp_boundary_nodes(self._h, ctypes.byref(nb), out.ctypes.data),
+                    "dgidp_boundary_nodes")
+        return out[: nb.value]
+
+    def set_boundary_states(self, kind, ext):
+        kind = np.ascontiguousarray(kind, dtype=np.int8)
+        ext = np.ascontiguousarray(ext, dtype=np.float64)
+        if kind.shape != (self.NB,) or ext.shape != (self.NB, 4):
+            raise DgidpError("set_boundary_states: expected kind [NB] and ext [NB, 4]")
+        self._check(_lib.dgidp_set_boundary_states(self._h, kind.ctypes.data, ext.ctypes.data),
+                    "dgidp_set_boundary_states")
 
     def node_coords(self):
         sh = (self.E, self.n, self.n)

@@ -50,6 +50,11 @@ struct dgidp_ctx {
     float* ind_buf = nullptr;      // [E] indicator / [E*16] features staging
     size_t ind_cap = 0;
     bool has_state = false;
+    // domain sides (x-, x+, y-, y+): condition and exterior state
+    int bc[4] = {0, 0, 0, 0};
+    double bc_ext[16] = {};
+    int64_t NB = 0;  // boundary nodes of the mesh
+    std::vector<int> bface_elem;  // [NB / (N+1)] external element * 4 + face
 };
 
 namespace {
@@ -88,6 +93,8 @@ void free_mesh(dgidp_ctx* c)
     dfree(c->dm.fnbr);
     dfree(c->dm.fnbr2);
     dfree(c->dm.fmort);
+    dfree(c->dm.bkind);
+    dfree(c->dm.bext);
     dfree(c->dm.mort);
     dfree(c->dm.h);
     dfree(c->dm.slot_node);
@@ -100,6 +107,8 @@ void free_mesh(dgidp_ctx* c)
     dfree(c->W2);
     c->dm = DevMesh();
     c->E = c->M = 0;
+    c->NB = 0;
+    c->bface_elem.clear();
     c->has_state = false;
 }
 
@@ -151,8 +160,13 @@ int sync_stats(dgidp_ctx* ctx, dgidp_stats* s, int nstages)
     return 0;
 }
 
-// Connectivity of a periodic quadtree mesh, in internal (Morton) element order.
+// Connectivity of a quadtree mesh, in internal (Morton) element order.  A face
+// on a non-periodic domain side has the code -2 - (its boundary face index) and
+// the element itself as neighbour; boundary faces are numbered in external
+// element order, then by face, and own the nodes [index (N+1), (index+1) (N+1)).
 struct HostMesh {
+    int64_t NBF = 0;                // boundary faces
+    std::vector<int> bface_elem;    // [NBF] external element, face: e * 4 + f
     int M = 0;
     std::vector<int> perm;          // internal -> external
     std::vector<int> fnbr, fmort;   // [E*4]
@@ -162,7 +176,7 @@ struct HostMesh {
 };
 
 int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, const int32_t* iy,
-                    int nx0, int ny0, HostMesh& hm, std::string& err)
+                    int nx0, int ny0, const int* bc, HostMesh& hm, std::string& err)
 {
     if (N != 3 && N != 4) {
         err = "unsupported N";
@@ -207,6 +221,22 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         return DGIDP_E_MESH_GAP_OR_OVERLAP;
     }
     auto lookup = [&](int l, int64_t i, int64_t j) -> int { return (int)find.get_wrapped(l, i, j); };
+    // a face of leaf e on a non-periodic side of the domain
+    const bool open_x = bc && bc[0] != DGIDP_BC_PERIODIC, open_y = bc && bc[2] != DGIDP_BC_PERIODIC;
+    auto on_boundary = [&](int64_t e, int f) -> bool {
+        const int l = level[e];
+        if (f < 2) return open_x && (f == 0 ? ix[e] == 0 : ix[e] == ((int64_t)nx0 << l) - 1);
+        return open_y && (f == 2 ? iy[e] == 0 : iy[e] == ((int64_t)ny0 << l) - 1);
+    };
+    std::vector<int> bface((size_t)E * 4, -1);
+    hm.bface_elem.clear();
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f)
+            if (on_boundary(e, f)) {
+                bface[e * 4 + f] = (int)hm.bface_elem.size();
+                hm.bface_elem.push_back((int)(e * 4 + f));
+            }
+    hm.NBF = (int64_t)hm.bface_elem.size();
     // internal order: Morton order of the leaves on the finest grid, cut into
     // the eight contiguous ranges that the stage kernel hands to the eight
     // XCDs; inside each range the leaves with a nonconforming face come first.
@@ -230,7 +260,8 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
                 const int e = o.second;
                 for (int f = 0; f < 4; ++f) {
                     const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
-                    if (lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy) < 0) return true;
+                    if (bface[e * 4 + f] < 0 && lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy) < 0)
+                        return true;
                 }
                 return false;
             });
@@ -252,6 +283,11 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
     for (int64_t i = 0; i < E; ++i) {
         const int e = hm.perm[i], l = level[e];
         for (int f = 0; f < 4; ++f) {
+            if (bface[e * 4 + f] >= 0) {
+                hm.fnbr[i * 4 + f] = (int)i;
+                hm.fmort[i * 4 + f] = -2 - bface[e * 4 + f];
+                continue;
+            }
             const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
             const int64_t cx = ix[e] + dx, cy = iy[e] + dy;
             const int g = lookup(l, cx, cy);
@@ -452,8 +488,19 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     const int N = ctx->p.N, n = N + 1, NN = n * n;
     HostMesh hm;
     std::string err;
-    const int code = build_host_mesh(N, E, level, ix, iy, nx0, ny0, hm, err);
+    const int code = build_host_mesh(N, E, level, ix, iy, nx0, ny0, ctx->bc, hm, err);
     if (code) return fail(ctx, code, err);
+    // every boundary node starts with its side's condition and exterior state
+    const int64_t NB = hm.NBF * n;
+    std::vector<int8_t> bkind((size_t)NB);
+    std::vector<double> bext((size_t)NB * 4);
+    for (int64_t j = 0; j < hm.NBF; ++j) {
+        const int f = hm.bface_elem[j] & 3;
+        for (int k = 0; k < n; ++k) {
+            bkind[j * n + k] = (int8_t)ctx->bc[f];
+            for (int v = 0; v < 4; ++v) bext[(j * n + k) * 4 + v] = ctx->bc_ext[f * 4 + v];
+        }
+    }
     const int M = hm.M;
     std::vector<double> hh(E * 2);
     for (int64_t i = 0; i < E; ++i) {
@@ -479,8 +526,11 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
         (rc = upload(ctx, ctx->dm.fmort, hm.fmort)) ||
         (rc = upload(ctx, ctx->dm.mort, hm.mort)) || (rc = upload(ctx, ctx->dm.h, hh)) ||
         (rc = upload(ctx, ctx->dm.slot_node, hm.snode)) ||
-        (rc = upload(ctx, ctx->dm.slot_partner, hm.spart)) || (rc = upload(ctx, ctx->dm.perm, hm.perm)))
+        (rc = upload(ctx, ctx->dm.slot_partner, hm.spart)) || (rc = upload(ctx, ctx->dm.perm, hm.perm)) ||
+        (rc = upload(ctx, ctx->dm.bkind, bkind)) || (rc = upload(ctx, ctx->dm.bext, bext)))
         return rc;
+    ctx->NB = NB;
+    ctx->bface_elem = hm.bface_elem;
     const size_t sz = (size_t)E * 4 * NN * sizeof(double);
     HIPCHK(hipMalloc((void**)&ctx->dm.slot, std::max<size_t>(1, (size_t)M * 3 * n) * kSlotW * sizeof(double)));
     HIPCHK(hipMalloc((void**)&ctx->dm.shock_ind, std::max<size_t>(1, (size_t)E) * sizeof(double)));
@@ -498,7 +548,7 @@ int dgidp_mesh_validate(int N, int64_t n_leaves, const int8_t* level, const int3
 {
     HostMesh hm;
     std::string err;
-    const int code = build_host_mesh(N, n_leaves, level, ix, iy, nx0, ny0, hm, err);
+    const int code = build_host_mesh(N, n_leaves, level, ix, iy, nx0, ny0, nullptr, hm, err);
     if (msg && msglen > 0) {
         std::snprintf(msg, (size_t)msglen, "%s", err.c_str());
     }
@@ -509,6 +559,73 @@ int dgidp_mesh_validate(int N, int64_t n_leaves, const int8_t* level, const int3
         for (int p : hm.spart) c += p >= 0;
         *n_two_mortar_nodes = c / 2;
     }
+    return 0;
+}
+
+namespace {
+// an exterior state must be a finite admissible state (rho > 0, p > 0)
+bool admissible_state(const double* u, double gamma)
+{
+    for (int v = 0; v < 4; ++v)
+        if (!std::isfinite(u[v])) return false;
+    if (!(u[0] > 0.0)) return false;
+    return (gamma - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]) > 0.0;
+}
+}  // namespace
+
+int dgidp_set_boundaries(dgidp_ctx* ctx, const int* bc, const double* ext)
+{
+    if (!ctx || !bc) return DGIDP_E_INVALID_ARG;
+    if (ctx->E > 0) return fail(ctx, DGIDP_E_INVALID_ARG, "set the boundaries before uploading the mesh");
+    for (int f = 0; f < 4; ++f)
+        if (bc[f] < DGIDP_BC_PERIODIC || bc[f] > DGIDP_BC_OUTFLOW)
+            return fail(ctx, DGIDP_E_INVALID_ARG, "unknown boundary condition");
+    if ((bc[0] == DGIDP_BC_PERIODIC) != (bc[1] == DGIDP_BC_PERIODIC) ||
+        (bc[2] == DGIDP_BC_PERIODIC) != (bc[3] == DGIDP_BC_PERIODIC))
+        return fail(ctx, DGIDP_E_INVALID_ARG, "opposite sides must both be periodic or both not");
+    for (int f = 0; f < 4; ++f)
+        if (bc[f] == DGIDP_BC_CHARACTERISTIC && (!ext || !admissible_state(ext + 4 * f, ctx->p.gamma)))
+            return fail(ctx, DGIDP_E_INVALID_ARG, "a characteristic side needs an admissible exterior state");
+    for (int f = 0; f < 4; ++f) {
+        ctx->bc[f] = bc[f];
+        for (int v = 0; v < 4; ++v) ctx->bc_ext[f * 4 + v] = ext ? ext[f * 4 + v] : 0.0;
+    }
+    return 0;
+}
+
+int dgidp_boundary_nodes(dgidp_ctx* ctx, int64_t* n_nodes, int64_t* nodes)
+{
+    if (!ctx || !n_nodes) return DGIDP_E_INVALID_ARG;
+    if (ctx->E == 0) return fail(ctx, DGIDP_E_NO_MESH, "no mesh");
+    *n_nodes = ctx->NB;
+    if (nodes) {
+        const int n = ctx->p.N + 1;
+        for (size_t j = 0; j < ctx->bface_elem.size(); ++j)
+            for (int k = 0; k < n; ++k) {
+                nodes[(j * n + k) * 3 + 0] = ctx->bface_elem[j] >> 2;
+                nodes[(j * n + k) * 3 + 1] = ctx->bface_elem[j] & 3;
+                nodes[(j * n + k) * 3 + 2] = k;
+            }
+    }
+    return 0;
+}
+
+int dgidp_set_boundary_states(dgidp_ctx* ctx, const int8_t* kind, const double* ext)
+{
+    if (!ctx || !kind || !ext) return DGIDP_E_INVALID_ARG;
+    if (ctx->E == 0) return fail(ctx, DGIDP_E_NO_MESH, "no mesh");
+    for (int64_t j = 0; j < ctx->NB; ++j) {
+        if (kind[j] < DGIDP_BC_WALL || kind[j] > DGIDP_BC_OUTFLOW)
+            return fail(ctx, DGIDP_E_INVALID_ARG, "boundary node " + std::to_string(j) + ": unknown condition");
+        if (kind[j] == DGIDP_BC_CHARACTERISTIC && !admissible_state(ext + 4 * j, ctx->p.gamma))
+            return fail(ctx, DGIDP_E_INVALID_ARG,
+                        "boundary node " + std::to_string(j) + ": exterior state not admissible");
+    }
+    if (ctx->NB == 0) return 0;
+    // the stream may still read the previous states
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(ctx->dm.bkind, kind, (size_t)ctx->NB, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->dm.bext, ext, (size_t)ctx->NB * 4 * sizeof(double), hipMemcpyHostToDevice));
     return 0;
 }
 

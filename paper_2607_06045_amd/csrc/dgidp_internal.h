@@ -62,6 +62,8 @@ struct DevMesh {
     double* slot = nullptr;     // [M*3n*kSlotW]
     int* perm = nullptr;        // [E] external index of internal element e
     double* shock_ind = nullptr;  // [E] shock indicator of combined limiting (internal order)
+    int8_t* bkind = nullptr;    // [NB] condition of each boundary node (external numbering)
+    double* bext = nullptr;     // [NB*4] exterior state of each boundary node
 };
 
 struct KernelParams {

@@ -135,6 +135,43 @@ __device__ __forceinline__ void make_node(NodeP& s, double g)
     s.c = sqrt(g * s.p * ir);
 }
 
+// Ghost state across a boundary face f (0 x-, 1 x+, 2 y-, 3 y+) of the interior
+// node s; the outward normal is the axis f / 2, negative on even faces.  Wall:
+// the normal momentum reversed.  Characteristic, by the outward normal velocity
+// vn and sound speed c of s: the exterior state x if vn <= -c; x's density and
+// velocity with s's pressure if vn <= 0; s's density and velocity with x's
+// pressure if vn < c; else s.  Outflow: s.
+__device__ __forceinline__ void boundary_ghost(int kind, const double* x, const NodeP& s, int f,
+                                               double g, double* gu)
+{
+    const int d = f >> 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gu[v] = s.u[v];
+    if (kind == DGIDP_BC_WALL) {  // (constant indices keep gu in registers)
+        if (d == 0) gu[1] = -s.u[1];
+        else gu[2] = -s.u[2];
+        return;
+    }
+    if (kind != DGIDP_BC_CHARACTERISTIC) return;
+    const double vn = (f & 1) ? (d == 0 ? s.v1 : s.v2) : -(d == 0 ? s.v1 : s.v2);
+    if (vn >= s.c) return;
+    if (vn <= -s.c) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gu[v] = x[v];
+        return;
+    }
+    const double ixr = 1.0 / x[0], xv1 = x[1] * ixr, xv2 = x[2] * ixr;
+    if (vn <= 0.0) {
+        gu[0] = x[0];
+        gu[1] = x[0] * xv1;
+        gu[2] = x[0] * xv2;
+        gu[3] = s.p / (g - 1.0) + 0.5 * x[0] * (xv1 * xv1 + xv2 * xv2);
+    } else {
+        const double xp = (g - 1.0) * (x[3] - 0.5 * (x[1] * xv1 + x[2] * xv2));
+        gu[3] = xp / (g - 1.0) + 0.5 * s.r * (s.v1 * s.v1 + s.v2 * s.v2);
+    }
+}
+
 __device__ __forceinline__ double pressure(const double* u, double g)
 {
     return (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) * frcp(u[0]));
@@ -534,6 +571,8 @@ struct StageArgs {
     const int* mort;
     const double* h;
     double* slot;
+    const int8_t* bkind;  // boundary nodes: condition and exterior state
+    const double* bext;
     int E;
     double gamma, beta;
     int limiter;
@@ -627,8 +666,8 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     int fcode[4] = {-1, -1, -1, -1};
     const bool fnode = act && q < NFN;       // this lane also evaluates one face node
     const int ff = q / n, fk = q - (q / n) * n;  // its face and position
-    int fcode_f = -1, fnb = 0, fnb2 = -1;
-    double onb[4];  // conforming neighbour state across face ff at position fk
+    int fcode_f = -1, fnb = 0, fnb2 = -1, bk = 0;
+    double onb[4];  // conforming neighbour state (boundary: exterior state) across face ff at fk
     double us1[4];  // large side: the second small element's trace at position fk
     double un4[4] = {0, 0, 0, 0};  // u^n of this node for the SSP combination
     double u0[4] = {0, 0, 0, 0};   // this node's state (uin)
@@ -696,8 +735,13 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         if (need_loc) ls_own = MIXED ? log(me.p) - g * log(me.r) : (1.0 - g) * lr - lz;
         if (fnode) {
             fcode_f = fcode[ff];
-            if (fcode_f < 0) {
+            if (fcode_f == -1) {
                 load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
+            } else if (fcode_f < -1) {
+                const int j = (-2 - fcode_f) * n + fk;
+                bk = A.bkind[j];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) onb[v] = A.bext[(size_t)j * 4 + v];
             } else if (!fm_small(fcode_f)) {
                 // large side: both small traces at position fk, kept in
                 // registers for the mortar-node fluxes and staged for the
@@ -743,8 +787,12 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         LDS_NODE(own, face_q<N>(ff, fk));
         if (fcode_f < 0) {
             NodeP o;
+            if (fcode_f == -1) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) o.u[v] = onb[v];
+                for (int v = 0; v < 4; ++v) o.u[v] = onb[v];
+            } else {
+                boundary_ghost(bk, onb, own, ff, g, o.u);
+            }
             make_node(o, g);
             double F[4];
             llf_face(dff, lowf, own, o, F);
@@ -1391,6 +1439,8 @@ struct DtArgs {
     const int* fmort;
     const int* mort;
     const double* h;
+    const int8_t* bkind;
+    const double* bext;
     int E;
     double gamma;
     int mode;
@@ -1446,7 +1496,18 @@ __global__ __launch_bounds__(256) void k_dt(DtArgs A)
         sL[le][1][q] = wave_speed(me, 1);
         if (fnode) {
             NodeP o;
-            load_node<N>(A.u, nb, face_q<N>(ff ^ 1, fk), o, g);
+            if (code >= -1) {
+                load_node<N>(A.u, nb, face_q<N>(ff ^ 1, fk), o, g);
+            } else {  // boundary: the ghost state of the face node
+                const int j = (-2 - code) * n + fk;
+                double x[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) x[v] = A.bext[(size_t)j * 4 + v];
+                NodeP s;
+                load_node<N>(A.u, e, face_q<N>(ff, fk), s, g);
+                boundary_ghost(A.bkind[j], x, s, ff, g, o.u);
+                make_node(o, g);
+            }
             lo_nb = wave_speed(o, dff);
             if (code >= 0) {
                 // mortar: stage the wave speeds of the other side at position fk
@@ -1915,6 +1976,8 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.fnbr = m.fnbr;
     A.fnbr2 = m.fnbr2;
     A.fmort = m.fmort;
+    A.bkind = m.bkind;
+    A.bext = m.bext;
     A.mort = m.mort;
     A.h = m.h;
     A.slot = m.slot;
@@ -1995,6 +2058,8 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
     A.fnbr = m.fnbr;
     A.fnbr2 = m.fnbr2;
     A.fmort = m.fmort;
+    A.bkind = m.bkind;
+    A.bext = m.bext;
     A.mort = m.mort;
     A.h = m.h;
     A.E = m.E;
