@@ -20,7 +20,7 @@ _lib = None
 
 RHS_HIGH, RHS_LOW = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
-LIM_NONE, LIM_POSITIVITY, LIM_LOCAL, LIM_COMBINED = 0, 1, 2, 3
+LIM_NONE, LIM_POSITIVITY, LIM_LOCAL, LIM_COMBINED, LIM_LOCAL_LO = 0, 1, 2, 3, 4
 BC_PERIODIC, BC_WALL, BC_CHARACTERISTIC, BC_OUTFLOW = 0, 1, 2, 3
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -92,6 +92,7 @@ def lib():
         L.orc_theta_entropy.restype = ctypes.c_double
         L.orc_theta_entropy.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_local_bounds.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D, _D, _D]
+        L.orc_lowsol_bounds.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D, _D, _D]
         L.orc_shock_indicator.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D]
         L.orc_fe_step_ind.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, _D, _D, _D]
@@ -324,6 +325,16 @@ class Mesh:
         sh = (self.E, self.n, self.n)
         lo, hi, sm = np.zeros(sh), np.zeros(sh), np.zeros(sh)
         lib().orc_local_bounds(self._h, _ptr(u), gamma, _ptr(lo), _ptr(hi), _ptr(sm))
+        return lo, hi, sm
+
+    def lowsol_bounds(self, ufv, gamma=1.4):
+        """(rho_min, rho_max, s_min), each [E, n, n], over the low-order states
+        ufv of every node and its low-order neighbours (eq. Bounds_LowOrder; s_min
+        over those with positive density and pressure)."""
+        ufv = np.ascontiguousarray(ufv, dtype=np.float64)
+        sh = (self.E, self.n, self.n)
+        lo, hi, sm = np.zeros(sh), np.zeros(sh), np.zeros(sh)
+        lib().orc_lowsol_bounds(self._h, _ptr(ufv), gamma, _ptr(lo), _ptr(hi), _ptr(sm))
         return lo, hi, sm
 
     def shock_indicator(self, u, gamma=1.4):

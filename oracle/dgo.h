@@ -115,7 +115,9 @@ typedef struct {
 
 enum { RHS_HIGH = 0, RHS_LOW = 1 };
 enum { DT_IDP = 0, DT_LOWORDER = 1 };
-enum { LIM_NONE = 0, LIM_POSITIVITY = 1, LIM_LOCAL = 2, LIM_COMBINED = 3 };
+/* LIM_LOCAL: bounds from bar states (eq. Bounds_Barstates); LIM_LOCAL_LO: from
+   the low-order solution (eq. Bounds_LowOrder) */
+enum { LIM_NONE = 0, LIM_POSITIVITY = 1, LIM_LOCAL = 2, LIM_COMBINED = 3, LIM_LOCAL_LO = 4 };
 
 int dgo_rhs(const dgo_mesh* m, const double* u, int which, double gamma, double* du);
 double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, double gamma);
@@ -130,6 +132,9 @@ double dgo_spec_entropy(const double* u, double gamma);
 void dgo_local_bounds(const dgo_mesh* m, const double* u, double gamma, double* rlo, double* rhi,
                       double* smin);
 double dgo_theta_entropy(const double* u0, const double* dc, double st, double gamma, double thi);
+/* local bounds from the low-order solution ufv (eq. Bounds_LowOrder) */
+void dgo_lowsol_bounds(const dgo_mesh* m, const double* ufv, double gamma, double* rlo, double* rhi,
+                       double* smin);
 /* combined limiting (eq. combination_posLim_local): per-element shock
    indicator on the pressure in [0, 1]; a FE step with the indicator given
    (NULL: computed from u) */

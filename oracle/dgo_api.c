@@ -259,6 +259,12 @@ void orc_local_bounds(void* h, const double* u, double gamma, double* rlo, doubl
     dgo_local_bounds((dgo_mesh*)h, u, gamma, rlo, rhi, smin);
 }
 
+void orc_lowsol_bounds(void* h, const double* ufv, double gamma, double* rlo, double* rhi,
+                       double* smin)
+{
+    dgo_lowsol_bounds((dgo_mesh*)h, ufv, gamma, rlo, rhi, smin);
+}
+
 void orc_shock_indicator(void* h, const double* u, double gamma, double* ind)
 {
     dgo_shock_indicator((dgo_mesh*)h, u, gamma, ind);

@@ -552,6 +552,78 @@ void dgo_local_bounds(const dgo_mesh* m, const double* u, double gamma, double* 
             }
 }
 
+/* Local bounds from the low-order solution (eq. Bounds_LowOrder): per node i
+   the density range over the low-order states u^FV_j of j in {i} and N(i) (the
+   same neighbours as for the bar states: subcell neighbours, the matching node
+   across a conforming face, the nodes with a nonzero sparse weight across a
+   mortar; a boundary face adds none), and the smallest specific entropy
+   p rho^-gamma among those of them with positive density and pressure. */
+static void lo_add(const double* q, double gamma, double* lo, double* hi, double* sm)
+{
+    if (q[0] < *lo) *lo = q[0];
+    if (q[0] > *hi) *hi = q[0];
+    if (q[0] > 0.0 && dgo_pressure(q, gamma) > 0.0) {
+        double s = dgo_spec_entropy(q, gamma);
+        if (s < *sm) *sm = s;
+    }
+}
+
+void dgo_lowsol_bounds(const dgo_mesh* m, const double* ufv, double gamma, double* rlo, double* rhi,
+                       double* smin)
+{
+    const dgo_basis* B = &m->B;
+    int N = B->N, n = B->n;
+    int64_t nn = n * n;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < m->E; ++e)
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                double q[4];
+                double lo = INFINITY, hi = -INFINITY, sm = INFINITY;
+                get_node(ufv, n, e, a, b, q);
+                lo_add(q, gamma, &lo, &hi, &sm);
+                if (a > 0) { get_node(ufv, n, e, a - 1, b, q); lo_add(q, gamma, &lo, &hi, &sm); }
+                if (a < N) { get_node(ufv, n, e, a + 1, b, q); lo_add(q, gamma, &lo, &hi, &sm); }
+                if (b > 0) { get_node(ufv, n, e, a, b - 1, q); lo_add(q, gamma, &lo, &hi, &sm); }
+                if (b < N) { get_node(ufv, n, e, a, b + 1, q); lo_add(q, gamma, &lo, &hi, &sm); }
+                for (int f = 0; f < 4; ++f) {
+                    int k = -1;
+                    if (f == 0 && a == 0) k = b;
+                    if (f == 1 && a == N) k = b;
+                    if (f == 2 && b == 0) k = a;
+                    if (f == 3 && b == N) k = a;
+                    if (k < 0) continue;
+                    const dgo_face* F = &m->face[e * 4 + f];
+                    int a2, b2;
+                    if (F->type == FACE_CONF) {
+                        face_node(f ^ 1, k, N, &a2, &b2);
+                        get_node(ufv, n, F->nbr, a2, b2, q);
+                        lo_add(q, gamma, &lo, &hi, &sm);
+                    } else if (F->type == FACE_LARGE) {
+                        const dgo_mortar* M = &m->mort[F->mortar];
+                        for (int h = 0; h < 2; ++h)
+                            for (int l = 0; l < n; ++l) {
+                                if (B->Wt[k][h * n + l] == 0.0) continue;
+                                face_node(f ^ 1, l, N, &a2, &b2);
+                                get_node(ufv, n, M->small[h], a2, b2, q);
+                                lo_add(q, gamma, &lo, &hi, &sm);
+                            }
+                    } else if (F->type == FACE_SMALL) {
+                        const dgo_mortar* M = &m->mort[F->mortar];
+                        for (int kk = 0; kk < n; ++kk) {
+                            if (B->Wt[kk][F->half * n + k] == 0.0) continue;
+                            face_node(M->face, kk, N, &a2, &b2);
+                            get_node(ufv, n, M->large, a2, b2, q);
+                            lo_add(q, gamma, &lo, &hi, &sm);
+                        }
+                    }
+                }
+                rlo[e * nn + b * n + a] = lo;
+                rhi[e * nn + b * n + a] = hi;
+                smin[e * nn + b * n + a] = sm;
+            }
+}
+
 /* psi(theta) = p(u0 + theta dc) - st rho(u0 + theta dc)^gamma and its derivative.
    psi >= 0 with rho > 0 is s >= st; psi is concave along the ray (p is concave
    in the conserved variables and rho^gamma convex). */
@@ -805,13 +877,32 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
     /* local: local bounds enforced; comb: positivity and local factors both
        computed and blended per element with the shock indicator */
     const int comb = limiter == LIM_COMBINED;
-    const int local = limiter == LIM_LOCAL || comb;
+    const int pure_local = limiter == LIM_LOCAL || limiter == LIM_LOCAL_LO;
+    const int local = pure_local || comb;
     double *rlo = 0, *rhi = 0, *smin = 0, *ind = 0;
     if (local) {
         rlo = (double*)malloc(sizeof(double) * E * nn);
         rhi = (double*)malloc(sizeof(double) * E * nn);
         smin = (double*)malloc(sizeof(double) * E * nn);
-        dgo_local_bounds(m, u, gamma, rlo, rhi, smin);
+        if (limiter == LIM_LOCAL_LO) {
+            /* the low-order solution first (the same arithmetic as below), then
+               its bounds */
+#pragma omp parallel for schedule(static)
+            for (int64_t e = 0; e < E; ++e) {
+                double R[4 * DGO_NMAX * DGO_NMAX];
+                memset(R, 0, sizeof(R));
+                volume_low(m, u, gamma, e, R);
+                add_surface(m, u, gamma, LO, e, R);
+                for (int v = 0; v < 4; ++v)
+                    for (int b = 0; b < n; ++b)
+                        for (int a = 0; a < n; ++a)
+                            uFV[IDX(e, v, b, a)] =
+                                u[IDX(e, v, b, a)] + dt / mass(m, e, a, b) * R[(v * n + b) * n + a];
+            }
+            dgo_lowsol_bounds(m, uFV, gamma, rlo, rhi, smin);
+        } else {
+            dgo_local_bounds(m, u, gamma, rlo, rhi, smin);
+        }
     }
     if (comb) {
         ind = (double*)malloc(sizeof(double) * (E > 0 ? E : 1));
@@ -889,7 +980,7 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
                 if (b > 0) { for (int v = 0; v < 4; ++v) cf[nf][v] = dt / mi * Ay[a][b - 1][v]; nf++; }
                 if (b < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ay[a][b][v]; nf++; }
                 int64_t i = e * nn + b * n + a;
-                if (limiter == LIM_LOCAL) {
+                if (pure_local) {
                     th[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
                 } else {
                     th[b][a] = volume_node_factor(q, cf, nf, rmin[i], pmin[i], 0, 0.0, 0.0, gamma);
@@ -978,7 +1069,7 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
                 }
                 /* this node's factor, then the minimum over the mortar's nodes */
                 int64_t i = e * nn + b * n + a;
-                double tn = limiter == LIM_LOCAL
+                double tn = pure_local
                                 ? mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma)
                                 : mortar_node_factor(q, dc, rmin[i], pmin[i], 0, 0.0, 0.0, gamma);
                 if (tn < t) t = tn;
@@ -1047,7 +1138,7 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
                 get_node(out, n, e, a, b, q);
                 int64_t i = e * nn + b * n + a;
                 /* combined limiting guarantees the positivity bounds only */
-                if (limiter != LIM_LOCAL) {
+                if (!pure_local) {
                     if (q[0] < rmin[i] || dgo_pressure(q, gamma) < pmin[i] || q[0] != q[0]) viol++;
                 } else if (!(q[0] >= rlo[i] * (1.0 - LOCAL_TOL)) || q[0] > rhi[i] * (1.0 + LOCAL_TOL) ||
                            dgo_pressure(q, gamma) < pmin[i] ||

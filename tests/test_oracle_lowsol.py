@@ -1,0 +1,144 @@
+"""Pins of the oracle's local bounds from the low-order solution (Sec. 3.4,
+eq. Bounds_LowOrder).
+
+- Brute force: the bounds of every node equal the min/max over the node and
+  its low-order neighbours found from geometry alone: the subcell neighbours
+  inside the element, and across a face every node of the touching element
+  whose subcell interval along the face overlaps the node's own with positive
+  length (the matching node on a conforming face; the sparse-weight partners on
+  a mortar, App. A).  Specific entropy only from states with positive density
+  and pressure.
+- A limited step keeps the bounds and conserves; a uniform state is kept; the
+  bounds are those of the step's own low-order solution u + dt R_LO / m."""
+import numpy as np
+import pytest
+
+from workloads import states
+from workloads.meshes import random_mesh
+
+G = 1.4
+
+
+def _brute_bounds(M, ufv, w):
+    N, n = M.N, M.n
+    x, y, _ = M.geometry()
+    x0, y0, Lx, Ly, nx0, ny0 = M.box
+    edges = np.concatenate([[0.0], np.cumsum(w) / 2.0])  # subcell edges on [0, 1]
+    lo = np.full((M.E, n, n), np.inf)
+    hi = np.full((M.E, n, n), -np.inf)
+    sm = np.full((M.E, n, n), np.inf)
+    rho = ufv[:, 0]
+    p = (G - 1) * (ufv[:, 3] - 0.5 * (ufv[:, 1] ** 2 + ufv[:, 2] ** 2) / ufv[:, 0])
+    with np.errstate(all="ignore"):
+        s = np.where((rho > 0) & (p > 0), p * np.abs(rho) ** (-G), np.inf)
+
+    def add(e, b, a, g, bb, aa):
+        lo[e, b, a] = min(lo[e, b, a], rho[g, bb, aa])
+        hi[e, b, a] = max(hi[e, b, a], rho[g, bb, aa])
+        sm[e, b, a] = min(sm[e, b, a], s[g, bb, aa])
+
+    ext = np.stack([x.min(axis=(1, 2)), x.max(axis=(1, 2)), y.min(axis=(1, 2)), y.max(axis=(1, 2))], 1)
+
+    def face_nodes(e, f):
+        """(b, a) of the nodes of face f and their subcell intervals along it."""
+        lo_, hi_ = (ext[e, 2], ext[e, 3]) if f < 2 else (ext[e, 0], ext[e, 1])
+        out = []
+        for k in range(n):
+            b, a = (k, 0 if f == 0 else N) if f < 2 else (0 if f == 2 else N, k)
+            out.append((b, a, lo_ + (hi_ - lo_) * edges[k], lo_ + (hi_ - lo_) * edges[k + 1]))
+        return out
+
+    def same(u, v, L):
+        d = (u - v) % L
+        return min(d, L - d) < 1e-12
+
+    for e in range(M.E):
+        for b in range(n):
+            for a in range(n):
+                add(e, b, a, e, b, a)
+                for bb, aa in ((b, a - 1), (b, a + 1), (b - 1, a), (b + 1, a)):
+                    if 0 <= bb < n and 0 <= aa < n:
+                        add(e, b, a, e, bb, aa)
+        for f in range(4):
+            pos = ext[e, 1] if f == 1 else ext[e, 0] if f == 0 else ext[e, 3] if f == 3 else ext[e, 2]
+            Lp, Lt = (Lx, Ly) if f < 2 else (Ly, Lx)
+            mine = face_nodes(e, f)
+            for g in range(M.E):
+                if g == e and not (Lp == (ext[e, 1] - ext[e, 0] if f < 2 else ext[e, 3] - ext[e, 2])):
+                    continue
+                gpos = [ext[g, 0], ext[g, 1], ext[g, 2], ext[g, 3]][f ^ 1]
+                if not same(pos, gpos, Lp):
+                    continue
+                for (b, a, s0, s1) in mine:
+                    for (bb, aa, t0, t1) in face_nodes(g, f ^ 1):
+                        # overlap of [s0, s1] and [t0, t1] on the periodic line
+                        for shift in (-Lt, 0.0, Lt):
+                            if min(s1, t1 + shift) - max(s0, t0 + shift) > 1e-12:
+                                add(e, b, a, g, bb, aa)
+    return lo, hi, sm
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_lowsol_bounds_brute_force(oracle, N):
+    spec = random_mesh(5, 3, 2, 0.45)
+    M = oracle.Mesh(N, *spec.args())
+    assert M.M > 0
+    x, y, m = M.geometry()
+    ufv = states.random_admissible(x, 21)
+    # element 3 with negative pressure: no entropy bound from its nodes
+    ufv[3, 3] = 0.25 * (ufv[3, 1] ** 2 + ufv[3, 2] ** 2) / ufv[3, 0]
+    lo, hi, sm = M.lowsol_bounds(ufv)
+    w = oracle.basis(N)[1]
+    blo, bhi, bsm = _brute_bounds(M, ufv, w)
+    assert np.array_equal(lo, blo) and np.array_equal(hi, bhi)
+    assert np.allclose(sm, bsm, rtol=1e-14, atol=0)
+    assert np.isinf(bsm).sum() == np.isinf(sm).sum()
+
+
+def test_lowsol_bounds_walls_add_nothing(oracle):
+    """Across a wall the node has no low-order neighbour: the bounds of a node on
+    the wall are those of the periodic mesh without the wrapped partner."""
+    spec = random_mesh(5, 3, 2, 0.45)
+    P = oracle.Mesh(3, *spec.args())
+    W = oracle.Mesh(3, *spec.args(), bc=[1, 1, 1, 1])
+    x, y, m = P.geometry()
+    ufv = states.random_admissible(x, 22)
+    w = oracle.basis(3)[1]
+    lo, hi, sm = W.lowsol_bounds(ufv)
+    blo, bhi, bsm = _brute_bounds(P, ufv, w)
+    inner = (x.min(axis=(1, 2)) > 1e-12) & (x.max(axis=(1, 2)) < 1 - 1e-12) & \
+            (y.min(axis=(1, 2)) > 1e-12) & (y.max(axis=(1, 2)) < 1 - 1e-12)
+    assert np.array_equal(lo[inner], blo[inner])
+    # on the walls the range is narrower or equal
+    assert np.all(lo >= blo) and np.all(hi <= bhi) and np.all(sm >= bsm * (1 - 1e-14))
+    assert np.any(lo > blo)
+
+
+def test_lowsol_step(oracle):
+    """A limited forward-Euler step with bounds from the low-order solution: the
+    bounds are the low-order solution's own (u + dt R_LO / m); the result lies
+    inside them; mass, momentum and energy are conserved; the factors act on a
+    blast; a uniform state is kept."""
+    spec = random_mesh(10, 8, 2, 0.45, L=4.0, x0=-2.0, y0=-2.0)
+    M = oracle.Mesh(3, *spec.args())
+    x, y, m = M.geometry()
+    u = states.sedov_tophat(x, y, r0=0.5)
+    dt = M.max_dt(u, 0.4, mode=oracle.DT_LOWORDER)
+    out, st = M.fe_step(u, dt, limiter=oracle.LIM_LOCAL_LO)
+    assert st["violations"] == 0 and st["fv_inadmissible"] == 0
+    ufv = u + dt * M.rhs(u, oracle.RHS_LOW)
+    lo, hi, sm = M.lowsol_bounds(ufv)
+    rho = out[:, 0]
+    p = (G - 1) * (out[:, 3] - 0.5 * (out[:, 1] ** 2 + out[:, 2] ** 2) / out[:, 0])
+    assert np.all(rho >= lo * (1 - 1e-11)) and np.all(rho <= hi * (1 + 1e-11))
+    assert np.all(p * rho ** (-G) >= sm * (1 - 1e-11))
+    tot0, tot = (u * m[:, None]).sum(axis=(0, 2, 3)), (out * m[:, None]).sum(axis=(0, 2, 3))
+    scale = (np.abs(out) * m[:, None]).sum(axis=(0, 2, 3))  # momentum starts at zero
+    assert np.all(np.abs(tot - tot0) < 1e-13 * scale)
+    assert st["theta_vol_min"] < 0.5 and st["alpha_vol_mean"] > 0
+    # differs from the bar-state bounds
+    bar, sb = M.fe_step(u, dt, limiter=oracle.LIM_LOCAL)
+    assert np.abs(bar - out).max() > 1e-6
+    uc = states.constant(x, rho=0.8, v1=0.4, v2=-0.3, p=1.2)
+    oc, _ = M.fe_step(uc, M.max_dt(uc, 0.4, mode=oracle.DT_LOWORDER), limiter=oracle.LIM_LOCAL_LO)
+    assert np.abs(oc - uc).max() < 1e-13
