@@ -43,7 +43,13 @@ enum {
 
 enum { DGIDP_FP64 = 0, DGIDP_MIXED = 1 };           /* precision of the high-order fluxes */
 enum { DGIDP_DT_IDP = 0, DGIDP_DT_LOWORDER = 1 };   /* time-step rule */
-enum { DGIDP_LIMIT_NONE = 0, DGIDP_LIMIT_POSITIVITY = 1, DGIDP_LIMIT_LOCAL = 2, DGIDP_LIMIT_COMBINED = 3 };
+enum {
+    DGIDP_LIMIT_NONE = 0,
+    DGIDP_LIMIT_POSITIVITY = 1,
+    DGIDP_LIMIT_LOCAL = 2,
+    DGIDP_LIMIT_COMBINED = 3,
+    DGIDP_LIMIT_LOCAL_LOWORDER = 4
+};
 enum { DGIDP_RHS_HIGH = 0, DGIDP_RHS_LOW = 1 };
 enum { DGIDP_FLUX_RANOCHA = 0, DGIDP_FLUX_CHANDRASHEKAR = 1 };  /* two-point volume flux */
 /* boundary condition of a domain side or boundary node */
@@ -74,7 +80,14 @@ typedef struct dgidp_ctx dgidp_ctx;
  *             the element's Hennemann indicator on the pressure in [0, 1],
  *             computed from each stage's input; per mortar w is the largest
  *             indicator of its three elements; only the positivity bounds
- *             are guaranteed)
+ *             are guaranteed), or DGIDP_LIMIT_LOCAL_LOWORDER (Sec. 3.4,
+ *             eq. Bounds_LowOrder: as DGIDP_LIMIT_LOCAL, with the bounds
+ *             taken over the low-order solution u + dt R_LO / m of the node
+ *             and its low-order neighbours instead of the bar states; no
+ *             neighbour across a boundary; the entropy bound only from
+ *             low-order states with positive density and pressure; meant
+ *             for the low-order CFL rule, under which it is not provably
+ *             bound-preserving)
  *  strict_dt  if nonzero, dgidp_limit() rejects a dt above the IDP bound
  *  volume_flux  two-point flux of the volume flux differencing:
  *             DGIDP_FLUX_RANOCHA (Ranocha's entropy-conserving, kinetic-energy-

@@ -19,7 +19,7 @@ if not os.path.exists(LIB_PATH):
 
 FP64, MIXED = 0, 1
 DT_IDP, DT_LOWORDER = 0, 1
-LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED = 0, 1, 2, 3
+LIMIT_NONE, LIMIT_POSITIVITY, LIMIT_LOCAL, LIMIT_COMBINED, LIMIT_LOCAL_LOWORDER = 0, 1, 2, 3, 4
 FLUX_RANOCHA, FLUX_CHANDRASHEKAR = 0, 1
 BC_PERIODIC, BC_WALL, BC_CHARACTERISTIC, BC_OUTFLOW = 0, 1, 2, 3
 RHS_HIGH, RHS_LOW = 0, 1

@@ -95,6 +95,8 @@ void free_mesh(dgidp_ctx* c)
     dfree(c->dm.fmort);
     dfree(c->dm.bkind);
     dfree(c->dm.bext);
+    dfree(c->dm.dlo);
+    dfree(c->dm.lob);
     dfree(c->dm.mort);
     dfree(c->dm.h);
     dfree(c->dm.slot_node);
@@ -402,6 +404,11 @@ int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, dou
     if (kp.limiter == DGIDP_LIMIT_COMBINED &&
         launch_shock_indicator(ctx->p.N, ctx->dm, uin, kp.gamma, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
+    // bounds from the low-order solution: R_LO / m of the input, then the bounds
+    if (kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
+        (launch_rhs(ctx->p.N, ctx->dm, kp, uin, DGIDP_RHS_LOW, ctx->dm.dlo, ctx->stream) ||
+         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, uin, ctx->dm.dlo, dt, ctx->dm.lob, ctx->stream)))
+        return fail(ctx, DGIDP_E_DEVICE, "low-order bounds launch failed");
     if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
     if (launch_mortar(ctx->p.N, ctx->dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
@@ -424,7 +431,8 @@ int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
         (p->precision != DGIDP_FP64 && p->precision != DGIDP_MIXED) ||
         (p->dt_mode != DGIDP_DT_IDP && p->dt_mode != DGIDP_DT_LOWORDER) ||
         (p->limiter != DGIDP_LIMIT_NONE && p->limiter != DGIDP_LIMIT_POSITIVITY &&
-         p->limiter != DGIDP_LIMIT_LOCAL && p->limiter != DGIDP_LIMIT_COMBINED) ||
+         p->limiter != DGIDP_LIMIT_LOCAL && p->limiter != DGIDP_LIMIT_COMBINED &&
+         p->limiter != DGIDP_LIMIT_LOCAL_LOWORDER) ||
         (p->volume_flux != DGIDP_FLUX_RANOCHA && p->volume_flux != DGIDP_FLUX_CHANDRASHEKAR))
         return DGIDP_E_INVALID_ARG;
     dgidp_ctx* ctx = new dgidp_ctx();
@@ -534,6 +542,10 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     const size_t sz = (size_t)E * 4 * NN * sizeof(double);
     HIPCHK(hipMalloc((void**)&ctx->dm.slot, std::max<size_t>(1, (size_t)M * 3 * n) * kSlotW * sizeof(double)));
     HIPCHK(hipMalloc((void**)&ctx->dm.shock_ind, std::max<size_t>(1, (size_t)E) * sizeof(double)));
+    if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER) {
+        HIPCHK(hipMalloc((void**)&ctx->dm.dlo, sz));
+        HIPCHK(hipMalloc((void**)&ctx->dm.lob, (size_t)E * 3 * NN * sizeof(double)));
+    }
     HIPCHK(hipMalloc((void**)&ctx->U, sz));
     HIPCHK(hipMalloc((void**)&ctx->W1, sz));
     HIPCHK(hipMalloc((void**)&ctx->W2, sz));
@@ -912,6 +924,12 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     if (kp.limiter == DGIDP_LIMIT_COMBINED &&
         launch_shock_indicator(ctx->p.N, ctx->dm, ctx->U, kp.gamma, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
+    // (the low-order-solution bounds are formed once, outside the timed stages)
+    if (kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
+        (launch_rhs(ctx->p.N, ctx->dm, kp, ctx->U, DGIDP_RHS_LOW, ctx->dm.dlo, ctx->stream) ||
+         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, ctx->U, ctx->dm.dlo, stored_dt(ctx), ctx->dm.lob,
+                          ctx->stream)))
+        return fail(ctx, DGIDP_E_DEVICE, "low-order bounds launch failed");
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
     for (int r = 0; r < reps; ++r)
         if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->U, nullptr, ctx->W1, 0.0, 1.0, stored_dt(ctx), nullptr,

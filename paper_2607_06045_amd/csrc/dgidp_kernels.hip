@@ -560,6 +560,7 @@ struct StageArgs {
     double a, b;
     const double* dt;
     const double* ind;  // combined limiting: shock indicator per element, in [0, 1]
+    const double* lob;  // bounds from the low-order solution: [E][3][NN] rho min, rho max, ln s min
     // when set, dt = cfl / max over the accumulator set dtmax (bits of
     // non-negative doubles); block 0 stores it in dt_out
     const unsigned long long* dtmax;
@@ -628,8 +629,10 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
         X.c = sR[le][4][qq];                              \
     } while (0)
 
-// LIMK: 0 positivity (or none, at run time), 1 local bounds, 2 the blend of
-// the two by the per-element shock indicator A.ind (eq. combination_posLim_local)
+// LIMK: 0 positivity (or none, at run time), 1 local bounds from bar states,
+// 2 the blend of positivity and bar-state local factors by the per-element
+// shock indicator A.ind (eq. combination_posLim_local), 3 local bounds from the
+// low-order solution (eq. Bounds_LowOrder), read from A.lob
 template <int N, int MODE, bool MIXED, int LIMK>
 // at least three waves per SIMD: the local-limiting variant would otherwise
 // take 172 registers and run two (63.3 against 67.7 us on the 22,156-leaf
@@ -637,7 +640,11 @@ template <int N, int MODE, bool MIXED, int LIMK>
 __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
 {
     using G = Geo<N>;
-    constexpr bool LOC = LIMK >= 1, COMB = LIMK == 2;
+    // LOC: local bounds enforced; COMB: blended with positivity; BAR: the bounds
+    // come from bar states (computed here), otherwise from the low-order
+    // solution (read from A.lob); PURE: local factors only
+    constexpr bool LOC = LIMK >= 1, COMB = LIMK == 2, BAR = LIMK == 1 || LIMK == 2;
+    constexpr bool PURE = LIMK == 1 || LIMK == 3;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN;
     static_assert(NP % NN == 0, "pair split");
@@ -796,7 +803,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             make_node(o, g);
             double F[4];
             llf_face(dff, lowf, own, o, F);
-            if (need_loc) {
+            if (BAR && need_loc) {
                 bar_bounds(dff, lowf, own, o, g, fb_lo, fb_ls);
                 fb_hi = fb_lo;
             }
@@ -848,7 +855,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     make_node(us, g);
                     double Gf[4];
                     llf_face(dff, lowf, own, us, Gf);
-                    if (need_loc) {
+                    if (BAR && need_loc) {
                         double rb, lb;
                         bar_bounds(dff, lowf, own, us, g, rb, lb);
                         fb_lo = fmin(fb_lo, rb);
@@ -894,7 +901,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 make_node(uj, g);
                 double Gf[4];
                 llf_face(dff, lowf, own, uj, Gf);
-                if (need_loc) {
+                if (BAR && need_loc) {
                     double rb, lb;
                     bar_bounds(dff, lowf, own, uj, g, rb, lb);
                     fb_lo = fmin(fb_lo, rb);
@@ -1052,7 +1059,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             LDS_NODE(me, q);
             double F[4];
             llf_face(d, true, me, o, F);
-            if (need_loc) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
+            if (BAR && need_loc) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
             const double hs = 0.5 * (d == 0 ? hy : hx), wl = pick(tb.w, line);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1088,7 +1095,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // sR rows 1..7 are no longer read: rows 1-4 take the bar states of the
     // subcell faces owned by this node (x: density, log entropy; y: the same),
     // rows 5-7 the face lanes' bar-state range across the element face
-    if (need_loc) {
+    if (BAR && need_loc) {
         if (a < N) {
             sR[le][1][q] = brb[0];
             sR[le][2][q] = bls[0];
@@ -1180,7 +1187,17 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         if (!(uFV[0] > 0.0) || !(pFV > 0.0)) inad = 1;
         rmin = A.beta * uFV[0];
         pmin = A.beta * pFV;
-        if (need_loc) {
+        if (need_loc && !BAR) {
+            // bounds from the low-order solution; the node's own low-order
+            // state, as computed here, is inside them by definition (the
+            // bounds kernel's copy of it may differ in the last bit)
+            const size_t bi = (size_t)e * 3 * NN + q;
+            double rlo = fmin(A.lob[bi], uFV[0]);
+            rhi = fmax(A.lob[bi + NN], uFV[0]);
+            lsm = A.lob[bi + 2 * NN];
+            if (uFV[0] > 0.0 && pFV > 0.0) lsm = fmin(lsm, log(pFV) - g * log(uFV[0]));
+            rlf = fmax(rmin, rlo);
+        } else if (need_loc) {
             // bounds over the node and the bar states of its low-order neighbours
             double rlo = u0[0];
             rhi = u0[0];
@@ -1223,7 +1240,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             cf[3][v] = b < N ? -dtm * sPair[le][v][NF + fyt] : 0.0;
         }
         if (A.limiter != DGIDP_LIMIT_NONE) {
-            if (LIMK == 1) {
+            if (PURE) {
                 th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
             } else {
                 th = volume_factor<false>(uFV, cf, rmin, pmin, 0.0, 0.0, g, ig1);
@@ -1280,7 +1297,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             A.uout[idx] = r;
         }
         if (nmf == 0) {
-            if (LIMK == 1) {
+            if (PURE) {
                 if (A.st && (!(uvol[0] >= rlf * (1.0 - kLocalTol)) || uvol[0] > rhi * (1.0 + kLocalTol) ||
                              pressure(uvol, g) < pmin ||
                              !(log(pressure(uvol, g)) - g * log(uvol[0]) >= lsm - kLocalTol)))
@@ -1307,7 +1324,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     // an undefined high-order mortar flux keeps the low-order flux
                     if (!fin) {
                         ts = tsl = 0.0;
-                    } else if (LIMK == 1) {
+                    } else if (PURE) {
                         ts = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, g, ig1);
                     } else {
                         ts = mortar_factor<false>(uvol, dc, rmin, pmin, 0.0, 0.0, g, ig1);
@@ -1321,9 +1338,9 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     S[4 + v] = c[v];
                 }
                 S[8] = ts;
-                S[9] = LIMK == 1 ? rlf : rmin;
+                S[9] = PURE ? rlf : rmin;
                 S[10] = pmin;
-                if (LIMK == 1) {
+                if (PURE) {
                     S[11] = rhi;
                     S[12] = lsm;
                 }
@@ -1414,7 +1431,7 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
                 uout[((size_t)e * 4 + v) * NN + q] = uo[v] + bcoef * corr[v];
                 w[v] = rec[v] + corr[v];
             }
-            if (limiter == DGIDP_LIMIT_LOCAL) {
+            if (limiter == DGIDP_LIMIT_LOCAL || limiter == DGIDP_LIMIT_LOCAL_LOWORDER) {
                 const double rhi = R[11], lsm = R[12];
                 const double pw = pressure(w, gamma);
                 if (!(w[0] >= rec[9] * (1.0 - kLocalTol)) || w[0] > rhi * (1.0 + kLocalTol) ||
@@ -1427,6 +1444,148 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
         }
     }
     if (st) push_stats(st, 0, viol, thmin, asum, nm, true);
+}
+
+// ---------------------------------------------------------------------------
+// local bounds from the low-order solution (eq. Bounds_LowOrder): per node the
+// density range over u^FV = u + dt R_LO / m of the node and its low-order
+// neighbours (subcell neighbours; the matching node across a conforming face;
+// the nodes with a nonzero sparse weight across a mortar; none across a
+// boundary), and the smallest ln(p rho^-gamma) among those with rho, p > 0.
+// One thread per node, 256-thread blocks of whole elements; the element's own low-order states go through LDS, the
+// neighbours' are formed from u and R_LO / m loaded from global memory.
+// ---------------------------------------------------------------------------
+struct LoBoundsArgs {
+    const double* u;
+    const double* dlo;  // R_LO / m, [E][4][NN] (internal order)
+    const double* dt;   // dt source as for the stage kernel: dt, or cfl / max(dtmax)
+    const unsigned long long* dtmax;
+    double cfl;
+    const int* fnbr;
+    const int* fnbr2;
+    const int* fmort;
+    int E;
+    double gamma;
+    double* lob;  // [E][3][NN]
+};
+
+__device__ __forceinline__ void lo_bound_add(const double* w, double g, double& lo, double& hi,
+                                             double& ls)
+{
+    lo = fmin(lo, w[0]);
+    hi = fmax(hi, w[0]);
+    const double p = pressure(w, g);
+    if (w[0] > 0.0 && p > 0.0) ls = fmin(ls, log(p) - g * log(w[0]));
+}
+
+template <int N>
+__device__ __forceinline__ void lo_state(const LoBoundsArgs& A, int e, int q, double dt, double* w)
+{
+    constexpr int NN = (N + 1) * (N + 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const size_t i = ((size_t)e * 4 + v) * NN + q;
+        w[v] = A.u[i] + dt * A.dlo[i];
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_lowbounds(LoBoundsArgs A)
+{
+    constexpr int n = N + 1, NN = n * n, EPB = 256 / NN, NT = EPB * NN;
+    __shared__ double sW[EPB][4][NN];
+    const Tab<N>& tb = T<N>();
+    const double g = A.gamma;
+    const int tid = threadIdx.x;
+    const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
+    const int e = blockIdx.x * EPB + le;
+    const bool act = tid < NT && e < A.E;
+    double dt;
+    if (A.dtmax) {  // the same value the stage kernel derives
+        const double part = __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]);
+        dt = A.cfl / wave_max(part);
+    } else {
+        dt = *A.dt;
+    }
+    double w[4];
+    if (act) {
+        lo_state<N>(A, e, q, dt, w);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sW[le][v][q] = w[v];
+    }
+    __syncthreads();
+    if (!act) return;
+    double lo = __builtin_inf(), hi = -__builtin_inf(), ls = __builtin_inf();
+    lo_bound_add(w, g, lo, hi, ls);
+    const int qn4[4] = {q - 1, q + 1, q - n, q + n};
+    const bool has[4] = {a > 0, a < N, b > 0, b < N};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!has[j]) continue;
+        double o[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = sW[le][v][qn4[j]];
+        lo_bound_add(o, g, lo, hi, ls);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (has[f]) continue;  // the node is on face f exactly when it has no neighbour that way
+        const int code = A.fmort[e * 4 + f];
+        if (code < -1) continue;  // boundary
+        const int k = f < 2 ? b : a;
+        const int nb = A.fnbr[e * 4 + f];
+        double o[4];
+        if (code == -1) {
+            lo_state<N>(A, nb, face_q<N>(f ^ 1, k), dt, o);
+            lo_bound_add(o, g, lo, hi, ls);
+        } else if (!fm_small(code)) {
+            const int nb2 = A.fnbr2[e * 4 + f];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                for (int l = 0; l < n; ++l) {
+                    if (tb.Wt[k][hh * n + l] == 0.0) continue;
+                    lo_state<N>(A, hh == 0 ? nb : nb2, face_q<N>(f ^ 1, l), dt, o);
+                    lo_bound_add(o, g, lo, hi, ls);
+                }
+        } else {
+            const int hh = fm_half(code);
+#pragma unroll
+            for (int kk = 0; kk < n; ++kk) {
+                if (tb.Wt[kk][hh * n + k] == 0.0) continue;
+                lo_state<N>(A, nb, face_q<N>(f ^ 1, kk), dt, o);
+                lo_bound_add(o, g, lo, hi, ls);
+            }
+        }
+    }
+    const size_t bi = (size_t)e * 3 * NN + q;
+    A.lob[bi] = lo;
+    A.lob[bi + NN] = hi;
+    A.lob[bi + 2 * NN] = ls;
+}
+
+int launch_lowbounds(int N, const DevMesh& m, double gamma, const double* u, const double* dlo,
+                     const DtSource& dt, double* lob, hipStream_t s)
+{
+    if (m.E == 0) return 0;
+    LoBoundsArgs A;
+    A.u = u;
+    A.dlo = dlo;
+    A.dt = dt.dt;
+    A.dtmax = dt.dtmax;
+    A.cfl = dt.cfl;
+    A.fnbr = m.fnbr;
+    A.fnbr2 = m.fnbr2;
+    A.fmort = m.fmort;
+    A.E = m.E;
+    A.gamma = gamma;
+    A.lob = lob;
+    const int epb = 256 / ((N + 1) * (N + 1));  // whole elements per 256-thread block
+    const dim3 grid((m.E + epb - 1) / epb);
+    if (N == 3) hipLaunchKernelGGL(k_lowbounds<3>, grid, dim3(256), 0, s, A);
+    else if (N == 4) hipLaunchKernelGGL(k_lowbounds<4>, grid, dim3(256), 0, s, A);
+    else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1970,6 +2129,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.b = b;
     A.dt = dt.dt;
     A.ind = m.shock_ind;
+    A.lob = m.lob;
     A.dtmax = dt.dtmax;
     A.cfl = dt.cfl;
     A.dt_out = dt.dt_out;
@@ -1990,9 +2150,14 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     const int grid = (m.E + G::EPB - 1) / G::EPB;
     const bool mixed = kp.precision == DGIDP_MIXED;
     const dim3 blk(G::BS);
-    const int lk = kp.limiter == DGIDP_LIMIT_LOCAL ? 1 : (kp.limiter == DGIDP_LIMIT_COMBINED ? 2 : 0);
+    const int lk = kp.limiter == DGIDP_LIMIT_LOCAL ? 1
+                   : kp.limiter == DGIDP_LIMIT_COMBINED ? 2
+                   : kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER ? 3 : 0;
     if (mode == MODE_STAGE) {
-        if (lk == 1) {
+        if (lk == 3) {
+            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 3>), dim3(grid), blk, 0, s, A);
+            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 3>), dim3(grid), blk, 0, s, A);
+        } else if (lk == 1) {
             if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 1>), dim3(grid), blk, 0, s, A);
             else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 1>), dim3(grid), blk, 0, s, A);
         } else if (lk == 2) {

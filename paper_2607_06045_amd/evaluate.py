@@ -22,6 +22,15 @@
       throughput (with and without the adaptation time), element counts,
       sampled bound violations and the L1 density difference of the two runs
 
+  python -m paper_2607_06045_amd.evaluate cfl [--t-end 3.0] [--n 128]
+      the Sedov blast of Sec. 3.4 ([-2, 2]^2, rho = 1, p0 = 1e-5, e = 1 in
+      r0 = 0.21875, N = 3) on a uniform n x n mesh (the finest level of the
+      paper's adaptive mesh) to t-end, twice: local bounds from bar states
+      with the IDP time step at CFL 0.95, and local bounds from the low-order
+      solution with the low-order time step at CFL 0.4; reports the number of
+      steps, wall time, the smallest and largest dt, mean limiting factors and
+      bound violations of each run
+
 Prints one JSON object.  All inputs are seeded and synthetic.
 """
 import argparse
@@ -373,13 +382,61 @@ def run_scale(steps, iters=2000, seeds=2, snaps=3):
             "l1_density_scale": float(np.abs(mp).mean())}
 
 
+def run_cfl(t_end=3.0, n=128):
+    import torch
+
+    import paper_2607_06045_amd as P
+    from workloads import states
+    from workloads.meshes import uniform_mesh
+
+    spec = uniform_mesh(n, n, -2.0, -2.0, 4.0, 4.0)
+    out = {"mesh": f"uniform {n}x{n} on [-2,2]^2, N=3", "t_end": t_end}
+    for name, lim, mode, cfl in (("bar_state_bounds_idp_cfl_0.95", P.LIMIT_LOCAL, P.DT_IDP, 0.95),
+                                 ("low_order_bounds_lo_cfl_0.4", P.LIMIT_LOCAL_LOWORDER, P.DT_LOWORDER, 0.4)):
+        s = P.Solver(3, limiter=lim, dt_mode=mode)
+        s.set_mesh(*spec.args())
+        x, y = s.node_coords()
+        s.upload(states.sedov_tophat(x, y))
+        t, k, viol, inad = 0.0, 0, 0, 0
+        a_vol, a_mort, dts = 0.0, 0.0, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while t < t_end * (1 - 1e-14):
+            dt = min(s.max_dt(cfl), t_end - t)
+            st = s.step_dt(dt)
+            t += dt
+            k += 1
+            dts.append(dt)
+            viol += st["violations"]
+            inad += st["fv_inadmissible"]
+            a_vol += st["alpha_vol_mean"]
+            a_mort += st["alpha_mort_mean"]
+            if k % 1000 == 0:
+                log(f"{name}: step {k} t={t:.4f}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"steps": k, "wall_s": wall, "ms_per_step": 1e3 * wall / k,
+                     "dt_min": min(dts), "dt_max": max(dts), "violations": viol,
+                     "fv_inadmissible": inad, "alpha_vol_mean": a_vol / k, "alpha_mort_mean": a_mort / k}
+        log(f"{name}: {out[name]}")
+    b_, l_ = out["bar_state_bounds_idp_cfl_0.95"], out["low_order_bounds_lo_cfl_0.4"]
+    out["step_ratio"] = b_["steps"] / l_["steps"]
+    out["time_ratio"] = b_["wall_s"] / l_["wall_s"]
+    out["paper"] = {"steps_bar_state": 6523, "steps_low_order": 2357, "time_ratio": "about 4"}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["mixed", "learned", "scale"])
+    ap.add_argument("mode", choices=["mixed", "learned", "scale", "cfl"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--t-end", type=float, default=3.0)
+    ap.add_argument("--n", type=int, default=128)
     a = ap.parse_args(argv)
-    if a.mode == "mixed":
+    if a.mode == "cfl":
+        out = run_cfl(a.t_end, a.n)
+    elif a.mode == "mixed":
         out = run_mixed(a.steps or 200)
     elif a.mode == "scale":
         out = run_scale(a.steps or 500, iters=a.iters)
