@@ -120,18 +120,18 @@ def main():
     N = 3
     spec = workload_mesh("blast22k")
 
-    def run(precision, limiter=P.LIMIT_POSITIVITY):
-        s = P.Solver(N, gamma=1.4, beta=0.1, precision=precision, dt_mode=P.DT_IDP,
+    def run(precision, limiter=P.LIMIT_POSITIVITY, dt_mode=P.DT_IDP, cfl=0.5):
+        s = P.Solver(N, gamma=1.4, beta=0.1, precision=precision, dt_mode=dt_mode,
                      limiter=limiter)
         s.set_mesh(*spec.args())
         x, y = s.node_coords()
         s.upload(states.workload_state("blast22k", x, y))
         for _ in range(args.warmup):
-            s.step(0.5, stats=False)
+            s.step(cfl, stats=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            s.step(0.5, stats=False)
+            s.step(cfl, stats=False)
         torch.cuda.synchronize()
         return s, time.perf_counter() - t0
 
@@ -191,6 +191,15 @@ def main():
                        "ms_per_step": el_c / args.steps * 1e3, "kernel_ms": kmc["stage"],
                        "dtype": "f64", "violations": stc["violations"],
                        "alpha_vol_mean": stc["alpha_vol_mean"]}
+    # local bounds from the low-order solution (eq. Bounds_LowOrder) with the
+    # low-order time step at CFL 0.4, FP64: per step one more residual launch
+    # and the bounds kernel; each step advances a larger dt
+    so, el_o = run(P.FP64, P.LIMIT_LOCAL_LOWORDER, P.DT_LOWORDER, 0.4)
+    sto = so.step(0.4, stats=True)
+    out["local_lowsol"] = {"value": dofs * 3 * args.steps / el_o, "unit": "DOF-updates/s",
+                           "ms_per_step": el_o / args.steps * 1e3, "dtype": "f64",
+                           "violations": sto["violations"], "dt": sto["dt"], "dt_idp_cfl_0.5": st["dt"],
+                           "alpha_vol_mean": sto["alpha_vol_mean"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, N)
     print(json.dumps(out), flush=True)

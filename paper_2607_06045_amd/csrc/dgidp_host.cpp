@@ -97,6 +97,7 @@ void free_mesh(dgidp_ctx* c)
     dfree(c->dm.bext);
     dfree(c->dm.dlo);
     dfree(c->dm.lob);
+    dfree(c->dm.lsv);
     dfree(c->dm.mort);
     dfree(c->dm.h);
     dfree(c->dm.slot_node);
@@ -407,7 +408,8 @@ int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, dou
     // bounds from the low-order solution: R_LO / m of the input, then the bounds
     if (kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
         (launch_rhs(ctx->p.N, ctx->dm, kp, uin, DGIDP_RHS_LOW, ctx->dm.dlo, ctx->stream) ||
-         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, uin, ctx->dm.dlo, dt, ctx->dm.lob, ctx->stream)))
+         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, uin, ctx->dm.dlo, dt, ctx->dm.lsv, ctx->dm.lob,
+                          ctx->stream)))
         return fail(ctx, DGIDP_E_DEVICE, "low-order bounds launch failed");
     if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
@@ -545,6 +547,7 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER) {
         HIPCHK(hipMalloc((void**)&ctx->dm.dlo, sz));
         HIPCHK(hipMalloc((void**)&ctx->dm.lob, (size_t)E * 3 * NN * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&ctx->dm.lsv, (size_t)E * 2 * NN * sizeof(double)));
     }
     HIPCHK(hipMalloc((void**)&ctx->U, sz));
     HIPCHK(hipMalloc((void**)&ctx->W1, sz));
@@ -927,8 +930,8 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
     // (the low-order-solution bounds are formed once, outside the timed stages)
     if (kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
         (launch_rhs(ctx->p.N, ctx->dm, kp, ctx->U, DGIDP_RHS_LOW, ctx->dm.dlo, ctx->stream) ||
-         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, ctx->U, ctx->dm.dlo, stored_dt(ctx), ctx->dm.lob,
-                          ctx->stream)))
+         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, ctx->U, ctx->dm.dlo, stored_dt(ctx), ctx->dm.lsv,
+                          ctx->dm.lob, ctx->stream)))
         return fail(ctx, DGIDP_E_DEVICE, "low-order bounds launch failed");
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
     for (int r = 0; r < reps; ++r)

@@ -64,6 +64,7 @@ struct DevMesh {
     double* shock_ind = nullptr;  // [E] shock indicator of combined limiting (internal order)
     double* dlo = nullptr;      // [E*4*NN] R_LO / m of a stage's input (low-order-solution bounds)
     double* lob = nullptr;      // [E*3*NN] rho min, rho max, ln s min from the low-order solution
+    double* lsv = nullptr;      // [E*2*NN] low-order density and ln s per node
     int8_t* bkind = nullptr;    // [NB] condition of each boundary node (external numbering)
     double* bext = nullptr;     // [NB*4] exterior state of each boundary node
 };
@@ -142,9 +143,10 @@ int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st,
                   double gamma, int limiter);
 // per-element shock indicator on the pressure of u into m.shock_ind (combined limiting)
 int launch_shock_indicator(int N, const DevMesh& m, const double* u, double gamma, hipStream_t s);
-// local bounds from the low-order solution u + dt * dlo into lob (eq. Bounds_LowOrder)
+// local bounds from the low-order solution u + dt * dlo into lob (eq. Bounds_LowOrder);
+// lsv [E*2*NN] holds the per-node low-order density and log entropy between the passes
 int launch_lowbounds(int N, const DevMesh& m, double gamma, const double* u, const double* dlo,
-                     const DtSource& dt, double* lob, hipStream_t s);
+                     const DtSource& dt, double* lsv, double* lob, hipStream_t s);
 // max over nodes of the dt denominator, atomically merged into the accumulator
 // set acc (all zero on entry); the set other is cleared for the next step
 int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, int mode,

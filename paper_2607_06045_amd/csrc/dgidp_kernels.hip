@@ -1452,8 +1452,8 @@ __global__ __launch_bounds__(256) void k_mortar(const double* __restrict__ slot,
 // neighbours (subcell neighbours; the matching node across a conforming face;
 // the nodes with a nonzero sparse weight across a mortar; none across a
 // boundary), and the smallest ln(p rho^-gamma) among those with rho, p > 0.
-// One thread per node, 256-thread blocks of whole elements; the element's own low-order states go through LDS, the
-// neighbours' are formed from u and R_LO / m loaded from global memory.
+// Two passes: k_lowsol forms each node's low-order density and log entropy
+// once (two logarithms per node, coalesced), k_lowbounds gathers them.
 // ---------------------------------------------------------------------------
 struct LoBoundsArgs {
     const double* u;
@@ -1466,96 +1466,85 @@ struct LoBoundsArgs {
     const int* fmort;
     int E;
     double gamma;
-    double* lob;  // [E][3][NN]
+    double* lsv;  // [E][2][NN] low-order density, ln s (+inf where rho or p <= 0)
+    double* lob;  // [E][3][NN] rho min, rho max, ln s min
 };
 
-__device__ __forceinline__ void lo_bound_add(const double* w, double g, double& lo, double& hi,
-                                             double& ls)
-{
-    lo = fmin(lo, w[0]);
-    hi = fmax(hi, w[0]);
-    const double p = pressure(w, g);
-    if (w[0] > 0.0 && p > 0.0) ls = fmin(ls, log(p) - g * log(w[0]));
-}
-
 template <int N>
-__device__ __forceinline__ void lo_state(const LoBoundsArgs& A, int e, int q, double dt, double* w)
+__global__ __launch_bounds__(256) void k_lowsol(LoBoundsArgs A)
 {
     constexpr int NN = (N + 1) * (N + 1);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const size_t i = ((size_t)e * 4 + v) * NN + q;
-        w[v] = A.u[i] + dt * A.dlo[i];
-    }
-}
-
-template <int N>
-__global__ __launch_bounds__(256) void k_lowbounds(LoBoundsArgs A)
-{
-    constexpr int n = N + 1, NN = n * n, EPB = 256 / NN, NT = EPB * NN;
-    __shared__ double sW[EPB][4][NN];
-    const Tab<N>& tb = T<N>();
-    const double g = A.gamma;
-    const int tid = threadIdx.x;
-    const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
-    const int e = blockIdx.x * EPB + le;
-    const bool act = tid < NT && e < A.E;
     double dt;
-    if (A.dtmax) {  // the same value the stage kernel derives
-        const double part = __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]);
+    if (A.dtmax) {  // the same value the stage kernel derives (every lane takes part)
+        const double part = __longlong_as_double((long long)A.dtmax[(threadIdx.x & 63) * kDtStride]);
         dt = A.cfl / wave_max(part);
     } else {
         dt = *A.dt;
     }
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)A.E * NN) return;
+    const size_t e = i / NN, q = i - e * NN;
     double w[4];
-    if (act) {
-        lo_state<N>(A, e, q, dt, w);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sW[le][v][q] = w[v];
+    for (int v = 0; v < 4; ++v) {
+        const size_t k = (e * 4 + v) * NN + q;
+        w[v] = A.u[k] + dt * A.dlo[k];
     }
-    __syncthreads();
-    if (!act) return;
+    const double p = pressure(w, A.gamma);
+    A.lsv[e * 2 * NN + q] = w[0];
+    A.lsv[e * 2 * NN + NN + q] =
+        w[0] > 0.0 && p > 0.0 ? log(p) - A.gamma * log(w[0]) : __builtin_inf();
+}
+
+template <int N>
+__device__ __forceinline__ void lo_gather(const double* __restrict__ lsv, int e, int q, double& lo,
+                                          double& hi, double& ls)
+{
+    constexpr int NN = (N + 1) * (N + 1);
+    const double r = lsv[(size_t)e * 2 * NN + q];
+    lo = fmin(lo, r);
+    hi = fmax(hi, r);
+    ls = fmin(ls, lsv[(size_t)e * 2 * NN + NN + q]);
+}
+
+// one thread per node
+template <int N>
+__global__ __launch_bounds__(256) void k_lowbounds(LoBoundsArgs A)
+{
+    constexpr int n = N + 1, NN = n * n;
+    const Tab<N>& tb = T<N>();
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)A.E * NN) return;
+    const int e = (int)(i / NN), q = (int)(i - (size_t)e * NN), a = q % n, b = q / n;
     double lo = __builtin_inf(), hi = -__builtin_inf(), ls = __builtin_inf();
-    lo_bound_add(w, g, lo, hi, ls);
-    const int qn4[4] = {q - 1, q + 1, q - n, q + n};
-    const bool has[4] = {a > 0, a < N, b > 0, b < N};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (!has[j]) continue;
-        double o[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) o[v] = sW[le][v][qn4[j]];
-        lo_bound_add(o, g, lo, hi, ls);
-    }
+    lo_gather<N>(A.lsv, e, q, lo, hi, ls);
+    if (a > 0) lo_gather<N>(A.lsv, e, q - 1, lo, hi, ls);
+    if (a < N) lo_gather<N>(A.lsv, e, q + 1, lo, hi, ls);
+    if (b > 0) lo_gather<N>(A.lsv, e, q - n, lo, hi, ls);
+    if (b < N) lo_gather<N>(A.lsv, e, q + n, lo, hi, ls);
+    const bool on[4] = {a == 0, a == N, b == 0, b == N};
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (has[f]) continue;  // the node is on face f exactly when it has no neighbour that way
+        if (!on[f]) continue;
         const int code = A.fmort[e * 4 + f];
         if (code < -1) continue;  // boundary
         const int k = f < 2 ? b : a;
         const int nb = A.fnbr[e * 4 + f];
-        double o[4];
         if (code == -1) {
-            lo_state<N>(A, nb, face_q<N>(f ^ 1, k), dt, o);
-            lo_bound_add(o, g, lo, hi, ls);
+            lo_gather<N>(A.lsv, nb, face_q<N>(f ^ 1, k), lo, hi, ls);
         } else if (!fm_small(code)) {
             const int nb2 = A.fnbr2[e * 4 + f];
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-                for (int l = 0; l < n; ++l) {
-                    if (tb.Wt[k][hh * n + l] == 0.0) continue;
-                    lo_state<N>(A, hh == 0 ? nb : nb2, face_q<N>(f ^ 1, l), dt, o);
-                    lo_bound_add(o, g, lo, hi, ls);
-                }
+                for (int l = 0; l < n; ++l)
+                    if (tb.Wt[k][hh * n + l] != 0.0)
+                        lo_gather<N>(A.lsv, hh == 0 ? nb : nb2, face_q<N>(f ^ 1, l), lo, hi, ls);
         } else {
             const int hh = fm_half(code);
 #pragma unroll
-            for (int kk = 0; kk < n; ++kk) {
-                if (tb.Wt[kk][hh * n + k] == 0.0) continue;
-                lo_state<N>(A, nb, face_q<N>(f ^ 1, kk), dt, o);
-                lo_bound_add(o, g, lo, hi, ls);
-            }
+            for (int kk = 0; kk < n; ++kk)
+                if (tb.Wt[kk][hh * n + k] != 0.0) lo_gather<N>(A.lsv, nb, face_q<N>(f ^ 1, kk), lo, hi, ls);
         }
     }
     const size_t bi = (size_t)e * 3 * NN + q;
@@ -1565,7 +1554,7 @@ __global__ __launch_bounds__(256) void k_lowbounds(LoBoundsArgs A)
 }
 
 int launch_lowbounds(int N, const DevMesh& m, double gamma, const double* u, const double* dlo,
-                     const DtSource& dt, double* lob, hipStream_t s)
+                     const DtSource& dt, double* lsv, double* lob, hipStream_t s)
 {
     if (m.E == 0) return 0;
     LoBoundsArgs A;
@@ -1579,12 +1568,19 @@ int launch_lowbounds(int N, const DevMesh& m, double gamma, const double* u, con
     A.fmort = m.fmort;
     A.E = m.E;
     A.gamma = gamma;
+    A.lsv = lsv;
     A.lob = lob;
-    const int epb = 256 / ((N + 1) * (N + 1));  // whole elements per 256-thread block
-    const dim3 grid((m.E + epb - 1) / epb);
-    if (N == 3) hipLaunchKernelGGL(k_lowbounds<3>, grid, dim3(256), 0, s, A);
-    else if (N == 4) hipLaunchKernelGGL(k_lowbounds<4>, grid, dim3(256), 0, s, A);
-    else return -1;
+    const size_t nodes = (size_t)m.E * (N + 1) * (N + 1);
+    const dim3 grid((unsigned)((nodes + 255) / 256));
+    if (N == 3) {
+        hipLaunchKernelGGL(k_lowsol<3>, grid, dim3(256), 0, s, A);
+        hipLaunchKernelGGL(k_lowbounds<3>, grid, dim3(256), 0, s, A);
+    } else if (N == 4) {
+        hipLaunchKernelGGL(k_lowsol<4>, grid, dim3(256), 0, s, A);
+        hipLaunchKernelGGL(k_lowbounds<4>, grid, dim3(256), 0, s, A);
+    } else {
+        return -1;
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
