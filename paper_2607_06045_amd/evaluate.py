@@ -31,6 +31,24 @@
       steps, wall time, the smallest and largest dt, mean limiting factors and
       bound violations of each run
 
+  python -m paper_2607_06045_amd.evaluate dmr [--level 4] [--t-end 0.2]
+      the double Mach reflection of Sec. 3.6 on [0, 3.25] x [0, 1] (16 x 5
+      root cells, uniform at the given level, N = 4, bar-state local limiting,
+      IDP time step at CFL 0.9): characteristic boundaries on x-, x+ and y+
+      against the exact moving incident shock (the post-shock state where
+      x < 1/6 + (y + 20 t)/sqrt(3), updated before every step), characteristic
+      inflow on y- for x < 1/6 and a slip wall beyond; reports steps, time,
+      violations, the smallest density and pressure, and the incident shock's
+      position on the upper side against its exact value
+
+  python -m paper_2607_06045_amd.evaluate jet [--level 8] [--t-end 0.0015]
+      the Mach-2000 jet of Sec. 3.6 on [-0.5, 0.5]^2 (gamma = 5/3, N = 3,
+      Chandrashekar volume flux, combined limiting, IDP time step at CFL 0.9,
+      uniform at the given level): characteristic inflow on x- with the jet
+      state for |y| <= 0.05 and the ambient state elsewhere, characteristic
+      x+, periodic in y; reports steps, time, violations and the smallest
+      density and pressure, and how far the jet head has come
+
 Prints one JSON object.  All inputs are seeded and synthetic.
 """
 import argparse
@@ -426,16 +444,146 @@ def run_cfl(t_end=3.0, n=128):
     return out
 
 
+def _boundary_xy(s, x, y):
+    """Coordinates of the solver's boundary nodes (numbering of boundary_nodes)."""
+    N = s.N
+    bn = s.boundary_nodes()
+    e, f, k = bn[:, 0], bn[:, 1], bn[:, 2]
+    a = np.where(f == 0, 0, np.where(f == 1, N, k))
+    b = np.where(f == 2, 0, np.where(f == 3, N, k))
+    return x[e, b, a], y[e, b, a], f
+
+
+def _cons(r, v1, v2, p, g):
+    return np.array([r, r * v1, r * v2, p / (g - 1.0) + 0.5 * r * (v1 * v1 + v2 * v2)])
+
+
+def run_dmr(level=4, t_end=0.2):
+    import torch
+
+    import paper_2607_06045_amd as P
+    from workloads.meshes import MeshSpec
+
+    g, N = 1.4, 4
+    nx, ny = 16 << level, 5 << level
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    spec = MeshSpec(np.full(nx * ny, level, np.int8), ii.ravel().astype(np.int32),
+                    jj.ravel().astype(np.int32), 0.0, 0.0, 3.25, 1.0, 16, 5)
+    post = _cons(8.0, 8.25 * np.cos(np.pi / 6), -8.25 * np.sin(np.pi / 6), 116.5, g)
+    pre = _cons(1.4, 0.0, 0.0, 1.0, g)
+    CH = P.BC_CHARACTERISTIC
+    s = P.Solver(N, gamma=g, limiter=P.LIMIT_LOCAL, bc=[CH] * 4,
+                 ext=np.stack([post, pre, post, pre]))
+    s.set_mesh(*spec.args())
+    x, y = s.node_coords()
+    left = x < 1.0 / 6.0 + y / np.sqrt(3.0)
+    u = np.where(left[:, None], post[None, :, None, None], pre[None, :, None, None])
+    s.upload(np.ascontiguousarray(u))
+    bx, by, bf = _boundary_xy(s, x, y)
+
+    def exterior(t):
+        kind = np.full(len(bx), CH, np.int8)
+        kind[(bf == 2) & (bx >= 1.0 / 6.0)] = P.BC_WALL
+        shocked = bx < 1.0 / 6.0 + (by + 20.0 * t) / np.sqrt(3.0)
+        ext = np.where(shocked[:, None], post[None, :], pre[None, :])
+        ext[bf == 2] = post  # the characteristic part of y- is post-shock
+        return kind, np.ascontiguousarray(ext)
+
+    t, k, viol = 0.0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while t < t_end * (1 - 1e-14):
+        s.set_boundary_states(*exterior(t))
+        dt = min(s.max_dt(0.9), t_end - t)
+        st = s.step_dt(dt)
+        viol += st["violations"]
+        t += dt
+        k += 1
+        if k % 500 == 0:
+            log(f"dmr: step {k} t={t:.4f}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    u = s.download()
+    rho = u[:, 0]
+    p = (g - 1) * (u[:, 3] - 0.5 * (u[:, 1] ** 2 + u[:, 2] ** 2) / u[:, 0])
+    # incident shock on the upper side: where the top row of nodes crosses the
+    # mean of the two densities, against 1/6 + (1 + 20 t)/sqrt(3)
+    top = np.abs(y - 1.0) < 1e-12
+    xs, rs = x[top], rho[top]
+    o = np.argsort(xs)
+    xs, rs = xs[o], rs[o]
+    mid = 0.5 * (8.0 + 1.4)
+    cross = xs[np.nonzero((rs[:-1] >= mid) & (rs[1:] < mid))[0]]
+    exact = 1.0 / 6.0 + (1.0 + 20.0 * t_end) / np.sqrt(3.0)
+    return {"mesh": f"uniform {nx}x{ny}, N={N}", "elements": s.E, "t_end": t_end, "steps": k,
+            "wall_s": wall, "ms_per_step": 1e3 * wall / k, "violations": viol,
+            "rho_min": float(rho.min()), "p_min": float(p.min()), "rho_max": float(rho.max()),
+            "top_shock_x": [float(c) for c in cross], "top_shock_x_exact": exact,
+            "hx": 3.25 / nx}
+
+
+def run_jet(level=8, t_end=0.0015):
+    import torch
+
+    import paper_2607_06045_amd as P
+    from workloads.meshes import uniform_mesh
+
+    g, N = 5.0 / 3.0, 3
+    n = 1 << level
+    spec = uniform_mesh(n, n, -0.5, -0.5, 1.0, 1.0)
+    amb = _cons(0.5, 0.0, 0.0, 0.4127, g)
+    jet = _cons(5.0, 800.0, 0.0, 0.4127, g)
+    CH = P.BC_CHARACTERISTIC
+    s = P.Solver(N, gamma=g, limiter=P.LIMIT_COMBINED, volume_flux=P.FLUX_CHANDRASHEKAR,
+                 bc=[CH, CH, P.BC_PERIODIC, P.BC_PERIODIC], ext=np.stack([amb, amb, amb, amb]))
+    s.set_mesh(*spec.args())
+    x, y = s.node_coords()
+    s.upload(np.ascontiguousarray(np.broadcast_to(amb[None, :, None, None], (s.E, 4, N + 1, N + 1))))
+    bx, by, bf = _boundary_xy(s, x, y)
+    ext = np.tile(amb, (len(bx), 1))
+    ext[(bf == 0) & (np.abs(by) <= 0.05)] = jet
+    s.set_boundary_states(np.full(len(bx), CH, np.int8), ext)
+    t, k, viol, inad = 0.0, 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while t < t_end * (1 - 1e-14):
+        dt = min(s.max_dt(0.9), t_end - t)
+        st = s.step_dt(dt)
+        viol += st["violations"]
+        inad += st["fv_inadmissible"]
+        t += dt
+        k += 1
+        if k % 500 == 0:
+            log(f"jet: step {k} t={t:.6f}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    u = s.download()
+    rho = u[:, 0]
+    p = (g - 1) * (u[:, 3] - 0.5 * (u[:, 1] ** 2 + u[:, 2] ** 2) / u[:, 0])
+    v1 = u[:, 1] / rho
+    fast = v1 > 400.0  # jet material
+    return {"mesh": f"uniform {n}x{n}, N={N}", "elements": s.E, "t_end": t_end, "steps": k,
+            "wall_s": wall, "ms_per_step": 1e3 * wall / k, "violations": viol,
+            "fv_inadmissible": inad, "rho_min": float(rho.min()), "p_min": float(p.min()),
+            "rho_max": float(rho.max()), "jet_head_x": float(x[fast].max()) if fast.any() else None,
+            "dofs": s.E * (N + 1) ** 2}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["mixed", "learned", "scale", "cfl"])
+    ap.add_argument("mode", choices=["mixed", "learned", "scale", "cfl", "dmr", "jet"])
+    ap.add_argument("--level", type=int, default=None)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=3000)
-    ap.add_argument("--t-end", type=float, default=3.0)
+    ap.add_argument("--t-end", type=float, default=None)
     ap.add_argument("--n", type=int, default=128)
     a = ap.parse_args(argv)
     if a.mode == "cfl":
-        out = run_cfl(a.t_end, a.n)
+        out = run_cfl(3.0 if a.t_end is None else a.t_end, a.n)
+    elif a.mode == "dmr":
+        out = run_dmr(4 if a.level is None else a.level, 0.2 if a.t_end is None else a.t_end)
+    elif a.mode == "jet":
+        out = run_jet(8 if a.level is None else a.level, 0.0015 if a.t_end is None else a.t_end)
     elif a.mode == "mixed":
         out = run_mixed(a.steps or 200)
     elif a.mode == "scale":

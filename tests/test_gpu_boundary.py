@@ -161,3 +161,31 @@ def test_boundary_arguments():
     from paper_2607_06045_amd import _lib
     b = np.array([0, 0, 0, 0], np.int32)
     assert _lib._lib.dgidp_set_boundaries(s._h, b.ctypes.data, None) == -1
+
+
+def test_double_mach_reflection_short():
+    """The double Mach reflection (Sec. 3.6) at 64 x 20 elements, N = 4, to
+    t = 0.05: the incident shock is straight and moves at a known speed, so its
+    position on the upper side (characteristic boundary against the exact moving
+    shock) is exact: within two cell widths.  No bound violations; the density
+    stays above the pre-shock value up to the limiter's tolerance."""
+    from paper_2607_06045_amd.evaluate import run_dmr
+    r = run_dmr(level=2, t_end=0.05)
+    print(r, flush=True)
+    assert r["violations"] == 0
+    assert r["rho_min"] > 1.4 * (1 - 1e-3) and r["p_min"] > 0.99
+    assert len(r["top_shock_x"]) == 1
+    assert abs(r["top_shock_x"][0] - r["top_shock_x_exact"]) < 2 * r["hx"]
+
+
+def test_jet_short():
+    """The Mach-2000 jet (Sec. 3.6: gamma = 5/3, Chandrashekar flux, combined
+    limiting, characteristic inflow band) at 32 x 32 elements to t = 5e-4: no
+    bound violations, no inadmissible low-order state, positive density and
+    pressure, and the jet has entered the domain."""
+    from paper_2607_06045_amd.evaluate import run_jet
+    r = run_jet(level=5, t_end=5e-4)
+    print(r, flush=True)
+    assert r["violations"] == 0 and r["fv_inadmissible"] == 0
+    assert r["rho_min"] > 0 and r["p_min"] > 0
+    assert r["jet_head_x"] is not None and r["jet_head_x"] > -0.3
