@@ -1608,16 +1608,19 @@ __device__ __forceinline__ double wave_speed(const NodeP& s, int d)
     return fabs(d == 0 ? s.v1 : s.v2) + s.c;
 }
 
-// the dt kernel: 256-thread blocks (16 elements at N = 3, 10 at N = 4), fewer
+// the dt kernel: kDtBlock = 256-thread blocks (16 elements at N = 3, 10 at N = 4), fewer
 // blocks and so fewer atomics than the stage kernel's geometry
+// threads per block of the dt kernel (whole elements per block)
+constexpr int kDtBlock = 256;
+
 template <int N>
 struct DtGeo {
     static constexpr int n = N + 1, NN = n * n, NFN = 4 * n;
-    static constexpr int BS = 256, EPB = BS / NN, NT = EPB * NN;
+    static constexpr int BS = kDtBlock, EPB = BS / NN, NT = EPB * NN;
 };
 
 template <int N>
-__global__ __launch_bounds__(256) void k_dt(DtArgs A)
+__global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
 {
     using G = DtGeo<N>;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
@@ -2229,9 +2232,9 @@ int launch_dt(int N, const DevMesh& m, const KernelParams& kp, const double* u, 
     A.acc = acc;
     A.other = other;
     if (N == 3)
-        hipLaunchKernelGGL(k_dt<3>, dim3((m.E + DtGeo<3>::EPB - 1) / DtGeo<3>::EPB), dim3(256), 0, s, A);
+        hipLaunchKernelGGL(k_dt<3>, dim3((m.E + DtGeo<3>::EPB - 1) / DtGeo<3>::EPB), dim3(kDtBlock), 0, s, A);
     else if (N == 4)
-        hipLaunchKernelGGL(k_dt<4>, dim3((m.E + DtGeo<4>::EPB - 1) / DtGeo<4>::EPB), dim3(256), 0, s, A);
+        hipLaunchKernelGGL(k_dt<4>, dim3((m.E + DtGeo<4>::EPB - 1) / DtGeo<4>::EPB), dim3(kDtBlock), 0, s, A);
     else return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
