@@ -338,6 +338,9 @@ class Solver:
         E, M = ctypes.c_int64(), ctypes.c_int64()
         self._check(_lib.dgidp_mesh_info(self._h, ctypes.byref(E), ctypes.byref(M)), "dgidp_mesh_info")
         self.E, self.M = E.value, M.value
+        nb = ctypes.c_int64()
+        self._check(_lib.dgidp_boundary_nodes(self._h, ctypes.byref(nb), None), "dgidp_boundary_nodes")
+        self.NB = nb.value
         return st.to_dict()
 
     def mesh(self):

@@ -31,7 +31,7 @@
       steps, wall time, the smallest and largest dt, mean limiting factors and
       bound violations of each run
 
-  python -m paper_2607_06045_amd.evaluate dmr [--level 4] [--t-end 0.2]
+  python -m paper_2607_06045_amd.evaluate dmr [--level 4] [--t-end 0.2] [--amr]
       the double Mach reflection of Sec. 3.6 on [0, 3.25] x [0, 1] (16 x 5
       root cells, uniform at the given level, N = 4, bar-state local limiting,
       IDP time step at CFL 0.9): characteristic boundaries on x-, x+ and y+
@@ -39,7 +39,9 @@
       x < 1/6 + (y + 20 t)/sqrt(3), updated before every step), characteristic
       inflow on y- for x < 1/6 and a slip wall beyond; reports steps, time,
       violations, the smallest density and pressure, and the incident shock's
-      position on the upper side against its exact value
+      position on the upper side against its exact value; with --amr the mesh
+      starts two levels coarser and the modal indicator adapts it every 5
+      steps up to the given level (the exterior states follow every new mesh)
 
   python -m paper_2607_06045_amd.evaluate jet [--level 8] [--t-end 0.0015]
       the Mach-2000 jet of Sec. 3.6 on [-0.5, 0.5]^2 (gamma = 5/3, N = 3,
@@ -458,16 +460,20 @@ def _cons(r, v1, v2, p, g):
     return np.array([r, r * v1, r * v2, p / (g - 1.0) + 0.5 * r * (v1 * v1 + v2 * v2)])
 
 
-def run_dmr(level=4, t_end=0.2):
+def run_dmr(level=4, t_end=0.2, amr=False, every=5):
     import torch
 
     import paper_2607_06045_amd as P
     from workloads.meshes import MeshSpec
 
     g, N = 1.4, 4
-    nx, ny = 16 << level, 5 << level
+    # with AMR: start two levels coarser; the modal indicator refines up to
+    # the given level (controller levels relative to the 16 x 5 root grid)
+    ctrl = (level - 2, level - 1, 0.01, level, 0.1)
+    start = level - 2 if amr else level
+    nx, ny = 16 << start, 5 << start
     ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
-    spec = MeshSpec(np.full(nx * ny, level, np.int8), ii.ravel().astype(np.int32),
+    spec = MeshSpec(np.full(nx * ny, start, np.int8), ii.ravel().astype(np.int32),
                     jj.ravel().astype(np.int32), 0.0, 0.0, 3.25, 1.0, 16, 5)
     post = _cons(8.0, 8.25 * np.cos(np.pi / 6), -8.25 * np.sin(np.pi / 6), 116.5, g)
     pre = _cons(1.4, 0.0, 0.0, 1.0, g)
@@ -475,11 +481,21 @@ def run_dmr(level=4, t_end=0.2):
     s = P.Solver(N, gamma=g, limiter=P.LIMIT_LOCAL, bc=[CH] * 4,
                  ext=np.stack([post, pre, post, pre]))
     s.set_mesh(*spec.args())
+
+    def initial(x, y):
+        left = x < 1.0 / 6.0 + y / np.sqrt(3.0)
+        return np.ascontiguousarray(np.where(left[:, None], post[None, :, None, None],
+                                             pre[None, :, None, None]))
+
     x, y = s.node_coords()
-    left = x < 1.0 / 6.0 + y / np.sqrt(3.0)
-    u = np.where(left[:, None], post[None, :, None, None], pre[None, :, None, None])
-    s.upload(np.ascontiguousarray(u))
+    s.upload(initial(x, y))
+    if amr:  # refine the initial discontinuity, taking the exact state each time
+        for _ in range(3):
+            s.refine_coarsen(P.amr_flags(s.indicator(), s.mesh()[0], *ctrl))
+            x, y = s.node_coords()
+            s.upload(initial(x, y))
     bx, by, bf = _boundary_xy(s, x, y)
+    leaves = [s.E]
 
     def exterior(t):
         kind = np.full(len(bx), CH, np.int8)
@@ -493,6 +509,11 @@ def run_dmr(level=4, t_end=0.2):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while t < t_end * (1 - 1e-14):
+        if amr and k > 0 and k % every == 0:
+            s.refine_coarsen(P.amr_flags(s.indicator(), s.mesh()[0], *ctrl))
+            x, y = s.node_coords()
+            bx, by, bf = _boundary_xy(s, x, y)
+            leaves.append(s.E)
         s.set_boundary_states(*exterior(t))
         dt = min(s.max_dt(0.9), t_end - t)
         st = s.step_dt(dt)
@@ -515,11 +536,14 @@ def run_dmr(level=4, t_end=0.2):
     mid = 0.5 * (8.0 + 1.4)
     cross = xs[np.nonzero((rs[:-1] >= mid) & (rs[1:] < mid))[0]]
     exact = 1.0 / 6.0 + (1.0 + 20.0 * t_end) / np.sqrt(3.0)
-    return {"mesh": f"uniform {nx}x{ny}, N={N}", "elements": s.E, "t_end": t_end, "steps": k,
+    mesh = (f"adaptive, levels {ctrl[0]}..{ctrl[3]} of the 16x5 root grid (finest {16 << level}x{5 << level}),"
+            f" adapted every {every} steps, N={N}" if amr else f"uniform {nx}x{ny}, N={N}")
+    return {"mesh": mesh, "elements": s.E, "leaves_min": min(leaves), "leaves_max": max(leaves),
+            "t_end": t_end, "steps": k,
             "wall_s": wall, "ms_per_step": 1e3 * wall / k, "violations": viol,
             "rho_min": float(rho.min()), "p_min": float(p.min()), "rho_max": float(rho.max()),
             "top_shock_x": [float(c) for c in cross], "top_shock_x_exact": exact,
-            "hx": 3.25 / nx}
+            "hx": 3.25 / (16 << level)}
 
 
 def run_jet(level=8, t_end=0.0015):
@@ -573,6 +597,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=["mixed", "learned", "scale", "cfl", "dmr", "jet"])
     ap.add_argument("--level", type=int, default=None)
+    ap.add_argument("--amr", action="store_true")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--t-end", type=float, default=None)
@@ -581,7 +606,7 @@ def main(argv=None):
     if a.mode == "cfl":
         out = run_cfl(3.0 if a.t_end is None else a.t_end, a.n)
     elif a.mode == "dmr":
-        out = run_dmr(4 if a.level is None else a.level, 0.2 if a.t_end is None else a.t_end)
+        out = run_dmr(4 if a.level is None else a.level, 0.2 if a.t_end is None else a.t_end, a.amr)
     elif a.mode == "jet":
         out = run_jet(8 if a.level is None else a.level, 0.0015 if a.t_end is None else a.t_end)
     elif a.mode == "mixed":
