@@ -134,3 +134,40 @@ def test_refine_coarsen_errors():
         s.refine_coarsen(np.zeros(spec.E + 1, np.int8))
     with pytest.raises(P.DgidpError):
         s.refine_coarsen(np.zeros(spec.E, np.int8), zs_eps=-1.0)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_adaptation_with_walls(oracle, N):
+    """Adaptation on a mesh with slip walls and characteristic sides: the same
+    leaf list and transferred state as the oracle (the balance rules are those
+    of the periodic domain), the boundary nodes of the new mesh numbered as the
+    oracle numbers them and reset to the side settings, and a step on the
+    adapted mesh equal to the oracle's."""
+    import paper_2607_06045_amd as P
+    spec = random_mesh(2, 4, 3, 0.4)
+    ext = np.tile(np.array([1.0, 0.3, -0.1, 2.5]), (4, 1))
+    bc = [P.BC_WALL, P.BC_WALL, P.BC_CHARACTERISTIC, P.BC_OUTFLOW]
+    s = P.Solver(N, bc=bc, ext=ext)
+    s.set_mesh(*spec.args())
+    M = oracle.Mesh(N, *spec.args(), bc=bc, ext=ext)
+    x, y, m = M.geometry()
+    u = states.density_wave(x, y)
+    s.upload(u)
+    s.set_boundary_states(np.full(s.NB, P.BC_WALL, np.int8), np.tile(ext[0], (s.NB, 1)))
+    flags = random_flags(spec, 31, p_refine=0.2, p_coarsen=0.6)
+    s.refine_coarsen(flags, zs_eps=1e-10)
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, flags)
+    lv, ix, iy = s.mesh()
+    assert np.array_equal(lv, nl) and np.array_equal(ix, nx) and np.array_equal(iy, ny)
+    ref, _, _ = oracle.transfer(N, kind, src, u, eps=1e-10)
+    assert state_err(s.download(), ref) < TOL
+    M2 = oracle.Mesh(N, nl, nx, ny, *spec.args()[3:], bc=bc, ext=ext)
+    assert (s.E, s.M, s.NB) == (M2.E, M2.M, M2.NB)
+    assert np.array_equal(s.boundary_nodes(), M2.boundary_nodes())
+    u2 = s.download()
+    dt = M2.max_dt(u2, 0.5)
+    st = s.step_dt(dt)
+    c, sc = M2.ssprk3_dt(u2, dt)
+    err = state_err(s.download(), c)
+    print(f"adaptation with walls N={N}: {spec.E} -> {s.E} leaves, NB {s.NB}, step err={err:.2e}", flush=True)
+    assert err < TOL and st["violations"] == 0
