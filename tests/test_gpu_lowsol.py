@@ -145,3 +145,18 @@ def test_lowsol_mixed_precision(oracle):
     scale = (np.abs(g) * m[:, None]).sum(axis=(0, 2, 3))
     cons = np.abs((g * m[:, None]).sum(axis=(0, 2, 3)) - tot0) / scale
     assert cons.max() < 1e-9
+
+
+def test_cfl_comparison_short():
+    """The comparison of Sec. 3.4 on a 32 x 32 Sedov mesh to t = 0.2: local
+    bounds from bar states with the IDP time step at CFL 0.95 need more steps
+    than local bounds from the low-order solution with the low-order time step
+    at CFL 0.4 (the paper: 6523 against 2357 on its adaptive mesh to t = 3);
+    both runs keep their bounds."""
+    from paper_2607_06045_amd.evaluate import run_cfl
+    r = run_cfl(t_end=0.2, n=32)
+    b, l = r["bar_state_bounds_idp_cfl_0.95"], r["low_order_bounds_lo_cfl_0.4"]
+    print(f"steps {b['steps']} against {l['steps']}, ratio {r['step_ratio']:.2f}", flush=True)
+    assert b["violations"] == 0 and l["violations"] == 0
+    assert b["fv_inadmissible"] == 0 and l["fv_inadmissible"] == 0
+    assert r["step_ratio"] > 1.5
