@@ -3,11 +3,12 @@
 # N = 3, FP64): kernel-trace statistics of bench.py, then a FETCH_SIZE pass and
 # a WRITE_SIZE pass of the same benchmark and of a plain 512 MiB device copy
 # (counter calibration).  Run from the repository root on a machine with the
-# GPU; raw output and the two summaries go to $PROFILE_OUT (default
-# gpurun_out/prof): kernels_k_stage_blast22k.txt, traffic_k_stage_blast22k.json.
+# GPU; raw output and the two summaries go to $PROFILE_OUT (default prof_out,
+# not tracked): kernels_k_stage_blast22k.txt, traffic_k_stage_blast22k.json
+# under summary/.
 set -o pipefail
 ROOT=$(pwd)
-OUT=$ROOT/${PROFILE_OUT:-gpurun_out/prof}
+OUT=$ROOT/${PROFILE_OUT:-prof_out}
 mkdir -p "$OUT/summary"
 cd /tmp && export TMPDIR=/tmp && cd "$ROOT" || exit 1
 CMD="bash paper_2607_06045_amd/profile_bench.sh"
