@@ -25,7 +25,14 @@ namespace dgidp {
 
 namespace {
 
-inline int64_t pmod(int64_t a, int64_t m) { return ((a % m) + m) % m; }
+// a mod m in [0, m); neighbour indices are at most one period off, which
+// needs no division
+inline int64_t pmod(int64_t a, int64_t m)
+{
+    if (a >= 0 && a < m) return a;
+    if (a >= -m && a < 2 * m) return a < 0 ? a + m : a - m;
+    return ((a % m) + m) % m;
+}
 
 // leaves across face f of leaf e (one same-level or coarser leaf, or up to two
 // finer ones); returns the count

@@ -129,15 +129,20 @@ inline uint64_t key_of(int l, int64_t i, int64_t j)
     return ((uint64_t)l << 56) | ((uint64_t)i << 28) | (uint64_t)j;
 }
 
-inline uint64_t morton(uint64_t x, uint64_t y)
+// bits 0..30 of v moved to the even bit positions 0..60
+inline uint64_t spread_bits(uint64_t v)
 {
-    uint64_t k = 0;
-    for (int b = 0; b < 31; ++b) {
-        k |= ((x >> b) & 1ull) << (2 * b);
-        k |= ((y >> b) & 1ull) << (2 * b + 1);
-    }
-    return k;
+    v &= 0x7fffffffull;
+    v = (v | (v << 16)) & 0x0000ffff0000ffffull;
+    v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
+    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
 }
+
+// Morton (Z-order) key of cell (x, y): the bits of x and y interleaved, x first
+inline uint64_t morton(uint64_t x, uint64_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
 
 double host_pressure(const double* u, double g)
 {
@@ -240,6 +245,15 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
                 hm.bface_elem.push_back((int)(e * 4 + f));
             }
     hm.NBF = (int64_t)hm.bface_elem.size();
+    // the same-level leaf across each face (-1: none, the face is nonconforming;
+    // unused on boundary faces), looked up once for the ordering and pass 1
+    std::vector<int> same((size_t)E * 4, -1);
+    for (int64_t e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f) {
+            if (bface[e * 4 + f] >= 0) continue;
+            const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
+            same[e * 4 + f] = lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy);
+        }
     // internal order: Morton order of the leaves on the finest grid, cut into
     // the eight contiguous ranges that the stage kernel hands to the eight
     // XCDs; inside each range the leaves with a nonconforming face come first.
@@ -261,11 +275,8 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
             const int64_t lo = std::min<int64_t>(E, g0 * epb), hi = std::min<int64_t>(E, (g0 + gn) * epb);
             std::stable_partition(ord.begin() + lo, ord.begin() + hi, [&](const std::pair<uint64_t, int>& o) {
                 const int e = o.second;
-                for (int f = 0; f < 4; ++f) {
-                    const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
-                    if (bface[e * 4 + f] < 0 && lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy) < 0)
-                        return true;
-                }
+                for (int f = 0; f < 4; ++f)
+                    if (bface[e * 4 + f] < 0 && same[e * 4 + f] < 0) return true;
                 return false;
             });
             g0 += gn;
@@ -293,7 +304,7 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
             }
             const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
             const int64_t cx = ix[e] + dx, cy = iy[e] + dy;
-            const int g = lookup(l, cx, cy);
+            const int g = same[e * 4 + f];
             if (g >= 0) {
                 hm.fnbr[i * 4 + f] = inv[g];
                 continue;

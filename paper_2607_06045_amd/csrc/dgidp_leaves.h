@@ -65,12 +65,15 @@ class LeafLookup {
         return it == map_.end() ? -1 : it->second;
     }
 
-    // the same with periodic wrapping of (i, j)
+    // the same with periodic wrapping of (i, j); the remainders are taken only
+    // for indices outside the grid (face neighbours of boundary leaves)
     int64_t get_wrapped(int l, int64_t i, int64_t j) const
     {
         if (l < 0 || l > lmax_) return -1;
         const int64_t nx = (int64_t)nx0_ << l, ny = (int64_t)ny0_ << l;
-        return get(l, ((i % nx) + nx) % nx, ((j % ny) + ny) % ny);
+        if (i < 0 || i >= nx) i = ((i % nx) + nx) % nx;
+        if (j < 0 || j >= ny) j = ((j % ny) + ny) % ny;
+        return get(l, i, j);
     }
 
     int max_level() const { return lmax_; }
