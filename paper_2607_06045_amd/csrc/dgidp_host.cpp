@@ -18,6 +18,21 @@ int host_tables(int N, double* out);
 
 using namespace dgidp;
 
+// Device buffers of a context that live from one mesh to the next: a mesh
+// upload or adaptation reallocates a buffer only when it needs more than the
+// buffer holds (then with 25% headroom), instead of freeing and allocating
+// every array each time.  The state alternates between two slots so that an
+// adaptation can read the old state while it writes the new one.
+enum PoolSlot {
+    P_FNBR, P_FNBR2, P_FMORT, P_MORT, P_H, P_SNODE, P_SPART, P_PERM, P_BKIND, P_BEXT, P_SLOT,
+    P_SHOCK, P_DLO, P_LOB, P_LSV, P_U0, P_U1, P_W1, P_W2, P_TKIND, P_TSRC, P_TGRP, P_TCOUNT,
+    P_COUNT
+};
+struct PoolBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
 struct dgidp_ctx {
     dgidp_params p{};
     hipStream_t stream = nullptr;
@@ -53,6 +68,8 @@ struct dgidp_ctx {
     // domain sides (x-, x+, y-, y+): condition and exterior state
     int bc[4] = {0, 0, 0, 0};
     double bc_ext[16] = {};
+    PoolBuf pool[P_COUNT];
+    int u_slot = 0;  // P_U0 + u_slot holds the state
     int64_t NB = 0;  // boundary nodes of the mesh
     std::vector<int> bface_elem;  // [NB / (N+1)] external element * 4 + face
 };
@@ -87,27 +104,42 @@ void drop_graphs(dgidp_ctx* c)
     }
 }
 
+// a pool buffer of at least bytes (its previous contents are not kept when it
+// grows); the caller has made sure that no queued work still uses it
+template <typename T>
+int pool_get(dgidp_ctx* c, int slot, size_t bytes, T*& out)
+{
+    bytes = std::max<size_t>(bytes, 1);
+    PoolBuf& b = c->pool[slot];
+    if (b.cap < bytes) {
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        const size_t want = bytes + bytes / 4;
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            b.p = nullptr;
+            out = nullptr;
+            return fail(c, DGIDP_E_DEVICE, "device allocation failed");
+        }
+        b.cap = want;
+    }
+    out = (T*)b.p;
+    return 0;
+}
+
+void free_pool(dgidp_ctx* c)
+{
+    for (auto& b : c->pool) {
+        if (b.p) (void)hipFree(b.p);
+        b = PoolBuf();
+    }
+}
+
+// forget the mesh; its device buffers stay in the pool
 void free_mesh(dgidp_ctx* c)
 {
     drop_graphs(c);
-    dfree(c->dm.fnbr);
-    dfree(c->dm.fnbr2);
-    dfree(c->dm.fmort);
-    dfree(c->dm.bkind);
-    dfree(c->dm.bext);
-    dfree(c->dm.dlo);
-    dfree(c->dm.lob);
-    dfree(c->dm.lsv);
-    dfree(c->dm.mort);
-    dfree(c->dm.h);
-    dfree(c->dm.slot_node);
-    dfree(c->dm.slot_partner);
-    dfree(c->dm.slot);
-    dfree(c->dm.perm);
-    dfree(c->dm.shock_ind);
-    dfree(c->U);
-    dfree(c->W1);
-    dfree(c->W2);
+    c->U = c->W1 = c->W2 = nullptr;
     c->dm = DevMesh();
     c->E = c->M = 0;
     c->NB = 0;
@@ -116,10 +148,10 @@ void free_mesh(dgidp_ctx* c)
 }
 
 template <typename T>
-int upload(dgidp_ctx* ctx, T*& dst, const std::vector<T>& src)
+int upload(dgidp_ctx* ctx, int slot, T*& dst, const std::vector<T>& src)
 {
     const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
-    HIPCHK(hipMalloc((void**)&dst, bytes));
+    if (int rc = pool_get(ctx, slot, bytes, dst)) return rc;
     if (!src.empty()) HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
     return 0;
 }
@@ -474,6 +506,7 @@ void dgidp_destroy(dgidp_ctx* ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     free_mesh(ctx);
+    free_pool(ctx);
     dfree(ctx->dt_dev);
     dfree(ctx->acc);
     dfree(ctx->ind_buf);
@@ -543,26 +576,28 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     ctx->nx0 = nx0;
     ctx->ny0 = ny0;
     int rc = 0;
-    if ((rc = upload(ctx, ctx->dm.fnbr, hm.fnbr)) || (rc = upload(ctx, ctx->dm.fnbr2, hm.fnbr2)) ||
-        (rc = upload(ctx, ctx->dm.fmort, hm.fmort)) ||
-        (rc = upload(ctx, ctx->dm.mort, hm.mort)) || (rc = upload(ctx, ctx->dm.h, hh)) ||
-        (rc = upload(ctx, ctx->dm.slot_node, hm.snode)) ||
-        (rc = upload(ctx, ctx->dm.slot_partner, hm.spart)) || (rc = upload(ctx, ctx->dm.perm, hm.perm)) ||
-        (rc = upload(ctx, ctx->dm.bkind, bkind)) || (rc = upload(ctx, ctx->dm.bext, bext)))
+    if ((rc = upload(ctx, P_FNBR, ctx->dm.fnbr, hm.fnbr)) || (rc = upload(ctx, P_FNBR2, ctx->dm.fnbr2, hm.fnbr2)) ||
+        (rc = upload(ctx, P_FMORT, ctx->dm.fmort, hm.fmort)) ||
+        (rc = upload(ctx, P_MORT, ctx->dm.mort, hm.mort)) || (rc = upload(ctx, P_H, ctx->dm.h, hh)) ||
+        (rc = upload(ctx, P_SNODE, ctx->dm.slot_node, hm.snode)) ||
+        (rc = upload(ctx, P_SPART, ctx->dm.slot_partner, hm.spart)) ||
+        (rc = upload(ctx, P_PERM, ctx->dm.perm, hm.perm)) ||
+        (rc = upload(ctx, P_BKIND, ctx->dm.bkind, bkind)) || (rc = upload(ctx, P_BEXT, ctx->dm.bext, bext)))
         return rc;
     ctx->NB = NB;
     ctx->bface_elem = hm.bface_elem;
     const size_t sz = (size_t)E * 4 * NN * sizeof(double);
-    HIPCHK(hipMalloc((void**)&ctx->dm.slot, std::max<size_t>(1, (size_t)M * 3 * n) * kSlotW * sizeof(double)));
-    HIPCHK(hipMalloc((void**)&ctx->dm.shock_ind, std::max<size_t>(1, (size_t)E) * sizeof(double)));
-    if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER) {
-        HIPCHK(hipMalloc((void**)&ctx->dm.dlo, sz));
-        HIPCHK(hipMalloc((void**)&ctx->dm.lob, (size_t)E * 3 * NN * sizeof(double)));
-        HIPCHK(hipMalloc((void**)&ctx->dm.lsv, (size_t)E * 2 * NN * sizeof(double)));
-    }
-    HIPCHK(hipMalloc((void**)&ctx->U, sz));
-    HIPCHK(hipMalloc((void**)&ctx->W1, sz));
-    HIPCHK(hipMalloc((void**)&ctx->W2, sz));
+    if ((rc = pool_get(ctx, P_SLOT, (size_t)M * 3 * n * kSlotW * sizeof(double), ctx->dm.slot)) ||
+        (rc = pool_get(ctx, P_SHOCK, (size_t)E * sizeof(double), ctx->dm.shock_ind)))
+        return rc;
+    if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
+        ((rc = pool_get(ctx, P_DLO, sz, ctx->dm.dlo)) ||
+         (rc = pool_get(ctx, P_LOB, (size_t)E * 3 * NN * sizeof(double), ctx->dm.lob)) ||
+         (rc = pool_get(ctx, P_LSV, (size_t)E * 2 * NN * sizeof(double), ctx->dm.lsv))))
+        return rc;
+    if ((rc = pool_get(ctx, P_U0 + ctx->u_slot, sz, ctx->U)) || (rc = pool_get(ctx, P_W1, sz, ctx->W1)) ||
+        (rc = pool_get(ctx, P_W2, sz, ctx->W2)))
+        return rc;
     ctx->dm.E = (int)E;
     ctx->dm.M = M;
     return 0;
@@ -999,16 +1034,13 @@ int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int
     // old external -> old internal
     std::vector<int> inv_old((size_t)ctx->E);
     for (int64_t i = 0; i < ctx->E; ++i) inv_old[ctx->perm[i]] = (int)i;
-    // keep the old state; installing the new mesh frees everything else
+    // keep the old state in its slot; the new mesh takes the other state slot
     double* uold = ctx->U;
-    ctx->U = nullptr;
+    ctx->u_slot ^= 1;
     const double x0 = ctx->x0, y0 = ctx->y0, Lx = ctx->Lx, Ly = ctx->Ly;
     rc = dgidp_mesh_upload(ctx, En, plan.level.data(), plan.ix.data(), plan.iy.data(), x0, y0, Lx,
                            Ly, ctx->nx0, ctx->ny0);
-    if (rc) {
-        (void)hipFree(uold);
-        return rc;
-    }
+    if (rc) return rc;
     // new external -> new internal
     std::vector<int> inv_new((size_t)En);
     for (int64_t i = 0; i < En; ++i) inv_new[ctx->perm[i]] = (int)i;
@@ -1040,18 +1072,12 @@ int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int
     int *dk = nullptr, *ds = nullptr, *dg = nullptr;
     unsigned long long* dcount = nullptr;
     unsigned long long counts[2] = {0, 0};
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(dk);
-        (void)hipFree(ds);
-        (void)hipFree(dg);
-        (void)hipFree(dcount);
-        (void)hipFree(uold);
-    };
-    if (hipMalloc((void**)&dk, tkind.size() * sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&ds, tsrc.size() * sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&dg, std::max<size_t>(1, zgrp.size()) * sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&dcount, 2 * sizeof(unsigned long long)) != hipSuccess ||
+    // (the transfer buffers are pool slots: nothing to free)
+    auto cleanup = [&]() { (void)hipStreamSynchronize(ctx->stream); };
+    if (pool_get(ctx, P_TKIND, tkind.size() * sizeof(int), dk) ||
+        pool_get(ctx, P_TSRC, tsrc.size() * sizeof(int), ds) ||
+        pool_get(ctx, P_TGRP, zgrp.size() * sizeof(int), dg) ||
+        pool_get(ctx, P_TCOUNT, 2 * sizeof(unsigned long long), dcount) ||
         hipMemcpyAsync(dk, tkind.data(), tkind.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         hipMemcpyAsync(ds, tsrc.data(), tsrc.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         (G > 0 && hipMemcpyAsync(dg, zgrp.data(), zgrp.size() * sizeof(int), hipMemcpyHostToDevice,
