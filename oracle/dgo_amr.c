@@ -27,8 +27,16 @@
  * of a refined leaf, or a new parent) is troubled if a node has rho < eps or
  * p < eps.  Then all its nodes are scaled toward the reference mean state ubar,
  * u_i <- ubar + theta (u_i - ubar), with the largest theta in [0, 1] that puts
- * every node at rho >= eps and p >= eps (aimed at eps (1 + 2^-40) so that the
- * rounding of the scaled states cannot fall below eps).  One theta per group
+ * every node at rho >= eps and p >= eps.  The density is aimed at
+ * eps (1 + 2^-40), the pressure at eps (1 + 2^-40) + 2^-40 max_i |E_i| over the
+ * group's nodes: p = (gamma-1)(E - |m|^2 / (2 rho)) is only known to a few
+ * units in the last place of E, and where the kinetic energy dwarfs the
+ * pressure (a Mach-2000 jet: E ~ 1e6, p ~ 0.4) a target of eps alone would be
+ * crossed by rounding.  The factor from the pressure quadratic can still miss
+ * where a node's density becomes small (the quadratic's coefficients cancel at
+ * the scale rho_bar E_bar, and p divides that rounding by rho): the scaled
+ * states are therefore checked directly, and if one fails, the factor is
+ * bisected between 0 (the admissible mean) and the closed-form value.  One theta per group
  * keeps the group's total sum_i m_i u_i.  ubar is the LGL mean of the parent
  * before refinement, or of the projected parent after coarsening.  A group
  * whose mean itself is below the thresholds cannot be fixed: theta = 0.
@@ -275,15 +283,28 @@ static void lgl_mean(const dgo_basis* B, const double* u, double* m)
     }
 }
 
-/* largest t in [0, 1] with rho >= et and p >= et along ubar + t (u - ubar) */
-static double zs_theta_node(const double* ub, const double* u, double et, double gamma)
+/* largest t in [0, 1] with rho >= rt and p >= pt along ubar + t (u - ubar) */
+static double zs_theta_node(const double* ub, const double* u, double rt, double pt, double gamma)
 {
     double d[4];
     for (int v = 0; v < 4; ++v) d[v] = u[v] - ub[v];
     double t = 1.0;
-    if (u[0] < et) t = (ub[0] - et) / (ub[0] - u[0]);
-    double tp = dgo_theta_pressure(ub, d, et, gamma);
+    if (u[0] < rt) t = (ub[0] - rt) / (ub[0] - u[0]);
+    double tp = dgo_theta_pressure(ub, d, pt, gamma);
     return tp < t ? tp : t;
+}
+
+/* every node of the group scaled by t toward ubar has rho >= eps and p >= eps */
+static int zs_group_ok(const double* un, int64_t first, int64_t cnt, int NN, const double* ub,
+                       double t, double eps, double gamma)
+{
+    for (int64_t g = first; g < first + cnt; ++g)
+        for (int q = 0; q < NN; ++q) {
+            double w[4];
+            for (int v = 0; v < 4; ++v) w[v] = ub[v] + t * (un[((size_t)g * 4 + v) * NN + q] - ub[v]);
+            if (!(w[0] >= eps) || !(dgo_pressure(w, gamma) >= eps)) return 0;
+        }
+    return 1;
 }
 
 void dgo_zhang_shu(int N, int64_t En, const int8_t* kind, const int64_t* src, const double* uo,
@@ -309,17 +330,20 @@ void dgo_zhang_shu(int N, int64_t En, const int8_t* kind, const int64_t* src, co
             continue;
         }
         int trouble = 0;
+        double emax = 0.0;
         for (int64_t g = first; g < first + cnt; ++g)
             for (int q = 0; q < NN; ++q) {
                 double w[4];
                 for (int v = 0; v < 4; ++v) w[v] = un[((size_t)g * 4 + v) * NN + q];
                 double p = dgo_pressure(w, gamma);
                 if (!(w[0] >= eps) || !(p >= eps)) trouble = 1;
+                if (fabs(w[3]) > emax) emax = fabs(w[3]);
             }
         if (!trouble) continue;
         ++lim;
+        const double pt = et + 0x1p-40 * emax;
         double theta;
-        if (!(ub[0] > et) || !(dgo_pressure(ub, gamma) > et)) {
+        if (!(ub[0] > et) || !(dgo_pressure(ub, gamma) > pt)) {
             theta = 0.0;
             ++bad;
         } else {
@@ -328,9 +352,18 @@ void dgo_zhang_shu(int N, int64_t En, const int8_t* kind, const int64_t* src, co
                 for (int q = 0; q < NN; ++q) {
                     double w[4];
                     for (int v = 0; v < 4; ++v) w[v] = un[((size_t)g * 4 + v) * NN + q];
-                    double t = zs_theta_node(ub, w, et, gamma);
+                    double t = zs_theta_node(ub, w, et, pt, gamma);
                     if (t < theta) theta = t;
                 }
+            if (!zs_group_ok(un, first, cnt, NN, ub, theta, eps, gamma)) {
+                double lo = 0.0, hi = theta;
+                for (int it = 0; it < 60; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (zs_group_ok(un, first, cnt, NN, ub, mid, eps, gamma)) lo = mid;
+                    else hi = mid;
+                }
+                theta = lo;
+            }
         }
         for (int64_t g = first; g < first + cnt; ++g)
             for (int v = 0; v < 4; ++v)

@@ -1971,6 +1971,26 @@ __global__ __launch_bounds__(256) void k_transfer(int E, const int* __restrict__
 // lifts every node to rho, p >= eps (aimed at eps (1 + 2^-40)); one theta per
 // group keeps the group's mass.  counts[0] limited groups, counts[1] groups
 // whose mean is itself below the thresholds (theta = 0).
+// every node of the group scaled by t toward ub has rho >= eps and p >= eps
+// (a wave-wide answer; every lane of the wave calls it)
+template <int N>
+__device__ bool zs_group_ok(const double* __restrict__ unew, const int* R, int cnt, int lane,
+                            const double* ub, double t, double eps, double gamma)
+{
+    constexpr int NN = (N + 1) * (N + 1);
+    int bad = 0;
+    for (int j = lane; j < cnt * NN; j += 64) {
+        const double* ue = unew + (size_t)R[2 + j / NN] * 4 * NN;
+        const int q = j % NN;
+        double w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[v] = ub[v] + t * (ue[v * NN + q] - ub[v]);
+        const double p = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+        if (!(w[0] >= eps) || !(p >= eps)) bad = 1;
+    }
+    return !__any(bad);
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void k_zhang_shu(int G, const int* __restrict__ grp,
                                                    const double* __restrict__ uold,
@@ -1996,6 +2016,7 @@ __global__ __launch_bounds__(256) void k_zhang_shu(int G, const int* __restrict_
         ub[v] = wave_sum(s) * 0.25;
     }
     int trouble = 0;
+    double em = 0.0;  // largest |E| of the group: the rounding scale of its pressures
     for (int j = lane; j < cnt * NN; j += 64) {
         const double* ue = unew + (size_t)R[2 + j / NN] * 4 * NN;
         const int q = j % NN;
@@ -2004,11 +2025,16 @@ __global__ __launch_bounds__(256) void k_zhang_shu(int G, const int* __restrict_
         for (int v = 0; v < 4; ++v) w[v] = ue[v * NN + q];
         const double p = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
         if (!(w[0] >= eps) || !(p >= eps)) trouble = 1;
+        em = fmax(em, fabs(w[3]));
     }
+    const double emax = wave_max(em);
     if (!__any(trouble)) return;
+    // density aimed at eps (1 + 2^-40); pressure in addition 2^-40 max|E| above,
+    // since p = (gamma-1)(E - |m|^2/(2 rho)) is known only to a few ulps of E
     const double et = eps * kMargin;
+    const double pt = et + 0x1p-40 * emax;
     const double pb = (gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
-    const bool fixable = ub[0] > et && pb > et;
+    const bool fixable = ub[0] > et && pb > pt;
     double theta = 0.0;
     if (fixable) {
         double t = 1.0;
@@ -2020,10 +2046,24 @@ __global__ __launch_bounds__(256) void k_zhang_shu(int G, const int* __restrict_
             for (int v = 0; v < 4; ++v) d[v] = ue[v * NN + q] - ub[v];
             double ti = 1.0;
             if (ub[0] + d[0] < et) ti = (ub[0] - et) / (-d[0]);
-            ti = fmin(ti, theta_p(ub, d, et, ig1));
+            ti = fmin(ti, theta_p(ub, d, pt, ig1));
             t = fmin(t, ti);
         }
         theta = wave_min(t);
+        // the quadratic's coefficients cancel at the scale rho_bar E_bar and p
+        // divides that rounding by rho: where a node's density gets small the
+        // factor can miss, so the scaled states are checked directly and, if
+        // one fails, the factor is bisected between 0 (the mean) and theta
+        if (!zs_group_ok<N>(unew, R, cnt, lane, ub, theta, eps, gamma)) {
+            double lo = 0.0, hi = theta;
+#pragma unroll 1
+            for (int it = 0; it < 60; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (zs_group_ok<N>(unew, R, cnt, lane, ub, mid, eps, gamma)) lo = mid;
+                else hi = mid;
+            }
+            theta = lo;
+        }
     }
     for (int j = lane; j < cnt * NN; j += 64) {
         double* ue = unew + (size_t)R[2 + j / NN] * 4 * NN;

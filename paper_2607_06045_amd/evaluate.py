@@ -43,13 +43,15 @@
       starts two levels coarser and the modal indicator adapts it every 5
       steps up to the given level (the exterior states follow every new mesh)
 
-  python -m paper_2607_06045_amd.evaluate jet [--level 8] [--t-end 0.0015]
+  python -m paper_2607_06045_amd.evaluate jet [--level 8] [--t-end 0.0015] [--amr]
       the Mach-2000 jet of Sec. 3.6 on [-0.5, 0.5]^2 (gamma = 5/3, N = 3,
       Chandrashekar volume flux, combined limiting, IDP time step at CFL 0.9,
       uniform at the given level): characteristic inflow on x- with the jet
       state for |y| <= 0.05 and the ambient state elsewhere, characteristic
       x+, periodic in y; reports steps, time, violations and the smallest
-      density and pressure, and how far the jet head has come
+      density and pressure, and how far the jet head has come; with --amr the
+      mesh adapts every 5 steps between level 2 and the given level (the
+      paper: 2..9) and the inflow band is set again on every new mesh
 
 Prints one JSON object.  All inputs are seeded and synthetic.
 """
@@ -546,15 +548,23 @@ def run_dmr(level=4, t_end=0.2, amr=False, every=5):
             "hx": 3.25 / (16 << level)}
 
 
-def run_jet(level=8, t_end=0.0015):
+def run_jet(level=8, t_end=0.0015, amr=False, every=5, base=2):
     import torch
 
     import paper_2607_06045_amd as P
     from workloads.meshes import uniform_mesh
 
     g, N = 5.0 / 3.0, 3
-    n = 1 << level
+    # with AMR: levels base..level of a single root cell (the paper: 2..9), the
+    # modal indicator every `every` steps
+    ctrl = (base, level - 1, 0.01, level, 0.1)
+    n = 1 << (base if amr else level)
     spec = uniform_mesh(n, n, -0.5, -0.5, 1.0, 1.0)
+    if amr:  # one root cell refined uniformly to the base level
+        from workloads.meshes import MeshSpec
+        ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        spec = MeshSpec(np.full(n * n, base, np.int8), ii.ravel().astype(np.int32),
+                        jj.ravel().astype(np.int32), -0.5, -0.5, 1.0, 1.0, 1, 1)
     amb = _cons(0.5, 0.0, 0.0, 0.4127, g)
     jet = _cons(5.0, 800.0, 0.0, 0.4127, g)
     CH = P.BC_CHARACTERISTIC
@@ -563,14 +573,33 @@ def run_jet(level=8, t_end=0.0015):
     s.set_mesh(*spec.args())
     x, y = s.node_coords()
     s.upload(np.ascontiguousarray(np.broadcast_to(amb[None, :, None, None], (s.E, 4, N + 1, N + 1))))
-    bx, by, bf = _boundary_xy(s, x, y)
-    ext = np.tile(amb, (len(bx), 1))
-    ext[(bf == 0) & (np.abs(by) <= 0.05)] = jet
-    s.set_boundary_states(np.full(len(bx), CH, np.int8), ext)
+
+    def inflow():
+        xx, yy = s.node_coords()
+        bx, by, bf = _boundary_xy(s, xx, yy)
+        ext = np.tile(amb, (len(bx), 1))
+        ext[(bf == 0) & (np.abs(by) <= 0.05)] = jet
+        s.set_boundary_states(np.full(len(bx), CH, np.int8), ext)
+
+    if amr:  # resolve the inflow band at the finest level before the first step
+        for _ in range(level - base):
+            lv, ix, iy = s.mesh()
+            h = 1.0 / (1 << lv.astype(np.int64))
+            yc = -0.5 + (iy + 0.5) * h
+            near = (ix == 0) & (np.abs(yc) < 0.05 + h)
+            s.refine_coarsen(np.where(near & (lv < level), 1, 0).astype(np.int8))
+        x, y = s.node_coords()
+        s.upload(np.ascontiguousarray(np.broadcast_to(amb[None, :, None, None], (s.E, 4, N + 1, N + 1))))
+    inflow()
+    leaves = [s.E]
     t, k, viol, inad = 0.0, 0, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while t < t_end * (1 - 1e-14):
+        if amr and k % every == 0:
+            s.refine_coarsen(P.amr_flags(s.indicator(), s.mesh()[0], *ctrl))
+            inflow()
+            leaves.append(s.E)
         dt = min(s.max_dt(0.9), t_end - t)
         st = s.step_dt(dt)
         viol += st["violations"]
@@ -586,7 +615,11 @@ def run_jet(level=8, t_end=0.0015):
     p = (g - 1) * (u[:, 3] - 0.5 * (u[:, 1] ** 2 + u[:, 2] ** 2) / u[:, 0])
     v1 = u[:, 1] / rho
     fast = v1 > 400.0  # jet material
-    return {"mesh": f"uniform {n}x{n}, N={N}", "elements": s.E, "t_end": t_end, "steps": k,
+    x, y = s.node_coords()
+    mesh = (f"adaptive, levels {base}..{level} (finest {1 << level}^2), adapted every {every} steps, N={N}"
+            if amr else f"uniform {n}x{n}, N={N}")
+    return {"mesh": mesh, "elements": s.E, "leaves_min": min(leaves), "leaves_max": max(leaves),
+            "t_end": t_end, "steps": k,
             "wall_s": wall, "ms_per_step": 1e3 * wall / k, "violations": viol,
             "fv_inadmissible": inad, "rho_min": float(rho.min()), "p_min": float(p.min()),
             "rho_max": float(rho.max()), "jet_head_x": float(x[fast].max()) if fast.any() else None,
@@ -608,7 +641,7 @@ def main(argv=None):
     elif a.mode == "dmr":
         out = run_dmr(4 if a.level is None else a.level, 0.2 if a.t_end is None else a.t_end, a.amr)
     elif a.mode == "jet":
-        out = run_jet(8 if a.level is None else a.level, 0.0015 if a.t_end is None else a.t_end)
+        out = run_jet(8 if a.level is None else a.level, 0.0015 if a.t_end is None else a.t_end, a.amr)
     elif a.mode == "mixed":
         out = run_mixed(a.steps or 200)
     elif a.mode == "scale":

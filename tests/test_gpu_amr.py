@@ -171,3 +171,43 @@ def test_adaptation_with_walls(oracle, N):
     err = state_err(s.download(), c)
     print(f"adaptation with walls N={N}: {spec.E} -> {s.E} leaves, NB {s.NB}, step err={err:.2e}", flush=True)
     assert err < TOL and st["violations"] == 0
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_zhang_shu_jet_edges(oracle, N):
+    """Refinement of elements that hold the edge of a hypersonic jet (gamma =
+    5/3, pressure a 1e-7 part of the energy): every pressure stays at or above
+    the threshold 1e-10, and the limited transfer equals the oracle's within
+    1e-10.  The scaling factor solves a pressure quadratic whose coefficients
+    cancel from the energy scale (1e6) down to the pressure (1e-1), so its
+    rounding is amplified by up to E/p ~ 1e7 over the unit roundoff, about
+    1e-9 in theta at worst (measured: 1.4e-12 in the state metric)."""
+    import paper_2607_06045_amd as P
+    g = 5.0 / 3.0
+    spec = to_spec((0.0, 0.0, 1.0, 1.0, 4, 4), {(0, i, j) for i in range(4) for j in range(4)})
+    M = oracle.Mesh(N, *spec.args())
+    x, y, m = M.geometry()
+    rng = np.random.default_rng(11)
+    u = np.empty((spec.E, 4, N + 1, N + 1))
+    for e in range(spec.E):
+        xi = 2 * (x[e] - x[e].min()) / (x[e].max() - x[e].min()) - 1
+        eta = 2 * (y[e] - y[e].min()) / (y[e].max() - y[e].min()) - 1
+        y0, d, ang = rng.uniform(-0.6, 0.6), rng.uniform(0.01, 0.1), rng.uniform(0, np.pi)
+        sgm = 0.5 * (1 + np.tanh((np.cos(ang) * eta + np.sin(ang) * xi - y0) / d))
+        rj, v, p = rng.uniform(2, 10), rng.uniform(200, 1000), rng.uniform(0.1, 1.0)
+        u[e] = states.conservative((0.5 + (rj - 0.5) * sgm)[None], (v * sgm)[None], 0 * sgm[None],
+                                   p + 0 * sgm[None], g)[0]
+    s = P.Solver(N, gamma=g)
+    s.set_mesh(*spec.args())
+    s.upload(u)
+    flags = np.ones(spec.E, np.int8)
+    st = s.refine_coarsen(flags, zs_eps=1e-10)
+    nl, nx, ny, kind, src = oracle.adapt(spec.level, spec.ix, spec.iy, 4, 4, flags)
+    ref, nlim, nbad = oracle.transfer(N, kind, src, u, eps=1e-10, gamma=g)
+    gpu = s.download()
+    pg = (g - 1) * (gpu[:, 3] - 0.5 * (gpu[:, 1] ** 2 + gpu[:, 2] ** 2) / gpu[:, 0])
+    err = state_err(gpu, ref)
+    print(f"jet-edge transfer N={N}: {st}, oracle limited {nlim}, err={err:.2e}, min p {pg.min():.3e}", flush=True)
+    assert nlim == spec.E and st["zs_limited"] == nlim and st["zs_unfixable"] == nbad == 0
+    assert (gpu[:, 0] >= 1e-10).all() and (pg >= 1e-10).all()
+    assert err < 1e-10
