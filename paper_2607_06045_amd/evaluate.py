@@ -22,14 +22,15 @@
       throughput (with and without the adaptation time), element counts,
       sampled bound violations and the L1 density difference of the two runs
 
-  python -m paper_2607_06045_amd.evaluate cfl [--t-end 3.0] [--n 128]
+  python -m paper_2607_06045_amd.evaluate cfl [--t-end 3.0] [--n 128] [--amr]
       the Sedov blast of Sec. 3.4 ([-2, 2]^2, rho = 1, p0 = 1e-5, e = 1 in
       r0 = 0.21875, N = 3) on a uniform n x n mesh (the finest level of the
       paper's adaptive mesh) to t-end, twice: local bounds from bar states
       with the IDP time step at CFL 0.95, and local bounds from the low-order
       solution with the low-order time step at CFL 0.4; reports the number of
       steps, wall time, the smallest and largest dt, mean limiting factors and
-      bound violations of each run
+      bound violations of each run; with --amr a 16 x 16 root grid adapts
+      every 5 steps between 16 and n elements per direction, as in the paper
 
   python -m paper_2607_06045_amd.evaluate dmr [--level 4] [--t-end 0.2] [--amr]
       the double Mach reflection of Sec. 3.6 on [0, 3.25] x [0, 1] (16 x 5
@@ -404,26 +405,40 @@ def run_scale(steps, iters=2000, seeds=2, snaps=3):
             "l1_density_scale": float(np.abs(mp).mean())}
 
 
-def run_cfl(t_end=3.0, n=128):
+def run_cfl(t_end=3.0, n=128, amr=False, every=5):
     import torch
 
     import paper_2607_06045_amd as P
     from workloads import states
     from workloads.meshes import uniform_mesh
 
-    spec = uniform_mesh(n, n, -2.0, -2.0, 4.0, 4.0)
-    out = {"mesh": f"uniform {n}x{n} on [-2,2]^2, N=3", "t_end": t_end}
+    # with AMR: a 16 x 16 root grid adapted by the modal indicator between 16
+    # and n elements per direction (the paper: 16 to 128), every `every` steps
+    top = max(0, int(round(np.log2(n / 16))))
+    ctrl = (0, max(0, top - 1), 0.01, top, 0.1)
+    spec = uniform_mesh(16, 16, -2.0, -2.0, 4.0, 4.0) if amr else uniform_mesh(n, n, -2.0, -2.0, 4.0, 4.0)
+    out = {"mesh": (f"adaptive 16^2..{16 << top}^2 on [-2,2]^2, every {every} steps, N=3" if amr
+                    else f"uniform {n}x{n} on [-2,2]^2, N=3"), "t_end": t_end}
     for name, lim, mode, cfl in (("bar_state_bounds_idp_cfl_0.95", P.LIMIT_LOCAL, P.DT_IDP, 0.95),
                                  ("low_order_bounds_lo_cfl_0.4", P.LIMIT_LOCAL_LOWORDER, P.DT_LOWORDER, 0.4)):
         s = P.Solver(3, limiter=lim, dt_mode=mode)
         s.set_mesh(*spec.args())
         x, y = s.node_coords()
         s.upload(states.sedov_tophat(x, y))
+        if amr:  # refine the initial disc, taking the exact state each time
+            for _ in range(top):
+                s.refine_coarsen(P.amr_flags(s.indicator(), s.mesh()[0], *ctrl))
+                x, y = s.node_coords()
+                s.upload(states.sedov_tophat(x, y))
+        leaves = [s.E]
         t, k, viol, inad = 0.0, 0, 0, 0
         a_vol, a_mort, dts = 0.0, 0.0, []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while t < t_end * (1 - 1e-14):
+            if amr and k > 0 and k % every == 0:
+                s.refine_coarsen(P.amr_flags(s.indicator(), s.mesh()[0], *ctrl))
+                leaves.append(s.E)
             dt = min(s.max_dt(cfl), t_end - t)
             st = s.step_dt(dt)
             t += dt
@@ -439,7 +454,8 @@ def run_cfl(t_end=3.0, n=128):
         wall = time.perf_counter() - t0
         out[name] = {"steps": k, "wall_s": wall, "ms_per_step": 1e3 * wall / k,
                      "dt_min": min(dts), "dt_max": max(dts), "violations": viol,
-                     "fv_inadmissible": inad, "alpha_vol_mean": a_vol / k, "alpha_mort_mean": a_mort / k}
+                     "fv_inadmissible": inad, "alpha_vol_mean": a_vol / k, "alpha_mort_mean": a_mort / k,
+                     "leaves_min": min(leaves), "leaves_max": max(leaves)}
         log(f"{name}: {out[name]}")
     b_, l_ = out["bar_state_bounds_idp_cfl_0.95"], out["low_order_bounds_lo_cfl_0.4"]
     out["step_ratio"] = b_["steps"] / l_["steps"]
@@ -637,7 +653,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=128)
     a = ap.parse_args(argv)
     if a.mode == "cfl":
-        out = run_cfl(3.0 if a.t_end is None else a.t_end, a.n)
+        out = run_cfl(3.0 if a.t_end is None else a.t_end, a.n, a.amr)
     elif a.mode == "dmr":
         out = run_dmr(4 if a.level is None else a.level, 0.2 if a.t_end is None else a.t_end, a.amr)
     elif a.mode == "jet":
