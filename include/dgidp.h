@@ -135,7 +135,9 @@ int dgidp_synchronize(dgidp_ctx* ctx);
  * e covers cell (ix[e], iy[e]) of the (nx0 2^level[e]) x (ny0 2^level[e]) grid.
  * Neighbours across a face may differ by one level (Sec. 2.2: 2-to-1
  * nonconforming interfaces).  Host arrays, copied.  Replaces any previous mesh
- * and state.  Errors: DGIDP_E_MESH_GAP_OR_OVERLAP (leaves do not tile the
+ * and state.  The device buffers of a mesh are kept by the context and reused
+ * by later meshes and adaptations (grown when a mesh needs more); only
+ * dgidp_destroy releases them.  Errors: DGIDP_E_MESH_GAP_OR_OVERLAP (leaves do not tile the
  * domain), DGIDP_E_MESH_NOT_BALANCED, DGIDP_E_INVALID_ARG. */
 int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t n_leaves, const int8_t* level, const int32_t* ix,
                       const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
