@@ -75,3 +75,36 @@ def test_density_wave_local_table(oracle):
         assert viol == 0
         errs.append(err[0])
     assert errs == sorted(errs, reverse=True)
+
+
+def test_isentropic_flow_table(oracle):
+    """Table ConvergenceTestIsentropicFlow (Sec. 3.2), N = 3, levels 2 to 4: the
+    near-vacuum flow (gamma = 3) to t = 0.1 with the low-order time step at CFL
+    0.5 and positivity limiting, active in the volume and at the mortars; L2
+    errors within 2.5% of the printed ones (the oracle's own tolerance), zero
+    bound violations, admissible low-order states."""
+    import paper_2607_06045_amd as P
+    from test_oracle_scheme import _isentropic_exact
+    g, s2 = 3.0, np.sqrt(2.0)
+    tab = T["isentropic_flow"]["3"]
+    for lev in (2, 3, 4):
+        ms = refined_box_mesh(2 ** lev, (-1 / s2, -1 / s2), (0.0, 1 / s2), -s2, -s2, 2 * s2)
+        s = P.Solver(3, gamma=g, dt_mode=P.DT_LOWORDER)
+        s.set_mesh(*ms.args())
+        M = oracle.Mesh(3, *ms.args())
+        x, y, m = M.geometry()
+        s.upload(states.isentropic_flow(x, y, gamma=g))
+        t, viol, inad, thmin = 0.0, 0, 0, 1.0
+        while t < 0.1 - 1e-14:
+            dt = min(s.max_dt(0.5), 0.1 - t)
+            st = s.step_dt(dt)
+            t += dt
+            viol += st["violations"]
+            inad += st["fv_inadmissible"]
+            thmin = min(thmin, st["theta_vol_min"])
+        err = _l2_errors(oracle, M, s.download(), lambda xx, yy: _isentropic_exact(xx, yy, 0.1), 8.0)
+        ref = np.array(tab[str(lev)])
+        print(f"isentropic level {lev}: {err} paper {ref}", flush=True)
+        assert np.all(np.abs(err - ref) <= 0.025 * ref), (lev, err, ref)
+        assert viol == 0 and inad == 0
+        assert thmin < 0.01
