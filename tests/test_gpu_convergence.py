@@ -6,7 +6,8 @@ meshes, L2 errors of (rho, rho v1, rho v2, rho e) against the printed values.
   of Table ConvergenceTest_polydeg4, N = 4), every printed level: within 0.5% (the
   tables print three significant digits), the exact variable ratios
   0.1 : 0.2 : 0.025, no limiting at all.
-- Local limiting (Table ConvergenceTestLocalLimiting, N = 3), every printed level:
+- Local limiting (Table ConvergenceTestLocalLimiting, N = 3, and the lower part of
+  Table ConvergenceTest_polydeg4, N = 4), every printed level:
   the tolerances of the oracle's own test (its errors lie 14%, 7%, 2% and 0.5%
   below the printed ones at levels 2 to 5; 1% at levels 6 and 7, which only the
   GPU runs), and no bound violations."""
@@ -61,15 +62,20 @@ def test_density_wave_positivity_table(oracle, N):
         assert abs(got - eoc[str(levels[i])]) < 0.01, (levels[i], got)
 
 
-def test_density_wave_local_table(oracle):
+LOCAL_TOL = {3: {2: 0.16, 3: 0.09, 4: 0.03, 5: 0.01, 6: 0.01, 7: 0.01},
+             4: {2: 0.16, 3: 0.09, 4: 0.03, 5: 0.01, 6: 0.01, 7: 0.01}}
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_density_wave_local_table(oracle, N):
     import paper_2607_06045_amd as P
-    tab = T["density_wave_local"]["3"]
-    tol = {2: 0.16, 3: 0.09, 4: 0.03, 5: 0.01, 6: 0.01, 7: 0.01}
+    tab = T["density_wave_local"][str(N)]
+    tol = LOCAL_TOL[N]
     errs = []
     for lev in sorted(int(k) for k in tab):
-        err, viol, _ = _run(oracle, 3, lev, P.LIMIT_LOCAL)
+        err, viol, _ = _run(oracle, N, lev, P.LIMIT_LOCAL)
         ref = np.array(tab[str(lev)])
-        print(f"local level {lev}: {err} paper {ref}", flush=True)
+        print(f"local N={N} level {lev}: {err} paper {ref} rel {err[0] / ref[0] - 1:+.4f}", flush=True)
         assert np.all(np.abs(err - ref) <= tol[lev] * ref), (lev, err, ref)
         assert np.allclose(err[1:] / err[0], [0.1, 0.2, 0.025], rtol=1e-6)
         assert viol == 0
