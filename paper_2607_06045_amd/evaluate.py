@@ -44,7 +44,7 @@
       starts two levels coarser and the modal indicator adapts it every 5
       steps up to the given level (the exterior states follow every new mesh)
 
-  python -m paper_2607_06045_amd.evaluate jet [--level 8] [--t-end 0.0015] [--amr]
+  python -m paper_2607_06045_amd.evaluate jet [--level 8] [--t-end 0.0015] [--amr] [--mixed]
       the Mach-2000 jet of Sec. 3.6 on [-0.5, 0.5]^2 (gamma = 5/3, N = 3,
       Chandrashekar volume flux, combined limiting, IDP time step at CFL 0.9,
       uniform at the given level): characteristic inflow on x- with the jet
@@ -564,7 +564,7 @@ def run_dmr(level=4, t_end=0.2, amr=False, every=5):
             "hx": 3.25 / (16 << level)}
 
 
-def run_jet(level=8, t_end=0.0015, amr=False, every=5, base=2):
+def run_jet(level=8, t_end=0.0015, amr=False, every=5, base=2, mixed=False):
     import torch
 
     import paper_2607_06045_amd as P
@@ -585,6 +585,7 @@ def run_jet(level=8, t_end=0.0015, amr=False, every=5, base=2):
     jet = _cons(5.0, 800.0, 0.0, 0.4127, g)
     CH = P.BC_CHARACTERISTIC
     s = P.Solver(N, gamma=g, limiter=P.LIMIT_COMBINED, volume_flux=P.FLUX_CHANDRASHEKAR,
+                 precision=P.MIXED if mixed else P.FP64,
                  bc=[CH, CH, P.BC_PERIODIC, P.BC_PERIODIC], ext=np.stack([amb, amb, amb, amb]))
     s.set_mesh(*spec.args())
     x, y = s.node_coords()
@@ -647,6 +648,7 @@ def main(argv=None):
     ap.add_argument("mode", choices=["mixed", "learned", "scale", "cfl", "dmr", "jet"])
     ap.add_argument("--level", type=int, default=None)
     ap.add_argument("--amr", action="store_true")
+    ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--t-end", type=float, default=None)
@@ -657,7 +659,8 @@ def main(argv=None):
     elif a.mode == "dmr":
         out = run_dmr(4 if a.level is None else a.level, 0.2 if a.t_end is None else a.t_end, a.amr)
     elif a.mode == "jet":
-        out = run_jet(8 if a.level is None else a.level, 0.0015 if a.t_end is None else a.t_end, a.amr)
+        out = run_jet(8 if a.level is None else a.level, 0.0015 if a.t_end is None else a.t_end, a.amr,
+                      mixed=a.mixed)
     elif a.mode == "mixed":
         out = run_mixed(a.steps or 200)
     elif a.mode == "scale":
