@@ -117,3 +117,29 @@ def test_mesh_validate_degenerate_meshes(oracle):
     for spec in cases:
         M, _ = P.validate_mesh(3, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
         assert M == oracle.Mesh(3, *spec.args()).M
+
+
+def test_binding_constants_match_the_header():
+    """Every enumerator of include/dgidp.h that the Python binding exposes has
+    the header's value (limiter modes, boundary conditions, fluxes, precision,
+    time-step rules, residual kinds, indicators)."""
+    import re
+    import paper_2607_06045_amd as P
+    from paper_2607_06045_amd import _lib
+    hdr = open(os.path.join(ROOT, "include", "dgidp.h")).read()
+    enums = {}
+    for body in re.findall(r"enum\s*\{([^}]*)\}", hdr):
+        for name, val in re.findall(r"(DGIDP_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            enums[name] = int(val)
+    checked = 0
+    for name, val in enums.items():
+        short = name[len("DGIDP_"):]
+        for mod in (P, _lib):
+            if hasattr(mod, short):
+                assert getattr(mod, short) == val, (name, getattr(mod, short), val)
+                checked += 1
+                break
+    assert checked >= 18, checked
+    for short in ("LIMIT_LOCAL_LOWORDER", "BC_WALL", "BC_CHARACTERISTIC", "BC_OUTFLOW",
+                  "FLUX_CHANDRASHEKAR", "LIMIT_COMBINED"):
+        assert getattr(P, short) == enums["DGIDP_" + short]
