@@ -149,6 +149,14 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t n_leaves, const int8_t* level, con
 int dgidp_mesh_validate(int N, int64_t n_leaves, const int8_t* level, const int32_t* ix,
                         const int32_t* iy, int nx0, int ny0, int64_t* n_mortars,
                         int64_t* n_two_mortar_nodes, char* msg, int msglen);
+/* The same with the side conditions bc[4] of dgidp_set_boundaries (NULL: all
+ * periodic): faces on non-periodic sides need no partner across the domain
+ * boundary.  Also returns the number of boundary nodes (n_boundary_nodes, may
+ * be NULL).  Errors as dgidp_mesh_validate, and DGIDP_E_INVALID_ARG for an
+ * unknown condition or opposite sides that disagree on periodicity. */
+int dgidp_mesh_validate_bc(int N, int64_t n_leaves, const int8_t* level, const int32_t* ix,
+                           const int32_t* iy, int nx0, int ny0, const int* bc, int64_t* n_mortars,
+                           int64_t* n_boundary_nodes, char* msg, int msglen);
 /* Boundary conditions of the domain sides, in the order x-, x+, y-, y+ (the
  * double Mach reflection and the jet of Sec. 3.6 use slip walls and
  * characteristic inflow/outflow).  bc[4]: DGIDP_BC_PERIODIC, DGIDP_BC_WALL

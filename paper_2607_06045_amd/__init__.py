@@ -7,4 +7,4 @@ from ._lib import (FP64, MIXED, DT_IDP, DT_LOWORDER, LIMIT_NONE, LIMIT_POSITIVIT
                    FLUX_RANOCHA, FLUX_CHANDRASHEKAR,  # noqa: F401
                    BC_PERIODIC, BC_WALL, BC_CHARACTERISTIC, BC_OUTFLOW,
                    RHS_HIGH, RHS_LOW, DgidpError, Solver, host_tables, exported_symbols,
-                   validate_mesh, adapt_leaves, amr_flags, IND_HENNEMANN, IND_MLP, MLP_NPARAM)
+                   validate_mesh, validate_mesh_bc, adapt_leaves, amr_flags, IND_HENNEMANN, IND_MLP, MLP_NPARAM)

@@ -86,6 +86,9 @@ _SIGS = {
     "dgidp_mesh_validate": (_i, [_i, ctypes.c_int64, _vp, _vp, _vp, _i, _i,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.c_char_p, _i]),
+    "dgidp_mesh_validate_bc": (_i, [_i, ctypes.c_int64, _vp, _vp, _vp, _i, _i, _vp,
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.c_char_p, _i]),
     "dgidp_adapt_leaves": (_i, [ctypes.c_int64, _vp, _vp, _vp, _i, _i, _vp, ctypes.c_int64,
                                 _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "dgidp_refine_coarsen": (_i, [_vp, _vp, _d, ctypes.POINTER(ctypes.c_int64),
@@ -147,6 +150,25 @@ def validate_mesh(N, level, ix, iy, nx0, ny0):
     if rc:
         raise DgidpError(f"dgidp_mesh_validate: {ERRORS.get(rc, rc)}: {msg.value.decode()}")
     return M.value, T2.value
+
+
+def validate_mesh_bc(N, level, ix, iy, nx0, ny0, bc=None):
+    """Host-only mesh check with side conditions bc[4] (None: all periodic):
+    returns (n_mortars, n_boundary_nodes) or raises."""
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    b = None if bc is None else np.ascontiguousarray(bc, dtype=np.int32)
+    if b is not None and b.shape != (4,):
+        raise DgidpError("bc must hold four conditions (x-, x+, y-, y+)")
+    M, NB = ctypes.c_int64(), ctypes.c_int64()
+    msg = ctypes.create_string_buffer(256)
+    rc = _lib.dgidp_mesh_validate_bc(N, len(level), level.ctypes.data, ix.ctypes.data,
+                                     iy.ctypes.data, nx0, ny0, None if b is None else b.ctypes.data,
+                                     ctypes.byref(M), ctypes.byref(NB), msg, 256)
+    if rc:
+        raise DgidpError(f"dgidp_mesh_validate_bc: {ERRORS.get(rc, rc)}: {msg.value.decode()}")
+    return M.value, NB.value
 
 
 def adapt_leaves(level, ix, iy, nx0, ny0, flags):

@@ -690,6 +690,33 @@ int dgidp_set_boundary_states(dgidp_ctx* ctx, const int8_t* kind, const double* 
     return 0;
 }
 
+int dgidp_mesh_validate_bc(int N, int64_t n_leaves, const int8_t* level, const int32_t* ix,
+                           const int32_t* iy, int nx0, int ny0, const int* bc, int64_t* n_mortars,
+                           int64_t* n_boundary_nodes, char* msg, int msglen)
+{
+    std::string err;
+    int code = 0;
+    if (bc) {
+        for (int f = 0; f < 4 && !code; ++f)
+            if (bc[f] < DGIDP_BC_PERIODIC || bc[f] > DGIDP_BC_OUTFLOW) {
+                err = "unknown boundary condition";
+                code = DGIDP_E_INVALID_ARG;
+            }
+        if (!code && ((bc[0] == DGIDP_BC_PERIODIC) != (bc[1] == DGIDP_BC_PERIODIC) ||
+                      (bc[2] == DGIDP_BC_PERIODIC) != (bc[3] == DGIDP_BC_PERIODIC))) {
+            err = "opposite sides must both be periodic or both not";
+            code = DGIDP_E_INVALID_ARG;
+        }
+    }
+    HostMesh hm;
+    if (!code) code = build_host_mesh(N, n_leaves, level, ix, iy, nx0, ny0, bc, hm, err);
+    if (msg && msglen > 0) std::snprintf(msg, (size_t)msglen, "%s", err.c_str());
+    if (code) return code;
+    if (n_mortars) *n_mortars = hm.M;
+    if (n_boundary_nodes) *n_boundary_nodes = hm.NBF * (N + 1);
+    return 0;
+}
+
 int dgidp_mesh_info(dgidp_ctx* ctx, int64_t* n_elements, int64_t* n_mortars)
 {
     if (!ctx) return DGIDP_E_INVALID_ARG;

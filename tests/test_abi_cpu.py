@@ -119,6 +119,37 @@ def test_mesh_validate_degenerate_meshes(oracle):
         assert M == oracle.Mesh(3, *spec.args()).M
 
 
+def test_mesh_validate_with_boundaries(oracle):
+    """The side conditions lift the 2:1 condition across a non-periodic side: a
+    2 x 1 root grid refined twice at x = 0 and not at all at x = 1 is unbalanced
+    across the periodic wrap and valid between walls; the library agrees with
+    the oracle on mortars and boundary nodes.  Conditions that disagree on
+    periodicity across the domain, or are unknown, are rejected."""
+    import paper_2607_06045_amd as P
+    from workloads.meshes import random_mesh, to_spec
+    leaves = {(2, i, j) for i in (0, 1) for j in range(4)} | {(1, 1, 0), (1, 1, 1), (0, 1, 0)}
+    spec = to_spec((0.0, 0.0, 2.0, 1.0, 2, 1), leaves)
+    a = (3, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0)
+    with pytest.raises(P.DgidpError, match="NOT_BALANCED"):
+        P.validate_mesh(*a)
+    with pytest.raises(P.DgidpError, match="NOT_BALANCED"):
+        P.validate_mesh_bc(*a, bc=[0, 0, 0, 0])
+    for bc in ([1, 1, 0, 0], [2, 3, 0, 0], [1, 1, 1, 1]):
+        nm, nb = P.validate_mesh_bc(*a, bc=bc)
+        M = oracle.Mesh(3, *spec.args(), bc=bc)
+        assert (nm, nb) == (M.M, M.NB)
+    assert P.validate_mesh_bc(*a, bc=[1, 1, 0, 0]) == (3, 20)
+    assert P.validate_mesh_bc(*a, bc=[1, 1, 1, 1])[1] == 4 * (4 + 1 + 4 + 4)
+    for bc in ([1, 0, 0, 0], [0, 0, 3, 0], [5, 5, 0, 0], [-1, -1, 0, 0]):
+        with pytest.raises(P.DgidpError, match="INVALID_ARG"):
+            P.validate_mesh_bc(*a, bc=bc)
+    with pytest.raises(P.DgidpError):
+        P.validate_mesh_bc(*a, bc=[1, 1, 0])
+    r = random_mesh(2, 4, 3, 0.4)
+    b = (3, r.level, r.ix, r.iy, r.nx0, r.ny0)
+    assert P.validate_mesh_bc(*b) == (P.validate_mesh(*b)[0], 0)
+
+
 def test_binding_constants_match_the_header():
     """Every enumerator of include/dgidp.h that the Python binding exposes has
     the header's value (limiter modes, boundary conditions, fluxes, precision,
