@@ -150,6 +150,29 @@ def test_mesh_validate_with_boundaries(oracle):
     assert P.validate_mesh_bc(*b) == (P.validate_mesh(*b)[0], 0)
 
 
+def test_null_handle_is_rejected_by_every_entry_point():
+    """Every entry point of include/dgidp.h that takes a context returns
+    DGIDP_E_INVALID_ARG for a NULL context (and NULL or zero for the rest)
+    before any device call; dgidp_destroy(NULL) is a no-op and dgidp_create
+    rejects NULL parameters.  Runs without a GPU."""
+    import ctypes
+    from paper_2607_06045_amd import _lib
+    inval = -1
+    assert _lib.ERRORS[inval] == "DGIDP_E_INVALID_ARG"
+    hdr = open(os.path.join(ROOT, "include", "dgidp.h")).read()
+    names = sorted(set(re.findall(r"^int (dgidp_\w+)\(dgidp_ctx\* ctx", hdr, re.M)))
+    assert len(names) >= 26
+    ints = (ctypes.c_int, ctypes.c_int64, ctypes.c_int8, ctypes.c_int32, ctypes.c_uint64)
+    for name in names:
+        fn = getattr(_lib._lib, name)
+        args = [0 if t in ints else 0.0 if t in (ctypes.c_double, ctypes.c_float) else None
+                for t in fn.argtypes]
+        assert fn(*args) == inval, name
+    _lib._lib.dgidp_destroy(None)
+    out = ctypes.c_void_p(7)
+    assert _lib._lib.dgidp_create(None, None, ctypes.byref(out)) == inval
+
+
 def test_binding_constants_match_the_header():
     """Every enumerator of include/dgidp.h that the Python binding exposes has
     the header's value (limiter modes, boundary conditions, fluxes, precision,
