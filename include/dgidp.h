@@ -137,8 +137,13 @@ int dgidp_synchronize(dgidp_ctx* ctx);
  * nonconforming interfaces).  Host arrays, copied.  Replaces any previous mesh
  * and state.  The device buffers of a mesh are kept by the context and reused
  * by later meshes and adaptations (grown when a mesh needs more); only
- * dgidp_destroy releases them.  Errors: DGIDP_E_MESH_GAP_OR_OVERLAP (leaves do not tile the
- * domain), DGIDP_E_MESH_NOT_BALANCED, DGIDP_E_INVALID_ARG. */
+ * dgidp_destroy releases them.  Limits: level[e] in 0..20, and 1 <= n_leaves <=
+ * 2^30 / (4 (N+1)^2) (16,777,216 at N = 3, 10,737,418 at N = 4), since the
+ * kernels index state values with 32-bit integers.  Errors:
+ * DGIDP_E_MESH_GAP_OR_OVERLAP (leaves do not tile the domain, or a leaf lies
+ * outside the root grid or above level 20), DGIDP_E_MESH_NOT_BALANCED,
+ * DGIDP_E_INVALID_ARG (n_leaves outside its limits, NULL arrays, an empty root
+ * grid). */
 int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t n_leaves, const int8_t* level, const int32_t* ix,
                       const int32_t* iy, double x0, double y0, double Lx, double Ly, int nx0,
                       int ny0);

@@ -104,6 +104,20 @@ def test_mesh_validate_errors():
         P.validate_mesh(3, lv, ix, iy, 0, 2)
 
 
+def test_mesh_validate_size_limits():
+    """The leaf-count limit of the header (32-bit state indices): one leaf past
+    2^30 / (4 (N+1)^2) is rejected before the leaves are read; a leaf above
+    level 20 is outside the supported grid."""
+    import paper_2607_06045_amd as P
+    for N in (3, 4):
+        E = (1 << 30) // (4 * (N + 1) ** 2) + 1
+        lv, z = np.zeros(E, np.int8), np.zeros(E, np.int32)
+        with pytest.raises(P.DgidpError, match="INVALID_ARG"):
+            P.validate_mesh(N, lv, z, z, 1, 1)
+    with pytest.raises(P.DgidpError, match="GAP_OR_OVERLAP"):
+        P.validate_mesh(3, np.array([21], np.int8), np.zeros(1, np.int32), np.zeros(1, np.int32), 1, 1)
+
+
 def test_mesh_validate_degenerate_meshes(oracle):
     """One leaf that is its own neighbour on every face (periodic 1 x 1 root),
     a 1 x 2 root, and a refined 1 x 1 root whose mortars wrap around: valid,
