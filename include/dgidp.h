@@ -1,7 +1,8 @@
 /*
  * dgidp: MI355X (gfx950) library for the invariant-domain-preserving (IDP)
  * limited LGL-DGSEM of the 2D compressible Euler equations on 2:1-balanced
- * periodic Cartesian quadtrees (Bolm, Rueda-Ramirez, Kuzmin, Gassner:
+ * Cartesian quadtrees, periodic or with slip-wall, characteristic or outflow
+ * sides (Bolm, Rueda-Ramirez, Kuzmin, Gassner:
  * "Invariant-domain-preserving limiting with Adaptive Mesh Refinement for
  * Legendre-Gauss-Lobatto Discontinuous Galerkin Spectral Element Methods").
  *
@@ -18,6 +19,11 @@
  *    buffers it allocates.
  *  - Asynchrony: entry points that take no host output pointer only enqueue
  *    work on the context's stream; those that return host values synchronise.
+ *  - Host threads: a context is not thread-safe; the caller serialises the
+ *    calls on one context.  Distinct contexts own distinct buffers and may be
+ *    driven from different threads; they share only the read-only basis
+ *    tables in device constant memory, which dgidp_create writes with the
+ *    same values for a given N.
  */
 #ifndef DGIDP_H
 #define DGIDP_H
