@@ -28,6 +28,8 @@ def pair(oracle, spec, N, bc, ext=None, limiter=None, **kw):
     M = oracle.Mesh(N, *spec.args(), bc=bc, ext=ext)
     assert (s.E, s.M, s.NB) == (M.E, M.M, M.NB)
     assert np.array_equal(s.boundary_nodes(), M.boundary_nodes())
+    # the host-only check agrees with the uploaded mesh
+    assert P.validate_mesh_bc(N, spec.level, spec.ix, spec.iy, spec.nx0, spec.ny0, bc=bc) == (s.M, s.NB)
     return s, M
 
 
