@@ -260,3 +260,27 @@ def test_full_size_quadrants247k_n4(oracle):
     assert err < TOL
     assert st["violations"] == 0
     assert abs(st["dt"] - sc["dt"]) <= 1e-14 * sc["dt"]
+
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_state_upload_rejects_inadmissible(on_device):
+    """Upload from host memory and from a device tensor: a NaN density, an
+    infinite energy and a negative pressure are each rejected with the first bad
+    node (element, node) in the message, and a rejected upload leaves the
+    previous state in place."""
+    import torch
+    import paper_2607_06045_amd as P
+    spec = workload_mesh("vortex304")
+    s = P.Solver(3)
+    s.set_mesh(*spec.args())
+    x, y = s.node_coords()
+    good = states.vortex(x, y)
+    s.upload(good)
+    for v, j, i, val in ((0, 1, 2, np.nan), (3, 0, 3, np.inf), (3, 2, 1, 0.0)):
+        u = good.copy()
+        u[40, v, j, i] = val
+        u[90, 0, 0, 0] = -1.0  # a later bad node: the first one is reported
+        arg = torch.from_numpy(u).cuda() if on_device else u
+        with pytest.raises(P.DgidpError, match=f"INADMISSIBLE.*element 40 node {j * 4 + i}"):
+            s.upload(arg)
+        assert np.array_equal(s.download(), good)
