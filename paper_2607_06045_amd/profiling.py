@@ -5,12 +5,19 @@
       per-kernel call count and mean / min / max duration of a --kernel-trace
       --stats run, as a short text table
 
-  python -m paper_2607_06045_amd.profiling traffic --fetch DIR --write DIR \\
-      --copy-fetch DIR --copy-write DIR --copy-mib 512 --kernel k_stage \\
-      --dofs D --algorithmic-bytes-per-node B --out profiles/traffic_....json
-      HBM bytes per launch of one kernel from a FETCH_SIZE pass and a WRITE_SIZE
-      pass (KiB per dispatch), each scaled by the ratio of known bytes to what
-      the same counter reads for a plain device copy of --copy-mib MiB
+  python -m paper_2607_06045_amd.profiling counters --fetch DIR --write DIR \\
+      --copy-fetch DIR --copy-write DIR --copy-mib 512 --sq DIR [DIR ...] \\
+      --kernel k_stage --dofs D --algorithmic-bytes-per-node B \\
+      --out profiles/counters_....json
+      per launch of one kernel: HBM bytes from a FETCH_SIZE pass and a
+      WRITE_SIZE pass (KiB per dispatch), each scaled by the ratio of known
+      bytes to what the same counter reads for a plain device copy of
+      --copy-mib MiB; and the instruction counters (SQ_INSTS_*) of the --sq
+      passes, as wave instructions per launch and lane instructions per node
+
+  python -m paper_2607_06045_amd.profiling copy --mib 512
+      a plain device-to-device copy of known size, the calibration workload of
+      the FETCH_SIZE / WRITE_SIZE counters
 """
 import argparse
 import csv
@@ -48,7 +55,13 @@ def _mean_counter(rows, name_part, counter):
     return sum(vals) / len(vals), len(vals)
 
 
-def traffic(a):
+def _mean_counter_opt(rows, name_part, counter):
+    vals = [float(r["Counter_Value"]) for r in rows
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def counters(a):
     f_kib, nf = _mean_counter(_counter_rows(a.fetch), a.kernel, "FETCH_SIZE")
     w_kib, nw = _mean_counter(_counter_rows(a.write), a.kernel, "WRITE_SIZE")
     cf_kib, _ = _mean_counter(_counter_rows(a.copy_fetch), a.copy_kernel, "FETCH_SIZE")
@@ -65,14 +78,44 @@ def traffic(a):
         "copy_calibration": {"mib": a.copy_mib, "fetch_kib_raw": cf_kib, "write_kib_raw": cw_kib,
                              "fetch_factor": ff, "write_factor": wf},
         "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
-        "bytes_per_launch": fetch_b + write_b,
+        "hbm_bytes_per_launch": fetch_b + write_b,
         "algorithmic_bytes_per_launch": alg,
-        "kernel_source_sha256_16": kernel_source_hash(),
-        "command": a.command,
     }
+    # instruction counters: wave instructions per dispatch of the kernel
+    sq = {}
+    for d in a.sq or []:
+        rows = _counter_rows(d)
+        for c in sorted({r["Counter_Name"] for r in rows}):
+            v, k = _mean_counter_opt(rows, a.kernel, c)
+            if v is not None:
+                sq[c] = v
+    if sq:
+        out["sq_per_launch"] = sq
+        vw = sq.get("SQ_INSTS_VALU")
+        if vw:
+            out["valu_wave_insts_per_launch"] = vw
+            if a.dofs:
+                out["valu_lane_insts_per_node"] = vw * 64.0 / a.dofs
+            f64 = sum(sq.get(k, 0.0) for k in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                                               "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64"))
+            if f64:
+                out["valu_f64_share"] = f64 / vw
+    out["kernel_source_sha256_16"] = kernel_source_hash()
+    out["command"] = a.command
     with open(a.out, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+
+
+def copy(a):
+    import torch
+    n = a.mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(a.reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copied {a.mib} MiB x {a.reps}", flush=True)
 
 
 def timed_region(a):
@@ -119,9 +162,10 @@ def stats(a):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
-    t = sub.add_parser("traffic")
+    t = sub.add_parser("counters")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "out"):
         t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--sq", nargs="*", default=[])
     t.add_argument("--copy-mib", type=float, default=512)
     t.add_argument("--copy-kernel", default="copyBuffer")
     t.add_argument("--kernel", default="k_stage")
@@ -138,11 +182,11 @@ def main(argv=None):
     s.add_argument("--kernel", default="")
     s.add_argument("--tail", type=int, default=0)
     s.add_argument("--bench-log", default="")
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=512)
+    c.add_argument("--reps", type=int, default=5)
     a = ap.parse_args(argv)
-    if a.mode == "traffic":
-        traffic(a)
-    else:
-        stats(a)
+    {"counters": counters, "stats": stats, "copy": copy}[a.mode](a)
 
 
 if __name__ == "__main__":
