@@ -96,6 +96,8 @@ def lib():
         L.orc_shock_indicator.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, _D]
         L.orc_fe_step_ind.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_fe_step_detail.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D]
         L.orc_set_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -360,6 +362,25 @@ class Mesh:
         d = _stats(st)
         d["rc"] = rc
         return out, d
+
+    def fe_step_detail(self, u, dt, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
+        """One limited forward-Euler step with its intermediate results: returns
+        (new state, stats, u_vol, dslot, theta) with u_vol the state after the
+        volume limiter, dslot [M, 3n, 4] the high-order minus low-order surface
+        flux terms of each mortar node (large face, lower small face, upper
+        small face, each by face position) and theta [M] the mortar factors."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        out = np.zeros_like(u)
+        uvol = np.zeros_like(u)
+        M = max(self.M, 1)
+        dslot = np.zeros((M, 3 * self.n, 4))
+        theta = np.zeros(M)
+        st = np.zeros(len(STAT_KEYS))
+        rc = lib().orc_fe_step_detail(self._h, _ptr(u), dt, gamma, beta, limiter, _ptr(out), _ptr(st),
+                                      _ptr(uvol), _ptr(dslot), _ptr(theta))
+        d = _stats(st)
+        d["rc"] = rc
+        return out, d, uvol, dslot[: self.M], theta[: self.M]
 
     def ssprk3(self, u, cfl, mode=DT_IDP, gamma=1.4, beta=0.1, limiter=LIM_POSITIVITY):
         """One SSP-RK3 step; returns (new state, stats)."""

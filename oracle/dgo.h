@@ -141,6 +141,15 @@ void dgo_lowsol_bounds(const dgo_mesh* m, const double* ufv, double gamma, doubl
 void dgo_shock_indicator(const dgo_mesh* m, const double* u, double gamma, double* ind);
 int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
                     int limiter, const double* ind, double* out, dgo_stats* st);
+/* the same step, exposing its intermediate results (each may be NULL): uvol
+   [E][4][n][n] the state after the volume limiter, before the mortar
+   correction; dslot [M][3n][4] per mortar node the difference of the high-order
+   and the low-order surface flux terms (Sec. 2.3, in the units of m_i du/dt,
+   slots in the order large face, lower small face, upper small face, each by
+   face position); theta [M] the mortar factors */
+int dgo_fe_step_detail(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
+                       int limiter, const double* ind, double* out, dgo_stats* st, double* uvol,
+                       double* dslot, double* theta);
 int dgo_ssprk3_dt(const dgo_mesh* m, double* u, double dt, double gamma, double beta, int limiter,
                   dgo_stats* st);
 

@@ -279,6 +279,15 @@ int orc_fe_step_ind(void* h, const double* u, double dt, double gamma, double be
     return rc;
 }
 
+int orc_fe_step_detail(void* h, const double* u, double dt, double gamma, double beta, int limiter,
+                       double* out, double* stats, double* uvol, double* dslot, double* theta)
+{
+    dgo_stats s;
+    int rc = dgo_fe_step_detail((dgo_mesh*)h, u, dt, gamma, beta, limiter, 0, out, &s, uvol, dslot, theta);
+    pack(&s, stats);
+    return rc;
+}
+
 int orc_set_threads(int t)
 {
 #ifdef _OPENMP

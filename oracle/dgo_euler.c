@@ -121,8 +121,8 @@ void dgo_flux_volume(int kind, const double* uL, const double* uR, int dir, doub
     else dgo_flux_ranocha(uL, uR, dir, gamma, f);
 }
 
-/* Ghost state of a boundary node; the double Mach reflection and the jet of
-   Sec. 3.6 use slip walls and characteristic inflow/outflow.  Face f is 0 x-,
+/* Ghost state of a boundary node; the double Mach reflection (Sec. 3.5)
+   and the jet (Sec. 3.6) use slip walls and characteristic inflow/outflow.  Face f is 0 x-,
    1 x+, 2 y-, 3 y+; the outward normal is the axis of direction f / 2, negated
    on the even faces.
    - slip wall: the interior state with its normal momentum reversed (the LLF

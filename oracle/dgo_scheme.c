@@ -845,6 +845,13 @@ int dgo_fe_step(const dgo_mesh* m, const double* u, double dt, double gamma, dou
 int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
                     int limiter, const double* ind_in, double* out, dgo_stats* st)
 {
+    return dgo_fe_step_detail(m, u, dt, gamma, beta, limiter, ind_in, out, st, 0, 0, 0);
+}
+
+int dgo_fe_step_detail(const dgo_mesh* m, const double* u, double dt, double gamma, double beta,
+                       int limiter, const double* ind_in, double* out, dgo_stats* st, double* uvol_out,
+                       double* dslot_out, double* theta_out)
+{
     const dgo_basis* B = &m->B;
     int N = B->N, n = B->n;
     int64_t E = m->E, nn = n * n;
@@ -856,6 +863,8 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
     double* HO = (double*)calloc(ns > 0 ? ns : 1, 8);
     double* LO = (double*)calloc(ns > 0 ? ns : 1, 8);
     compute_slots(m, u, gamma, HO, LO);
+    if (dslot_out)
+        for (int64_t i = 0; i < ns; ++i) dslot_out[i] = HO[i] - LO[i];
 
     if (limiter == LIM_NONE) {
         double* R = (double*)malloc(sizeof(double) * E * 4 * nn);
@@ -1030,6 +1039,7 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
     st->fv_inadmissible = inadm;
     st->theta_vol_min = thmin;
     st->alpha_vol_mean = nfaces ? alpha_sum / nfaces : 0.0;
+    if (uvol_out) memcpy(uvol_out, out, sizeof(double) * E * 4 * nn);
 
     /* mortar correction: one factor per mortar, antidiffusive flux scaled by
        the number n_i of mortars at node i (Sec. 2.3, remark on mortar limiting) */
@@ -1092,6 +1102,7 @@ int dgo_fe_step_ind(const dgo_mesh* m, const double* u, double dt, double gamma,
         }
         st->alpha_mort_mean = tmsum / m->M;
         st->theta_mort_min = tmmin;
+        if (theta_out) memcpy(theta_out, theta, sizeof(double) * m->M);
         /* apply: each node gathers its mortars in ascending mortar id */
 #pragma omp parallel for schedule(static)
         for (int64_t e = 0; e < E; ++e) {
