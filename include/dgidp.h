@@ -169,7 +169,7 @@ int dgidp_mesh_validate_bc(int N, int64_t n_leaves, const int8_t* level, const i
                            const int32_t* iy, int nx0, int ny0, const int* bc, int64_t* n_mortars,
                            int64_t* n_boundary_nodes, char* msg, int msglen);
 /* Boundary conditions of the domain sides, in the order x-, x+, y-, y+ (the
- * double Mach reflection and the jet of Sec. 3.6 use slip walls and
+ * double Mach reflection (Sec. 3.5) and the jet (Sec. 3.6) use slip walls and
  * characteristic inflow/outflow).  bc[4]: DGIDP_BC_PERIODIC, DGIDP_BC_WALL
  * (reflecting slip wall), DGIDP_BC_CHARACTERISTIC (inflow/outflow against an
  * exterior state) or DGIDP_BC_OUTFLOW (the exterior state is the interior
@@ -211,6 +211,13 @@ int dgidp_node_coords(dgidp_ctx* ctx, double* x, double* y);
  * node in the message). */
 int dgidp_state_upload(dgidp_ctx* ctx, const double* u, int on_device);
 int dgidp_state_download(dgidp_ctx* ctx, double* u, int on_device);
+/* Failure detection: check the context's current state on the device against
+ * the admissible set (every value finite, rho > 0, p > 0; the set that the
+ * limiter keeps, Sec. 2.2 and eq. Bounds_Positivity).  *first_bad = -1 if every
+ * node is admissible, else element * (N+1)^2 + node (external element order) of
+ * one inadmissible node: the first one in the library's internal order.
+ * Synchronises.  Errors: DGIDP_E_NO_STATE. */
+int dgidp_state_check(dgidp_ctx* ctx, int64_t* first_bad);
 
 /* Semi-discrete time derivative du/dt of the current state (eq. evolutionformula
  * with Kopriva's L2 mortars for DGIDP_RHS_HIGH; eq. FVmethod with the sparse IDP

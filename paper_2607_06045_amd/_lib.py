@@ -76,6 +76,7 @@ _SIGS = {
     "dgidp_node_coords": (_i, [_vp, _vp, _vp]),
     "dgidp_state_upload": (_i, [_vp, _vp, _i]),
     "dgidp_state_download": (_i, [_vp, _vp, _i]),
+    "dgidp_state_check": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "dgidp_rhs": (_i, [_vp, _i, _vp, _i]),
     "dgidp_max_dt": (_i, [_vp, _d, ctypes.POINTER(_d)]),
     "dgidp_limit": (_i, [_vp, _d, ctypes.POINTER(Stats)]),
@@ -307,6 +308,14 @@ class Solver:
         out = np.zeros(self.shape)
         self._check(_lib.dgidp_state_download(self._h, out.ctypes.data, 0), "dgidp_state_download")
         return out
+
+    def check_state(self):
+        """None if the device state is admissible (finite, rho > 0, p > 0), else
+        (element, node) of an inadmissible node (external element order)."""
+        b = ctypes.c_int64()
+        self._check(_lib.dgidp_state_check(self._h, ctypes.byref(b)), "dgidp_state_check")
+        nn = self.n * self.n
+        return None if b.value < 0 else (b.value // nn, b.value % nn)
 
     def rhs(self, which=RHS_HIGH):
         out = np.zeros(self.shape)

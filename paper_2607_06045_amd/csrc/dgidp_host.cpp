@@ -562,8 +562,6 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
         hh[2 * i] = Lx / (double)((int64_t)nx0 << l);
         hh[2 * i + 1] = Ly / (double)((int64_t)ny0 << l);
     }
-    ctx->E = E;
-    ctx->M = M;
     ctx->level.assign(level, level + E);
     ctx->ix.assign(ix, ix + E);
     ctx->iy.assign(iy, iy + E);
@@ -582,22 +580,27 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
         (rc = upload(ctx, P_SNODE, ctx->dm.slot_node, hm.snode)) ||
         (rc = upload(ctx, P_SPART, ctx->dm.slot_partner, hm.spart)) ||
         (rc = upload(ctx, P_PERM, ctx->dm.perm, hm.perm)) ||
-        (rc = upload(ctx, P_BKIND, ctx->dm.bkind, bkind)) || (rc = upload(ctx, P_BEXT, ctx->dm.bext, bext)))
+        (rc = upload(ctx, P_BKIND, ctx->dm.bkind, bkind)) || (rc = upload(ctx, P_BEXT, ctx->dm.bext, bext))) {
+        free_mesh(ctx);  // no half-built mesh: the context has none
         return rc;
-    ctx->NB = NB;
-    ctx->bface_elem = hm.bface_elem;
+    }
     const size_t sz = (size_t)E * 4 * NN * sizeof(double);
     if ((rc = pool_get(ctx, P_SLOT, (size_t)M * 3 * n * kSlotW * sizeof(double), ctx->dm.slot)) ||
-        (rc = pool_get(ctx, P_SHOCK, (size_t)E * sizeof(double), ctx->dm.shock_ind)))
+        (rc = pool_get(ctx, P_SHOCK, (size_t)E * sizeof(double), ctx->dm.shock_ind)) ||
+        (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
+         ((rc = pool_get(ctx, P_DLO, sz, ctx->dm.dlo)) ||
+          (rc = pool_get(ctx, P_LOB, (size_t)E * 3 * NN * sizeof(double), ctx->dm.lob)) ||
+          (rc = pool_get(ctx, P_LSV, (size_t)E * 2 * NN * sizeof(double), ctx->dm.lsv)))) ||
+        (rc = pool_get(ctx, P_U0 + ctx->u_slot, sz, ctx->U)) || (rc = pool_get(ctx, P_W1, sz, ctx->W1)) ||
+        (rc = pool_get(ctx, P_W2, sz, ctx->W2))) {
+        free_mesh(ctx);
         return rc;
-    if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
-        ((rc = pool_get(ctx, P_DLO, sz, ctx->dm.dlo)) ||
-         (rc = pool_get(ctx, P_LOB, (size_t)E * 3 * NN * sizeof(double), ctx->dm.lob)) ||
-         (rc = pool_get(ctx, P_LSV, (size_t)E * 2 * NN * sizeof(double), ctx->dm.lsv))))
-        return rc;
-    if ((rc = pool_get(ctx, P_U0 + ctx->u_slot, sz, ctx->U)) || (rc = pool_get(ctx, P_W1, sz, ctx->W1)) ||
-        (rc = pool_get(ctx, P_W2, sz, ctx->W2)))
-        return rc;
+    }
+    // every buffer is in place: only now does the context hold the mesh
+    ctx->NB = NB;
+    ctx->bface_elem = hm.bface_elem;
+    ctx->E = E;
+    ctx->M = M;
     ctx->dm.E = (int)E;
     ctx->dm.M = M;
     return 0;
@@ -806,6 +809,21 @@ int dgidp_state_download(dgidp_ctx* ctx, double* u, int on_device)
     return to_external(ctx, ctx->U, u, on_device);
 }
 
+int dgidp_state_check(dgidp_ctx* ctx, int64_t* first_bad)
+{
+    if (!ctx || !first_bad) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    const int N = ctx->p.N, NN = (N + 1) * (N + 1);
+    HIPCHK(hipMemsetAsync(ctx->bad, 0xff, sizeof(unsigned long long), ctx->stream));
+    if (launch_check_state(N, (int)ctx->E, ctx->p.gamma, ctx->U, ctx->bad, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "check kernel launch failed");
+    unsigned long long bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, ctx->bad, sizeof(bad), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *first_bad = bad == ~0ull ? -1 : (int64_t)ctx->perm[bad / NN] * NN + (int64_t)(bad % NN);
+    return 0;
+}
+
 int dgidp_rhs(dgidp_ctx* ctx, int which, double* du, int on_device)
 {
     if (!ctx || !du || (which != DGIDP_RHS_HIGH && which != DGIDP_RHS_LOW)) return DGIDP_E_INVALID_ARG;
@@ -875,6 +893,8 @@ int dgidp_limit(dgidp_ctx* ctx, double dt, dgidp_stats* s)
     int rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st, stored_dt(ctx));
     if (rc) return rc;
     std::swap(ctx->U, ctx->W1);
+    // captured steps hold the old state and stage buffer addresses
+    drop_graphs(ctx);
     if (s) {
         rc = sync_stats(ctx, s, 1);
         s->dt = dt;
@@ -1058,6 +1078,12 @@ int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int
                           ctx->ny0, flags, plan, err);
     if (rc) return fail(ctx, rc, err);
     const int64_t En = (int64_t)plan.level.size();
+    // the new mesh must fit the index range of the kernels (the limit that
+    // dgidp_mesh_upload enforces) before the current mesh and state are let go
+    if (En > (int64_t)(1 << 30) / (NN * 4))
+        return fail(ctx, DGIDP_E_INVALID_ARG,
+                    "adaptation would give " + std::to_string(En) + " leaves, above the limit of " +
+                        std::to_string((1 << 30) / (NN * 4)) + "; mesh and state kept");
     // old external -> old internal
     std::vector<int> inv_old((size_t)ctx->E);
     for (int64_t i = 0; i < ctx->E; ++i) inv_old[ctx->perm[i]] = (int)i;
@@ -1122,7 +1148,6 @@ int dgidp_refine_coarsen(dgidp_ctx* ctx, const int8_t* flags, double zs_eps, int
     cleanup();
     if (e1 != hipSuccess) return fail(ctx, DGIDP_E_DEVICE, "transfer counters");
     ctx->has_state = true;
-    (void)NN;
     if (n_leaves_out) *n_leaves_out = En;
     if (st) {
         st->n_refined = plan.n_refined;

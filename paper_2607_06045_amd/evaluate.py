@@ -33,7 +33,7 @@
       every 5 steps between 16 and n elements per direction, as in the paper
 
   python -m paper_2607_06045_amd.evaluate dmr [--level 4] [--t-end 0.2] [--amr]
-      the double Mach reflection of Sec. 3.6 on [0, 3.25] x [0, 1] (16 x 5
+      the double Mach reflection of Sec. 3.5 on [0, 3.25] x [0, 1] (16 x 5
       root cells, uniform at the given level, N = 4, bar-state local limiting,
       IDP time step at CFL 0.9): characteristic boundaries on x-, x+ and y+
       against the exact moving incident shock (the post-shock state where

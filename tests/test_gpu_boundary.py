@@ -1,5 +1,5 @@
 """GPU non-periodic boundaries (slip wall, characteristic inflow/outflow, outflow;
-the conditions of Sec. 3.6) against the oracle, through the C-ABI.
+the conditions of Sec. 3.5 and 3.6) against the oracle, through the C-ABI.
 
 Tolerances: 1e-12 per DOF (the state metric of parity.py) for residuals and for
 single limited forward-Euler steps; whole runs with local limiting are compared
@@ -166,7 +166,7 @@ def test_boundary_arguments():
 
 
 def test_double_mach_reflection_short():
-    """The double Mach reflection (Sec. 3.6) at 64 x 20 elements, N = 4, to
+    """The double Mach reflection (Sec. 3.5) at 64 x 20 elements, N = 4, to
     t = 0.05: the incident shock is straight and moves at a known speed, so its
     position on the upper side (characteristic boundary against the exact moving
     shock) is exact: within two cell widths.  No bound violations; the density

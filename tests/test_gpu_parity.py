@@ -199,7 +199,8 @@ def test_error_paths(oracle):
 def test_graph_replay_matches_eager():
     """Enqueue-only steps replay a captured graph: ten replays (alternating the
     two captured graphs), interleaved with an eager step that returns
-    statistics, give bit-identical states to kernel-by-kernel launches."""
+    statistics and with limited forward-Euler steps (which move the state to
+    another buffer), give bit-identical states to kernel-by-kernel launches."""
     import paper_2607_06045_amd as P
     spec = workload_mesh("blast22k")
     out = []
@@ -215,6 +216,8 @@ def test_graph_replay_matches_eager():
                 st = s.step(0.5)  # eager, with statistics
                 assert st["violations"] == 0
                 s.synchronize()
+            if k in (6, 7):
+                s.limit(2e-6, stats=False)
         out.append(s.download())
     print(f"graph vs eager: max |diff| {np.abs(out[0] - out[1]).max():.3e}", flush=True)
     assert np.array_equal(out[0], out[1])
