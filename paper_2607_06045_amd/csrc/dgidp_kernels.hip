@@ -94,6 +94,42 @@ constexpr unsigned long long pair_code()
     return c;
 }
 
+// The node pairs of an element, N per thread: thread q evaluates the pairs
+// q + i NN (i < N) of the list "x lines, then y lines; in each line the pairs
+// (l, k), l < k, in order" (N NN pairs in all, 2 n n(n-1)/2).  Entry
+// ql | qk << 5 | d << 10 | l << 11 | k << 14: the two nodes (element-local
+// indices), the direction and their positions along the line.
+template <int N>
+struct PairMap {
+    static constexpr int n = N + 1, NN = n * n, NPL = n * (n - 1) / 2;
+    unsigned int code[NN][N];
+    constexpr PairMap() : code()
+    {
+        for (int q = 0; q < NN; ++q)
+            for (int i = 0; i < N; ++i) {
+                const int p = q + i * NN;
+                const int d = p / (n * NPL), rem = p % (n * NPL), line = rem / NPL;
+                int l = 0, r = rem % NPL;
+                while (r >= n - 1 - l) {
+                    r -= n - 1 - l;
+                    ++l;
+                }
+                const int k = l + 1 + r;
+                const int ql = d == 0 ? line * n + l : l * n + line;
+                const int qk = d == 0 ? line * n + k : k * n + line;
+                code[q][i] = (unsigned)(ql | qk << 5 | d << 10 | l << 11 | k << 14);
+            }
+    }
+};
+__constant__ PairMap<3> c_pm3 = PairMap<3>();
+__constant__ PairMap<4> c_pm4 = PairMap<4>();
+template <int N>
+__device__ __forceinline__ unsigned pair_entry(int q, int i);
+template <>
+__device__ __forceinline__ unsigned pair_entry<3>(int q, int i) { return c_pm3.code[q][i]; }
+template <>
+__device__ __forceinline__ unsigned pair_entry<4>(int q, int i) { return c_pm4.code[q][i]; }
+
 // ---------------------------------------------------------------------------
 // arithmetic helpers
 // ---------------------------------------------------------------------------
@@ -106,6 +142,21 @@ __device__ __forceinline__ double frcp(double y)
     r = fma(r, e, r);
     e = fma(-y, r, 1.0);
     return fma(r, e, r);
+}
+
+// sqrt(y) for y >= 0 (normal or zero): the hardware reciprocal square root,
+// one step of the coupled Newton iteration for sqrt y and 1 / (2 sqrt y), then
+// a Newton correction of the root (about 1 ulp).  y = 0 gives 0, y < 0 or NaN
+// gives NaN.
+__device__ __forceinline__ double fsqrt(double y)
+{
+    const double r = __builtin_amdgcn_rsq(y);
+    double g = y * r, h = 0.5 * r;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    g = fma(fma(-g, g, y), h, g);
+    return y == 0.0 ? 0.0 : g;
 }
 
 // t[k] for a lane-dependent k < M from lane-uniform table entries: the entries
@@ -132,7 +183,7 @@ __device__ __forceinline__ void make_node(NodeP& s, double g)
     s.v1 = s.u[1] * ir;
     s.v2 = s.u[2] * ir;
     s.p = (g - 1.0) * (s.u[3] - 0.5 * (s.u[1] * s.v1 + s.u[2] * s.v2));
-    s.c = sqrt(g * s.p * ir);
+    s.c = fsqrt(g * s.p * ir);
 }
 
 // Ghost state across a boundary face f (0 x-, 1 x+, 2 y-, 3 y+) of the interior
@@ -218,29 +269,58 @@ __device__ __forceinline__ void mortar_flux(int d, bool large_low, const NodeP& 
     llf_face(d, large_low, ui, us, F);
 }
 
-// logarithmic mean (x - y) / (ln x - ln y) and its reciprocal from precomputed
-// logarithms; for ((x-y)/(x+y))^2 < 1e-4 the series of 2 atanh truncated after
-// f^6 (Ismail & Roe 2009)
+// logarithmic mean x^ln = (x - y) / (ln x - ln y) from the logarithms lx, ly.
+// Where ((x - y)/(x + y))^2 = f^2 < 1e-4 the series of 2 atanh truncated after
+// f^6 (Ismail & Roe 2009): (x + y) / (2 (1 + e)), e = f^2/3 + f^4/5 + f^6/7,
+// with 1/(1 + e) expanded to third order (e < 3.5e-5: remainder below 2e-18).
+// Branch free: one reciprocal serves whichever form applies.
 __device__ __forceinline__ double lnmean(double x, double y, double lx, double ly)
 {
     const double s = x + y, d = x - y;
-    if (d * d < 1e-4 * (s * s)) {
-        const double is = frcp(s);
-        const double f2 = d * d * is * is;
-        return s * frcp(2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0))));
-    }
-    return d * frcp(lx - ly);
+    const bool ser = d * d < 1e-4 * (s * s);
+    const double r = frcp(ser ? s : lx - ly);
+    const double f2 = d * d * (r * r);
+    const double e = f2 * (1.0 / 3.0 + f2 * (1.0 / 5.0 + f2 * (1.0 / 7.0)));
+    const double sv = 0.5 * s * (1.0 - e * (1.0 - e * (1.0 - e)));
+    return ser ? sv : d * r;
 }
 
+// 1 / x^ln = (ln x - ln y) / (x - y); series (2 + f^2 (2/3 + f^2 (2/5 + f^2 2/7))) / (x + y)
 __device__ __forceinline__ double inv_lnmean(double x, double y, double lx, double ly)
 {
     const double s = x + y, d = x - y;
-    if (d * d < 1e-4 * (s * s)) {
-        const double is = frcp(s);
-        const double f2 = d * d * is * is;
-        return (2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0)))) * is;
+    const bool ser = d * d < 1e-4 * (s * s);
+    const double r = frcp(ser ? s : d);
+    const double f2 = d * d * (r * r);
+    const double sv = (2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0)))) * r;
+    return ser ? sv : (lx - ly) * r;
+}
+
+// Natural logarithm for x > 0 normal (NaN for x <= 0 or NaN): x = m 2^k with
+// m in [sqrt(1/2), sqrt(2)), f = m - 1 (exact), s = f / (2 + f), so that
+// ln m = 2 atanh s = 2 s + T, T = 2 s^3/3 + 2 s^5/5 + ... (|s| < 0.172, the
+// series to s^21 leaves less than 2^-56 of ln m), and 2 s = f - s f gives
+// ln m = f - s (f - T / s) with T / s a polynomial in s^2; ln x = k ln 2 +
+// ln m with ln 2 split into a head whose product with k is exact and a tail.
+// About 1 ulp, thirty instructions (the run-time library's logarithm takes
+// about eighty).
+__device__ __forceinline__ double flog(double x)
+{
+    double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+    int k = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0x1.6a09e667f3bcdp-1) {
+        m *= 2.0;
+        k -= 1;
     }
-    return (lx - ly) * frcp(d);
+    const double f = m - 1.0;
+    const double sf = f * frcp(2.0 + f);
+    const double z = sf * sf;
+    const double t = z * (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0 + z * (2.0 / 9.0 + z * (2.0 / 11.0 +
+                     z * (2.0 / 13.0 + z * (2.0 / 15.0 + z * (2.0 / 17.0 + z * (2.0 / 19.0 + z * (2.0 / 21.0))))))))));
+    const double lm = f - sf * (f - t);
+    const double kd = (double)k;
+    const double r = fma(kd, 0x1.62e42fefp-1, fma(kd, 0x1.473de6af278edp-34, lm));
+    return x > 0.0 ? r : __builtin_nan("");
 }
 
 __device__ __forceinline__ float lnmeanf(float x, float y, float lx, float ly)
@@ -454,13 +534,13 @@ __device__ __forceinline__ double volume_factor(const double* uFV, const double 
     if (LOCB && P > -kLocalNegl * uFV[0]) P = 0.0;
     if (LOCB && Pp < kLocalNegl * uFV[0]) Pp = 0.0;
     double th = 1.0;
-    if (P < 0.0) th = fmax(fmin((rt - uFV[0]) / P, 1.0), 0.0);
+    if (P < 0.0) th = fmax(fmin((rt - uFV[0]) * frcp(P), 1.0), 0.0);
     if (LOCB && Pp > 0.0) th = fmin(th, fmax((rce * kMarginHi - uFV[0]) / Pp, 0.0));
-    // pressure: each face's increment scaled by Gamma = 2d = 4
+    // pressure: each face's increment scaled by Gamma = 2d = 4 (a zero
+    // increment, as on a missing face, admits theta = 1 at an admissible uFV)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
-        if (dc[0] == 0.0 && dc[1] == 0.0 && dc[2] == 0.0 && dc[3] == 0.0) continue;
         th = fmin(th, theta_p(uFV, dc, pt, ig1));
     }
     // specific entropy: per face on [0, th]
@@ -652,12 +732,12 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     static_assert(G::PP >= 12 * n, "mortar buffers reuse the pair buffer");
     static_assert(G::PU >= NFN, "surface terms reuse the state buffer");
     constexpr int MB = 4 * n;  // offset of the mortar-node fluxes in the pair buffer
-    constexpr unsigned long long PCODE = pair_code<N>();
 
     // variable-major, padded (see Geo)
     __shared__ double sU[EPB][4][G::PU];
     __shared__ double sR[EPB][8][G::PR];     // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
     __shared__ double sPair[EPB][4][G::PP];  // pair fluxes; later FV and A of the subcell faces
+    __shared__ double sTw[2][n];              // LGL weights and their reciprocals, read per lane
     // node factors of the volume limiter reuse the first row of sR (free after phase 5)
 #define sTh(qq) sR[le][0][qq]
 
@@ -667,6 +747,10 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
     const int e = xcd_batch(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = tid < NT && e < A.E;
+    if (tid < n) {
+        sTw[0][tid] = tb.w[tid];
+        sTw[1][tid] = tb.winv[tid];
+    }
 
     // ---- phase 1: own node into LDS; face-node role and its remote loads ----
     double hx = 1.0, hy = 1.0;
@@ -694,12 +778,11 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // lane-indexed table reads do not wait in the pair phase; the empty asm
     // keeps them in registers (no reload at the use)
     double spair[PPT];
+    unsigned pcode[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int p = q + i * NN;
-        const int rem = p % (n * NPL), pi = rem % NPL;
-        const int lk = (int)((PCODE >> (6 * pi)) & 63ull);
-        spair[i] = act ? tb.S[lk & 7][lk >> 3] : 0.0;
+        pcode[i] = act ? pair_entry<N>(q, i) : 0u;
+        spair[i] = act ? tb.S[(pcode[i] >> 11) & 7][(pcode[i] >> 14) & 7] : 0.0;
         asm volatile("" : "+v"(spair[i]));
     }
     if (act) {
@@ -723,7 +806,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         }
         // the logarithms feed only the two-point volume fluxes: FP32 in the
         // mixed mode (exactly representable in the FP64 slots)
-        const double lr = MIXED ? (double)__logf((float)me.r) : log(me.r);
+        const double lr = MIXED ? (double)__logf((float)me.r) : flog(me.r);
         const double z = me.r * frcp(me.p);
         sR[le][0][q] = me.r;
         sR[le][1][q] = me.v1;
@@ -732,7 +815,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         sR[le][4][q] = me.c;
         sR[le][5][q] = lr;
         sR[le][6][q] = z;
-        const double lz = MIXED ? (double)__logf((float)z) : log(z);
+        const double lz = MIXED ? (double)__logf((float)z) : flog(z);
         sR[le][7][q] = lz;
         // the blend needs local factors only where the indicator fires, and at
         // mortar nodes (their mortar may blend with another element's weight)
@@ -807,7 +890,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                 bar_bounds(dff, lowf, own, o, g, fb_lo, fb_ls);
                 fb_hi = fb_lo;
             }
-            const double W = sgf * pick(tb.w, fk) * hff * 0.5;
+            const double W = sgf * sTw[0][fk] * hff * 0.5;
 #pragma unroll
             for (int v = 0; v < 4; ++v) fterm[v] = W * F[v];
         } else if (!fm_small(fcode_f)) {
@@ -890,7 +973,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             double F[4], ho[4], lo[4] = {0, 0, 0, 0};
             mortar_flux(dff, !lowf, ui, own, F);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ho[v] = sgf * pick(tb.w, fk) * hff * 0.5 * F[v];
+            for (int v = 0; v < 4; ++v) ho[v] = sgf * sTw[0][fk] * hff * 0.5 * F[v];
 #pragma unroll
             for (int j = 0; j < n; ++j) {
                 const double wt = tb.Wt[j][hh * n + fk];
@@ -955,7 +1038,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                         for (int l = 0; l < n; ++l)
                             acc += tb.P[hh][fk][l] * sPair[le][v][MB + (ff * 2 + hh) * n + l];
                 }
-                ho[v] = sgf * pick(tb.w, fk) * hff * 0.5 * acc;
+                ho[v] = sgf * sTw[0][fk] * hff * 0.5 * acc;
             }
             double* R = A.slot + (size_t)(S * 3 * n + fk) * kSlotW;
 #pragma unroll
@@ -965,71 +1048,65 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     }
 
     // ---- phase 4: two-point volume fluxes, once per node pair of each line ----
+    // Each flux is evaluated in the frame of its pair's direction d: the normal
+    // velocity is read from LDS row 1 + d and the tangential one from row 2 - d,
+    // and the two momentum components are stored back to rows 1 + d and 2 - d,
+    // so that lanes holding x and y pairs run the same instructions.
     if (act) {
+        const double hh[2] = {0.5 * hy, 0.5 * hx};
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
+            const unsigned c = pcode[i];
+            const int ql = c & 31, qk = (c >> 5) & 31, d = (c >> 10) & 1;
             const int p = q + i * NN;
-            const int d = p / (n * NPL), rem = p - d * (n * NPL);
-            const int line = rem / NPL, pi = rem - line * NPL;
-            const int lk = (int)((PCODE >> (6 * pi)) & 63ull);
-            const int l = lk & 7, k = lk >> 3;
-            const int ql = d == 0 ? line * n + l : l * n + line;
-            const int qk = d == 0 ? line * n + k : k * n + line;
-            const double scale = spair[i] * 0.5 * (d == 0 ? hy : hx);
-            double L[8], R[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                L[j] = sR[le][j][ql];
-                R[j] = sR[le][j][qk];
-            }
-            double f[4];
+            const int rn = 1 + d, rt = 2 - d;
+            const double scale = spair[i] * (d ? hh[1] : hh[0]);
+            const double L0 = sR[le][0][ql], Ln = sR[le][rn][ql], Lt = sR[le][rt][ql], L3 = sR[le][3][ql];
+            const double L5 = sR[le][5][ql], L6 = sR[le][6][ql], L7 = sR[le][7][ql];
+            const double R0 = sR[le][0][qk], Rn = sR[le][rn][qk], Rt = sR[le][rt][qk], R3 = sR[le][3][qk];
+            const double R5 = sR[le][5][qk], R6 = sR[le][6][qk], R7 = sR[le][7][qk];
+            double f0, fn, ft, f3;
             if (!MIXED) {
-                const double rho_ln = lnmean(L[0], R[0], L[5], R[5]);
-                const double iz_ln = inv_lnmean(L[6], R[6], L[7], R[7]);
-                const double vnL = d == 0 ? L[1] : L[2], vnR = d == 0 ? R[1] : R[2];
-                const double fr = rho_ln * 0.5 * (vnL + vnR);
-                const double pa = 0.5 * (L[3] + R[3]);
-                f[0] = fr;
+                const double iz_ln = inv_lnmean(L6, R6, L7, R7);
+                const double vna = 0.5 * (Ln + Rn), vta = 0.5 * (Lt + Rt);
+                const double fr = lnmean(L0, R0, L5, R5) * vna;
+                f0 = fr;
                 if (A.vflux == DGIDP_FLUX_CHANDRASHEKAR) {
                     // Chandrashekar: beta = z / 2, so p~ = rho-bar / (2 beta-bar) =
                     // (rho_L + rho_R) / (z_L + z_R) and 1 / (2 beta^ln) = 1 / z^ln
-                    const double pt = (L[0] + R[0]) / (L[6] + R[6]);
-                    const double v1a = 0.5 * (L[1] + R[1]), v2a = 0.5 * (L[2] + R[2]);
-                    f[1] = fr * v1a + (d == 0 ? pt : 0.0);
-                    f[2] = fr * v2a + (d == 1 ? pt : 0.0);
-                    f[3] = fr * (ig1 * iz_ln - 0.25 * (L[1] * L[1] + L[2] * L[2] + R[1] * R[1] + R[2] * R[2])) +
-                           v1a * f[1] + v2a * f[2];
+                    const double pt = (L0 + R0) * frcp(L6 + R6);
+                    fn = fr * vna + pt;
+                    ft = fr * vta;
+                    f3 = fr * (ig1 * iz_ln - 0.25 * (Ln * Ln + Lt * Lt + Rn * Rn + Rt * Rt)) + vna * fn + vta * ft;
                 } else {
-                    f[1] = fr * 0.5 * (L[1] + R[1]) + (d == 0 ? pa : 0.0);
-                    f[2] = fr * 0.5 * (L[2] + R[2]) + (d == 1 ? pa : 0.0);
-                    f[3] = fr * (0.5 * (L[1] * R[1] + L[2] * R[2]) + ig1 * iz_ln) +
-                           0.5 * (L[3] * vnR + R[3] * vnL);
+                    fn = fr * vna + 0.5 * (L3 + R3);
+                    ft = fr * vta;
+                    f3 = fr * (0.5 * (Ln * Rn + Lt * Rt) + ig1 * iz_ln) + 0.5 * (L3 * Rn + R3 * Ln);
                 }
             } else {
-                const float rho_ln = lnmeanf((float)L[0], (float)R[0], (float)L[5], (float)R[5]);
-                const float iz_ln = inv_lnmeanf((float)L[6], (float)R[6], (float)L[7], (float)R[7]);
-                const float v1L = (float)L[1], v1R = (float)R[1], v2L = (float)L[2], v2R = (float)R[2];
-                const float pL = (float)L[3], pR = (float)R[3];
-                const float vnL = d == 0 ? v1L : v2L, vnR = d == 0 ? v1R : v2R;
-                const float fr = rho_ln * 0.5f * (vnL + vnR);
-                const float pa = 0.5f * (pL + pR);
-                f[0] = fr;
+                const float iz_ln = inv_lnmeanf((float)L6, (float)R6, (float)L7, (float)R7);
+                const float vnL = (float)Ln, vnR = (float)Rn, vtL = (float)Lt, vtR = (float)Rt;
+                const float pL = (float)L3, pR = (float)R3;
+                const float vna = 0.5f * (vnL + vnR), vta = 0.5f * (vtL + vtR);
+                const float fr = lnmeanf((float)L0, (float)R0, (float)L5, (float)R5) * vna;
+                f0 = fr;
                 if (A.vflux == DGIDP_FLUX_CHANDRASHEKAR) {
-                    const float pt = ((float)L[0] + (float)R[0]) / ((float)L[6] + (float)R[6]);
-                    const float v1a = 0.5f * (v1L + v1R), v2a = 0.5f * (v2L + v2R);
-                    f[1] = fr * v1a + (d == 0 ? pt : 0.0f);
-                    f[2] = fr * v2a + (d == 1 ? pt : 0.0f);
-                    f[3] = fr * ((float)ig1 * iz_ln - 0.25f * (v1L * v1L + v2L * v2L + v1R * v1R + v2R * v2R)) +
-                           v1a * (float)f[1] + v2a * (float)f[2];
+                    const float pt = ((float)L0 + (float)R0) / ((float)L6 + (float)R6);
+                    const float fnf = fr * vna + pt, ftf = fr * vta;
+                    fn = fnf;
+                    ft = ftf;
+                    f3 = fr * ((float)ig1 * iz_ln - 0.25f * (vnL * vnL + vtL * vtL + vnR * vnR + vtR * vtR)) +
+                         vna * fnf + vta * ftf;
                 } else {
-                    f[1] = fr * 0.5f * (v1L + v1R) + (d == 0 ? pa : 0.0f);
-                    f[2] = fr * 0.5f * (v2L + v2R) + (d == 1 ? pa : 0.0f);
-                    f[3] = fr * (0.5f * (v1L * v1R + v2L * v2R) + (float)ig1 * iz_ln) +
-                           0.5f * (pL * vnR + pR * vnL);
+                    fn = fr * vna + 0.5f * (pL + pR);
+                    ft = fr * vta;
+                    f3 = fr * (0.5f * (vnL * vnR + vtL * vtR) + (float)ig1 * iz_ln) + 0.5f * (pL * vnR + pR * vnL);
                 }
             }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sPair[le][v][p] = scale * f[v];
+            sPair[le][0][p] = scale * f0;
+            sPair[le][rn][p] = scale * fn;
+            sPair[le][rt][p] = scale * ft;
+            sPair[le][3][p] = scale * f3;
         }
     }
     __syncthreads();
@@ -1060,7 +1137,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             double F[4];
             llf_face(d, true, me, o, F);
             if (BAR && need_loc) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
-            const double hs = 0.5 * (d == 0 ? hy : hx), wl = pick(tb.w, line);
+            const double hs = 0.5 * (d == 0 ? hy : hx), wl = sTw[0][line];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 FVo[d][v] = hs * F[v];
@@ -1121,8 +1198,8 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     int slot0 = -1, slot1 = -1, nmf = 0;
     double im = 1.0;  // 1 / m_i
     if (act) {
-        im = 4.0 / (hx * hy) * pick(tb.winv, a) * pick(tb.winv, b);
-        const double wa = pick(tb.w, a), wb = pick(tb.w, b);
+        im = 4.0 * frcp(hx * hy) * sTw[1][a] * sTw[1][b];
+        const double wa = sTw[0][a], wb = sTw[0][b];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double r = 0.0;
@@ -1232,12 +1309,19 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             // the positivity floor stays: the density floor is the larger one
             rlf = fmax(rmin, rlo);
         }
+        // missing faces (on the element boundary) take a zero increment: their
+        // (clamped, in-range) table entry is multiplied by 0
+        {
+            const double m0 = a > 0 ? dtm : 0.0, m1 = a < N ? -dtm : 0.0;
+            const double m2 = b > 0 ? dtm : 0.0, m3 = b < N ? -dtm : 0.0;
+            const int i0 = NF + max(fxl, 0), i3 = NF + min(fyt, NF - 1);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            cf[0][v] = a > 0 ? dtm * sPair[le][v][NF + fxl] : 0.0;
-            cf[1][v] = a < N ? -dtm * sPair[le][v][NF + fxr] : 0.0;
-            cf[2][v] = b > 0 ? dtm * sPair[le][v][NF + fyb] : 0.0;
-            cf[3][v] = b < N ? -dtm * sPair[le][v][NF + fyt] : 0.0;
+            for (int v = 0; v < 4; ++v) {
+                cf[0][v] = m0 * sPair[le][v][i0];
+                cf[1][v] = m1 * sPair[le][v][NF + fxr];
+                cf[2][v] = m2 * sPair[le][v][NF + fyb];
+                cf[3][v] = m3 * sPair[le][v][i3];
+            }
         }
         if (A.limiter != DGIDP_LIMIT_NONE) {
             if (PURE) {
