@@ -1111,25 +1111,41 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     }
     __syncthreads();
 
-    // ---- phase 5: subcell faces owned by this node: x (a|a+1) and y (b|b+1) ----
+    // ---- phase 5a: telescoped high-order subcell fluxes, one lane per line ----
+    // Lanes q < 2n of an element own line q (x lines q < n, y lines after):
+    // the flux through the subcell face after position pos is the sum of the
+    // line's pair fluxes (l, k) with l <= pos < k.  With the position a loop
+    // constant, every index is static.  The N sums replace the line's first N
+    // pair slots, which no other lane reads.
+    if (act && q < 2 * n) {
+        const int base = q * NPL;  // x lines, then y lines, NPL pairs each
+        double hof[N][4];
+#pragma unroll
+        for (int pos = 0; pos < N; ++pos)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l <= pos; ++l)
+#pragma unroll
+                    for (int k = pos + 1; k < n; ++k)
+                        acc += sPair[le][v][base + l * (2 * n - l - 1) / 2 + (k - l - 1)];
+                hof[pos][v] = acc;
+            }
+#pragma unroll
+        for (int pos = 0; pos < N; ++pos)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sPair[le][v][base + pos] = hof[pos][v];
+    }
+    // ---- phase 5b: low-order subcell fluxes of the faces owned by this node,
+    // x (a|a+1) and y (b|b+1), and the antidiffusive fluxes ----
     double FVo[2][4], Ao[2][4];
     double brb[2] = {0.0, 0.0}, bls[2] = {0.0, 0.0};  // bar state of each owned subcell face
     if (act) {
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            const int pos = d == 0 ? a : b, line = d == 0 ? b : a;
+            const int pos = d == 0 ? a : b;
             if (pos >= N) continue;
-            double ho[4] = {0, 0, 0, 0};
-            // telescoped high-order flux: pairs (l, k) with l <= pos < k
-#pragma unroll
-            for (int l = 0; l <= pos; ++l)
-#pragma unroll
-                for (int k = pos + 1; k < n; ++k) {
-                    const int pi = l * (2 * n - l - 1) / 2 + (k - l - 1);
-                    const int p = d * n * NPL + line * NPL + pi;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) ho[v] += sPair[le][v][p];
-                }
             const int qn = d == 0 ? q + 1 : q + n;
             NodeP o, me;
             LDS_NODE(o, qn);
@@ -1137,12 +1153,21 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             double F[4];
             llf_face(d, true, me, o, F);
             if (BAR && need_loc) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
-            const double hs = 0.5 * (d == 0 ? hy : hx), wl = sTw[0][line];
+            const double hs = 0.5 * (d == 0 ? hy : hx);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                FVo[d][v] = hs * F[v];
-                Ao[d][v] = wl * (ho[v] - FVo[d][v]);
-            }
+            for (int v = 0; v < 4; ++v) FVo[d][v] = hs * F[v];
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int pos = d == 0 ? a : b, line = d == 0 ? b : a;
+            if (pos >= N) continue;
+            const int slot = (d * n + line) * NPL + pos;
+            const double wl = sTw[0][line];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ao[d][v] = wl * (sPair[le][v][slot] - FVo[d][v]);
         }
     }
     __syncthreads();
