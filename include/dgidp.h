@@ -247,6 +247,23 @@ int dgidp_step(dgidp_ctx* ctx, double cfl, double* dt_used, dgidp_stats* s);
 int dgidp_set_graphs(dgidp_ctx* ctx, int enable);
 /* Same with a given dt (used to land exactly on an end time). */
 int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): one SSP-RK3
+ * step in place, the same as dgidp_step(ctx, cfl, NULL, NULL), that allocates
+ * nothing.  Its per-step buffers (the two stage states, the mortar slot records,
+ * the dt accumulators and dt, the combined-limiting indicator and the
+ * low-order-bounds arrays) live in one static device array per GPU of 64 MiB
+ * (kept until the process ends), set up when a context is created.  Limit: the
+ * buffers of the mesh must fit, about 2 x 32 B per node plus 128 B per mortar
+ * node (plus 72 B per node with DGIDP_LIMIT_LOCAL_LOWORDER): up to about 1.0
+ * million nodes, for example 65,000 elements at N = 3 or 41,000 at N = 4;
+ * larger meshes return DGIDP_E_INVALID_ARG with the required size in the
+ * message, and nothing is enqueued.  Enqueue only (no statistics, no host
+ * synchronisation); the result equals dgidp_step's bit for bit.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (on several
+ * streams or host threads) race and must be serialised by the caller.  The
+ * device current on the calling thread must be the context's device. */
+int dgidp_step_noalloc(dgidp_ctx* ctx, double cfl);
 
 /* ---------------- adaptive mesh refinement (Sec. 2.4) ---------------- */
 

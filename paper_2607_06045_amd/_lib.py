@@ -78,6 +78,7 @@ _SIGS = {
     "dgidp_state_download": (_i, [_vp, _vp, _i]),
     "dgidp_state_check": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "dgidp_rhs": (_i, [_vp, _i, _vp, _i]),
+    "dgidp_step_noalloc": (_i, [_vp, _d]),
     "dgidp_max_dt": (_i, [_vp, _d, ctypes.POINTER(_d)]),
     "dgidp_limit": (_i, [_vp, _d, ctypes.POINTER(Stats)]),
     "dgidp_step": (_i, [_vp, _d, ctypes.POINTER(_d), ctypes.POINTER(Stats)]),
@@ -340,6 +341,11 @@ class Solver:
         self._check(_lib.dgidp_step(self._h, cfl, ctypes.byref(dt) if stats else None,
                                     ctypes.byref(st) if stats else None), "dgidp_step")
         return st.to_dict() if stats else None
+
+    def step_noalloc(self, cfl):
+        """One SSP-RK3 step that allocates nothing (buffers in the library's
+        static per-device scratch array); enqueue only."""
+        self._check(_lib.dgidp_step_noalloc(self._h, cfl), "dgidp_step_noalloc")
 
     def step_dt(self, dt, stats=True):
         st = Stats()

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgidp.so")
-SOURCES = ["dgidp_kernels.hip", "dgidp_tables.cpp", "dgidp_host.cpp", "dgidp_amr.cpp", "dgidp_mlp.hip"]
+SOURCES = ["dgidp_kernels.hip", "dgidp_tables.cpp", "dgidp_host.cpp", "dgidp_amr.cpp", "dgidp_mlp.hip",
+           "dgidp_noalloc.hip"]
 # packed FP32 instructions are disabled: hipcc would otherwise emit them from
 # ordinary float code.  The feature is a device one: the host (x86) pass of
 # hipcc reports that it does not know it, once per function; that line alone

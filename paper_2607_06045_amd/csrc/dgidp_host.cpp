@@ -439,26 +439,31 @@ DtSource stored_dt(const dgidp_ctx* c)
     return d;
 }
 
-// one limited forward-Euler stage: uout = a un + b FE(uin)
-int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, double a, double b,
-          DevStats* st, const DtSource& dt)
+// one limited forward-Euler stage: uout = a un + b FE(uin), with the mesh
+// arrays and per-stage buffers of dm
+int stage_on(dgidp_ctx* ctx, const DevMesh& dm, const double* uin, const double* un, double* uout,
+             double a, double b, DevStats* st, const DtSource& dt)
 {
     const KernelParams kp = kparams(ctx);
     // combined limiting weighs its factors with the indicator of the stage's input
-    if (kp.limiter == DGIDP_LIMIT_COMBINED &&
-        launch_shock_indicator(ctx->p.N, ctx->dm, uin, kp.gamma, ctx->stream))
+    if (kp.limiter == DGIDP_LIMIT_COMBINED && launch_shock_indicator(ctx->p.N, dm, uin, kp.gamma, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
     // bounds from the low-order solution: R_LO / m of the input, then the bounds
     if (kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER &&
-        (launch_rhs(ctx->p.N, ctx->dm, kp, uin, DGIDP_RHS_LOW, ctx->dm.dlo, ctx->stream) ||
-         launch_lowbounds(ctx->p.N, ctx->dm, kp.gamma, uin, ctx->dm.dlo, dt, ctx->dm.lsv, ctx->dm.lob,
-                          ctx->stream)))
+        (launch_rhs(ctx->p.N, dm, kp, uin, DGIDP_RHS_LOW, dm.dlo, ctx->stream) ||
+         launch_lowbounds(ctx->p.N, dm, kp.gamma, uin, dm.dlo, dt, dm.lsv, dm.lob, ctx->stream)))
         return fail(ctx, DGIDP_E_DEVICE, "low-order bounds launch failed");
-    if (launch_stage(ctx->p.N, ctx->dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
+    if (launch_stage(ctx->p.N, dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
         return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
-    if (launch_mortar(ctx->p.N, ctx->dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
+    if (launch_mortar(ctx->p.N, dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
         return fail(ctx, DGIDP_E_DEVICE, "mortar kernel launch failed");
     return 0;
+}
+
+int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, double a, double b,
+          DevStats* st, const DtSource& dt)
+{
+    return stage_on(ctx, ctx->dm, uin, un, uout, a, b, st, dt);
 }
 
 }  // namespace
@@ -487,6 +492,9 @@ int dgidp_create(const dgidp_params* p, void* stream, dgidp_ctx** out)
         delete ctx;
         return DGIDP_E_DEVICE;
     }
+    // the allocation-free step's scratch address on this device (if this
+    // fails, dgidp_step_noalloc tries again on its first call here)
+    (void)noalloc_scratch_setup();
     if (hipMalloc((void**)&ctx->dt_dev, sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&ctx->acc, 2 * kDtWords * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&ctx->stats, sizeof(DevStats)) != hipSuccess ||
@@ -1001,6 +1009,69 @@ int dgidp_step_dt(dgidp_ctx* ctx, double dt, dgidp_stats* s)
         s->dt = dt;
         return rc;
     }
+    return 0;
+}
+
+int dgidp_step_noalloc(dgidp_ctx* ctx, double cfl)
+{
+    if (!ctx || !(cfl > 0)) return DGIDP_E_INVALID_ARG;
+    if (!ctx->has_state) return fail(ctx, DGIDP_E_NO_STATE, "no state");
+    size_t cap = 0;
+    char* base = (char*)noalloc_scratch(&cap);
+    if (!base && noalloc_scratch_setup() == 0) base = (char*)noalloc_scratch(&cap);
+    if (!base) return fail(ctx, DGIDP_E_DEVICE, "scratch address not available on this device");
+    // carve the per-step buffers from the scratch array, 256-byte aligned
+    const int N = ctx->p.N, n = N + 1, NN = n * n;
+    const size_t E = (size_t)ctx->E, M = (size_t)ctx->M;
+    const size_t state = E * 4 * NN * sizeof(double);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        return at;
+    };
+    const size_t o_acc = take(2 * kDtWords * sizeof(unsigned long long));
+    const size_t o_dt = take(sizeof(double));
+    const size_t o_w1 = take(state), o_w2 = take(state);
+    const size_t o_slot = take(M * 3 * n * kSlotW * sizeof(double));
+    const size_t o_ind = take(E * sizeof(double));
+    size_t o_dlo = 0, o_lob = 0, o_lsv = 0;
+    if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER) {
+        o_dlo = take(state);
+        o_lob = take(E * 3 * NN * sizeof(double));
+        o_lsv = take(E * 2 * NN * sizeof(double));
+    }
+    if (off > cap)
+        return fail(ctx, DGIDP_E_INVALID_ARG,
+                    "dgidp_step_noalloc: this mesh needs " + std::to_string(off) +
+                        " bytes of scratch, the maximum is " + std::to_string(cap));
+    DevMesh dm = ctx->dm;
+    dm.slot = (double*)(base + o_slot);
+    dm.shock_ind = (double*)(base + o_ind);
+    if (ctx->p.limiter == DGIDP_LIMIT_LOCAL_LOWORDER) {
+        dm.dlo = (double*)(base + o_dlo);
+        dm.lob = (double*)(base + o_lob);
+        dm.lsv = (double*)(base + o_lsv);
+    }
+    unsigned long long* acc = (unsigned long long*)(base + o_acc);
+    double* dtp = (double*)(base + o_dt);
+    double* W1 = (double*)(base + o_w1);
+    double* W2 = (double*)(base + o_w2);
+    // the array keeps the previous call's contents: the dt maxima must start at 0
+    if (launch_fill_u64(acc, 2 * kDtWords, 0ull, ctx->stream) ||
+        launch_dt(N, dm, kparams(ctx), ctx->U, ctx->p.dt_mode, acc, acc + kDtWords, ctx->stream))
+        return fail(ctx, DGIDP_E_DEVICE, "dt launch failed");
+    DtSource first;
+    first.dtmax = acc;
+    first.cfl = cfl;
+    first.dt_out = dtp;
+    DtSource stored;
+    stored.dt = dtp;
+    int rc;
+    if ((rc = stage_on(ctx, dm, ctx->U, nullptr, W1, 0.0, 1.0, nullptr, first)) ||
+        (rc = stage_on(ctx, dm, W1, ctx->U, W2, 0.75, 0.25, nullptr, stored)) ||
+        (rc = stage_on(ctx, dm, W2, ctx->U, ctx->U, 1.0 / 3.0, 2.0 / 3.0, nullptr, stored)))
+        return rc;
     return 0;
 }
 

@@ -159,4 +159,13 @@ int launch_check_state(int N, int E, double gamma, const double* u, unsigned lon
                        hipStream_t s);
 int upload_tables(int N, const void* host_tab, size_t bytes);
 
+// allocation-free step (dgidp_noalloc.hip): the size of the static per-device
+// scratch array, its one-time set-up on the current device (hipGetSymbolAddress;
+// 0 on success), its device address on the current device (null if not set up),
+// and a fill kernel for clearing parts of it
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+int noalloc_scratch_setup();
+void* noalloc_scratch(size_t* bytes);
+int launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
+
 }  // namespace dgidp
