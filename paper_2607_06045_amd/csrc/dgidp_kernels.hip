@@ -159,18 +159,6 @@ __device__ __forceinline__ double fsqrt(double y)
     return y == 0.0 ? 0.0 : g;
 }
 
-// t[k] for a lane-dependent k < M from lane-uniform table entries: the entries
-// come through the scalar cache and the choice is made with selects, instead
-// of one vector memory round trip per lane-indexed table read
-template <int M>
-__device__ __forceinline__ double pick(const double (&t)[M], int k)
-{
-    double r = t[0];
-#pragma unroll
-    for (int i = 1; i < M; ++i) r = k == i ? t[i] : r;
-    return r;
-}
-
 struct NodeP {
     double u[4];
     double r, v1, v2, p, c;
@@ -674,7 +662,7 @@ __device__ __forceinline__ void load_u(const double* u, int e, int q, double* w)
 {
     constexpr int NN = (N + 1) * (N + 1);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
+    for (int v = 0; v < 4; ++v) w[v] = u[((unsigned)e * 4u + v) * NN + q];  // < 2^30 (mesh limit)
 }
 
 template <int N>
@@ -738,6 +726,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     __shared__ double sR[EPB][8][G::PR];     // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
     __shared__ double sPair[EPB][4][G::PP];  // pair fluxes; later FV and A of the subcell faces
     __shared__ double sTw[2][n];              // LGL weights and their reciprocals, read per lane
+    __shared__ double sS[n][n];               // Sbar, read per pair
     // node factors of the volume limiter reuse the first row of sR (free after phase 5)
 #define sTh(qq) sR[le][0][qq]
 
@@ -751,6 +740,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         sTw[0][tid] = tb.w[tid];
         sTw[1][tid] = tb.winv[tid];
     }
+    if (tid < NN) sS[tid / n][tid % n] = tb.S[tid / n][tid % n];
 
     // ---- phase 1: own node into LDS; face-node role and its remote loads ----
     double hx = 1.0, hy = 1.0;
@@ -774,17 +764,10 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     double fb_lo = __builtin_inf(), fb_hi = -__builtin_inf(), fb_ls = __builtin_inf();
     const double dtpart =
         A.dtmax ? __longlong_as_double((long long)A.dtmax[(tid & 63) * kDtStride]) : 0.0;
-    // Sbar of this thread's volume pairs, loaded with the state so that the
-    // lane-indexed table reads do not wait in the pair phase; the empty asm
-    // keeps them in registers (no reload at the use)
-    double spair[PPT];
+    // this thread's node pairs (the pair map), loaded with the state
     unsigned pcode[PPT];
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        pcode[i] = act ? pair_entry<N>(q, i) : 0u;
-        spair[i] = act ? tb.S[(pcode[i] >> 11) & 7][(pcode[i] >> 14) & 7] : 0.0;
-        asm volatile("" : "+v"(spair[i]));
-    }
+    for (int i = 0; i < PPT; ++i) pcode[i] = act ? pair_entry<N>(q, i) : 0u;
     if (act) {
         // issue the independent global loads first
 #pragma unroll
@@ -1060,7 +1043,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             const int ql = c & 31, qk = (c >> 5) & 31, d = (c >> 10) & 1;
             const int p = q + i * NN;
             const int rn = 1 + d, rt = 2 - d;
-            const double scale = spair[i] * (d ? hh[1] : hh[0]);
+            const double scale = sS[(c >> 11) & 7][(c >> 14) & 7] * (d ? hh[1] : hh[0]);
             const double L0 = sR[le][0][ql], Ln = sR[le][rn][ql], Lt = sR[le][rt][ql], L3 = sR[le][3][ql];
             const double L5 = sR[le][5][ql], L6 = sR[le][6][ql], L7 = sR[le][7][ql];
             const double R0 = sR[le][0][qk], Rn = sR[le][rn][qk], Rt = sR[le][rt][qk], R3 = sR[le][3][qk];
@@ -1269,7 +1252,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     if (b < N) r -= sPair[le][v][NF + fyt];
                     r += dS0[v] + dS1[v];
                 }
-                A.uout[((size_t)e * 4 + v) * NN + q] = r * im;
+                A.uout[((unsigned)e * 4u + v) * NN + q] = r * im;
             }
         }
         return;
@@ -1400,7 +1383,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const size_t idx = ((size_t)e * 4 + v) * NN + q;
+            const unsigned idx = ((unsigned)e * 4u + v) * NN + q;
             double r = A.b * uvol[v];
             if (A.a != 0.0) r += A.a * un4[v];
             A.uout[idx] = r;
@@ -1738,12 +1721,17 @@ __global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
     __shared__ double sMl[EPB][8 * n];  // wave speeds across mortars, staged per position
     constexpr int NW = G::BS / 64;  // waves per block
     __shared__ double sRed[NW];
+    __shared__ double sTw[2][n];  // LGL weights and their reciprocals, read per lane
     const Tab<N>& tb = T<N>();
     const double g = A.gamma;
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
     const int e = blockIdx.x * EPB + le;
     const bool act = tid < NT && e < A.E;
+    if (tid < n) {
+        sTw[0][tid] = tb.w[tid];
+        sTw[1][tid] = tb.winv[tid];
+    }
     const bool idp = A.mode != DGIDP_DT_LOWORDER;
     const bool fnode = act && idp && q < NFN;
     const int ff = q / n, fk = q - (q / n) * n, dff = ff >> 1;
@@ -1795,7 +1783,7 @@ __global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
         const double lm = sL[le][dff][face_q<N>(ff, fk)];
         double sum = 0.0;
         if (code < 0) {
-            sum = 2.0 * pick(tb.w, fk) * hf * 0.25 * fmax(lm, lo_nb);
+            sum = 0.5 * sTw[0][fk] * hf * fmax(lm, lo_nb);
         } else if (!fm_small(code)) {
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh)
@@ -1821,19 +1809,20 @@ __global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
     if (act) {
         const double lx = sL[le][0][q], ly = sL[le][1][q];
         if (!idp) {
-            s = (N + 1) * (lx / hx + ly / hy);
+            s = (N + 1) * (lx * frcp(hx) + ly * frcp(hy));
         } else {
+            // edges along x carry 2 |c| = w_b h_y / 2, along y w_a h_x / 2
+            const double cx = 0.5 * sTw[0][b] * hy, cy = 0.5 * sTw[0][a] * hx;
             double sum = 0.0;
-            const double wa = pick(tb.w, a), wb = pick(tb.w, b);
-            if (a > 0) sum += 2.0 * wb * hy * 0.25 * fmax(lx, sL[le][0][q - 1]);
-            if (a < N) sum += 2.0 * wb * hy * 0.25 * fmax(lx, sL[le][0][q + 1]);
-            if (b > 0) sum += 2.0 * wa * hx * 0.25 * fmax(ly, sL[le][1][q - n]);
-            if (b < N) sum += 2.0 * wa * hx * 0.25 * fmax(ly, sL[le][1][q + n]);
+            if (a > 0) sum += cx * fmax(lx, sL[le][0][q - 1]);
+            if (a < N) sum += cx * fmax(lx, sL[le][0][q + 1]);
+            if (b > 0) sum += cy * fmax(ly, sL[le][1][q - n]);
+            if (b < N) sum += cy * fmax(ly, sL[le][1][q + n]);
             if (a == 0) sum += sF[le][0 * n + b];
             if (a == N) sum += sF[le][1 * n + b];
             if (b == 0) sum += sF[le][2 * n + a];
             if (b == N) sum += sF[le][3 * n + a];
-            s = sum * 4.0 / (hx * hy) * pick(tb.winv, a) * pick(tb.winv, b);
+            s = sum * (4.0 * frcp(hx * hy)) * sTw[1][a] * sTw[1][b];
         }
     }
     s = wave_max(s);
