@@ -159,6 +159,19 @@ __device__ __forceinline__ double fsqrt(double y)
     return y == 0.0 ? 0.0 : g;
 }
 
+// two FP32 values in one FP64 LDS slot (register moves only)
+struct F2 {
+    float x, y;
+};
+__device__ __forceinline__ double pack2(float x, float y)
+{
+    return __hiloint2double(__float_as_int(y), __float_as_int(x));
+}
+__device__ __forceinline__ F2 unpack2(double d)
+{
+    return F2{__int_as_float(__double2loint(d)), __int_as_float(__double2hiint(d))};
+}
+
 struct NodeP {
     double u[4];
     double r, v1, v2, p, c;
@@ -788,18 +801,29 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             u0[v] = me.u[v];
         }
         // the logarithms feed only the two-point volume fluxes: FP32 in the
-        // mixed mode (exactly representable in the FP64 slots)
-        const double lr = MIXED ? (double)__logf((float)me.r) : flog(me.r);
+        // mixed mode, where rows 5-7 hold the FP32 operands of those fluxes in
+        // pairs (rho, p), (ln rho, z), (ln z, 0)
         const double z = me.r * frcp(me.p);
         sR[le][0][q] = me.r;
         sR[le][1][q] = me.v1;
         sR[le][2][q] = me.v2;
         sR[le][3][q] = me.p;
         sR[le][4][q] = me.c;
-        sR[le][5][q] = lr;
-        sR[le][6][q] = z;
-        const double lz = MIXED ? (double)__logf((float)z) : flog(z);
-        sR[le][7][q] = lz;
+        double lr, lz;
+        if (MIXED) {
+            const float lrf = __logf((float)me.r), lzf = __logf((float)z);
+            lr = lrf;
+            lz = lzf;
+            sR[le][5][q] = pack2((float)me.r, (float)me.p);
+            sR[le][6][q] = pack2(lrf, (float)z);
+            sR[le][7][q] = pack2(lzf, 0.0f);
+        } else {
+            lr = flog(me.r);
+            lz = flog(z);
+            sR[le][5][q] = lr;
+            sR[le][6][q] = z;
+            sR[le][7][q] = lz;
+        }
         // the blend needs local factors only where the indicator fires, and at
         // mortar nodes (their mortar may blend with another element's weight)
         need_loc = LOC && (!COMB || w_e > 0.0 || fcode[0] >= 0 || fcode[1] >= 0 || fcode[2] >= 0 ||
@@ -1044,12 +1068,14 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             const int p = q + i * NN;
             const int rn = 1 + d, rt = 2 - d;
             const double scale = sS[(c >> 11) & 7][(c >> 14) & 7] * (d ? hh[1] : hh[0]);
-            const double L0 = sR[le][0][ql], Ln = sR[le][rn][ql], Lt = sR[le][rt][ql], L3 = sR[le][3][ql];
-            const double L5 = sR[le][5][ql], L6 = sR[le][6][ql], L7 = sR[le][7][ql];
-            const double R0 = sR[le][0][qk], Rn = sR[le][rn][qk], Rt = sR[le][rt][qk], R3 = sR[le][3][qk];
-            const double R5 = sR[le][5][qk], R6 = sR[le][6][qk], R7 = sR[le][7][qk];
+            const double Ln = sR[le][rn][ql], Lt = sR[le][rt][ql];
+            const double Rn = sR[le][rn][qk], Rt = sR[le][rt][qk];
             double f0, fn, ft, f3;
             if (!MIXED) {
+                const double L0 = sR[le][0][ql], L3 = sR[le][3][ql];
+                const double L5 = sR[le][5][ql], L6 = sR[le][6][ql], L7 = sR[le][7][ql];
+                const double R0 = sR[le][0][qk], R3 = sR[le][3][qk];
+                const double R5 = sR[le][5][qk], R6 = sR[le][6][qk], R7 = sR[le][7][qk];
                 const double iz_ln = inv_lnmean(L6, R6, L7, R7);
                 const double vna = 0.5 * (Ln + Rn), vta = 0.5 * (Lt + Rt);
                 const double fr = lnmean(L0, R0, L5, R5) * vna;
@@ -1067,14 +1093,17 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     f3 = fr * (0.5 * (Ln * Rn + Lt * Rt) + ig1 * iz_ln) + 0.5 * (L3 * Rn + R3 * Ln);
                 }
             } else {
-                const float iz_ln = inv_lnmeanf((float)L6, (float)R6, (float)L7, (float)R7);
+                const F2 L5 = unpack2(sR[le][5][ql]), L6 = unpack2(sR[le][6][ql]);
+                const F2 R5 = unpack2(sR[le][5][qk]), R6 = unpack2(sR[le][6][qk]);
+                const float L7 = unpack2(sR[le][7][ql]).x, R7 = unpack2(sR[le][7][qk]).x;
+                const float rL = L5.x, rR = R5.x, pL = L5.y, pR = R5.y, zL = L6.y, zR = R6.y;
+                const float iz_ln = inv_lnmeanf(zL, zR, L7, R7);
                 const float vnL = (float)Ln, vnR = (float)Rn, vtL = (float)Lt, vtR = (float)Rt;
-                const float pL = (float)L3, pR = (float)R3;
                 const float vna = 0.5f * (vnL + vnR), vta = 0.5f * (vtL + vtR);
-                const float fr = lnmeanf((float)L0, (float)R0, (float)L5, (float)R5) * vna;
+                const float fr = lnmeanf(rL, rR, L6.x, R6.x) * vna;
                 f0 = fr;
                 if (A.vflux == DGIDP_FLUX_CHANDRASHEKAR) {
-                    const float pt = ((float)L0 + (float)R0) / ((float)L6 + (float)R6);
+                    const float pt = (rL + rR) / (zL + zR);
                     const float fnf = fr * vna + pt, ftf = fr * vta;
                     fn = fnf;
                     ft = ftf;
