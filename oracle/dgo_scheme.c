@@ -415,6 +415,16 @@ double dgo_max_dt(const dgo_mesh* m, const double* u, double cfl, int mode, doub
 /* density increments (per node and step) this small relative to the density are
    not limited against the local density bounds */
 #define LOCAL_NEGL 1e-14
+/* With bounds from the low-order solution the entropy target never lies above
+   the node's own low-order state: it is the smaller of the margin-raised bound
+   and the node's low-order specific entropy lowered by a relative 2^-41 (volume
+   step) or 2^-40 (mortar step).  Eq. Bounds_LowOrder includes the node itself
+   in the neighbourhood, so where it is the minimum the raised bound would lie
+   above the state the limiter starts from, and the factor would be 0 or full by
+   the sign of a rounding error.  (With bar states the node's own entry is its
+   input state, not u^FV: no cap.) */
+#define OWN_SLACK_VOL (1.0 - 0x1p-41)
+#define OWN_SLACK_MORT (1.0 - 0x1p-40)
 
 /* largest theta in [0,1] with rho(u0 + theta dc) > 0 and p(u0 + theta dc) >= pt.
    With rho > 0, p >= pt  <=>  g(theta) = (E - pt/(gamma-1)) rho - |m|^2/2 >= 0,
@@ -770,8 +780,9 @@ void dgo_shock_indicator(const dgo_mesh* m, const double* u, double gamma, doubl
    the ceiling), the pressure root per face and, with loc, the entropy root per
    face, the last two on Gamma = 4-scaled increments. */
 static double volume_node_factor(const double* q, double cf[4][4], int nf, double rfloor, double pfloor,
-                                 int loc, double rceil, double sm, double gamma)
+                                 int loc, double rceil, double sm, int cap, double gamma)
 {
+    /* (q is the node's low-order state u^FV; cap: entropy target capped by it) */
     double rt = rfloor * BOUND_MARGIN, pt = pfloor * BOUND_MARGIN;
     /* Zalesak: the sum of the negative (positive) density increments may use
        at most the distance to the lower (upper) bound */
@@ -802,20 +813,26 @@ static double volume_node_factor(const double* q, double cf[4][4], int nf, doubl
         double tp = dgo_theta_pressure(q, dc, pt, gamma);
         if (tp < t) t = tp;
     }
-    /* entropy: per face on [0, t] */
-    if (loc)
+    /* entropy: per face on [0, t], target capped by the node's own entropy */
+    if (loc) {
+        double st = sm * BOUND_MARGIN;
+        const double own = dgo_spec_entropy(q, gamma) * OWN_SLACK_VOL;
+        if (cap && own < st) st = own;
         for (int j = 0; j < nf; ++j) {
             double dc[4];
             for (int v = 0; v < 4; ++v) dc[v] = 4.0 * cf[j][v];
-            t = dgo_theta_entropy(q, dc, sm * BOUND_MARGIN, gamma, t);
+            t = dgo_theta_entropy(q, dc, st, gamma, t);
         }
+    }
     return t;
 }
 
 /* Factor of one mortar node with its n_i-scaled increment dc: density floor
-   (and ceiling), pressure root, entropy root, against half the volume margin. */
+   (and ceiling), pressure root, entropy root, against half the volume margin;
+   q is u^vol, sfv the specific entropy of the node's low-order state (the cap
+   of the entropy target). */
 static double mortar_node_factor(const double* q, const double* dc, double rfloor, double pfloor, int loc,
-                                 double rceil, double sm, double gamma)
+                                 double rceil, double sm, double sfv, double gamma)
 {
     double rt = rfloor * MORTAR_MARGIN, pt = pfloor * MORTAR_MARGIN;
     double tn = 1.0;
@@ -832,7 +849,11 @@ static double mortar_node_factor(const double* q, const double* dc, double rfloo
     }
     double tp = dgo_theta_pressure(q, dc, pt, gamma);
     if (tp < tn) tn = tp;
-    if (loc) tn = dgo_theta_entropy(q, dc, sm * MORTAR_MARGIN, gamma, tn);
+    if (loc) {
+        double st = sm * MORTAR_MARGIN;
+        if (sfv * OWN_SLACK_MORT < st) st = sfv * OWN_SLACK_MORT;
+        tn = dgo_theta_entropy(q, dc, st, gamma, tn);
+    }
     return tn;
 }
 
@@ -888,6 +909,7 @@ int dgo_fe_step_detail(const dgo_mesh* m, const double* u, double dt, double gam
     const int comb = limiter == LIM_COMBINED;
     const int pure_local = limiter == LIM_LOCAL || limiter == LIM_LOCAL_LO;
     const int local = pure_local || comb;
+    const int cap_own = limiter == LIM_LOCAL_LO;
     double *rlo = 0, *rhi = 0, *smin = 0, *ind = 0;
     if (local) {
         rlo = (double*)malloc(sizeof(double) * E * nn);
@@ -990,11 +1012,11 @@ int dgo_fe_step_detail(const dgo_mesh* m, const double* u, double dt, double gam
                 if (b < N) { for (int v = 0; v < 4; ++v) cf[nf][v] = -dt / mi * Ay[a][b][v]; nf++; }
                 int64_t i = e * nn + b * n + a;
                 if (pure_local) {
-                    th[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
+                    th[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], cap_own, gamma);
                 } else {
-                    th[b][a] = volume_node_factor(q, cf, nf, rmin[i], pmin[i], 0, 0.0, 0.0, gamma);
+                    th[b][a] = volume_node_factor(q, cf, nf, rmin[i], pmin[i], 0, 0.0, 0.0, 0, gamma);
                     if (comb)
-                        thl[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
+                        thl[b][a] = volume_node_factor(q, cf, nf, rlo[i], pmin[i], 1, rhi[i], smin[i], cap_own, gamma);
                 }
             }
         /* face factor: the smaller node factor of its two nodes, combined:
@@ -1079,12 +1101,18 @@ int dgo_fe_step_detail(const dgo_mesh* m, const double* u, double dt, double gam
                 }
                 /* this node's factor, then the minimum over the mortar's nodes */
                 int64_t i = e * nn + b * n + a;
+                double sfv = INFINITY;
+                if (cap_own) {
+                    double qf[4];
+                    get_node(uFV, n, e, a, b, qf);
+                    sfv = dgo_spec_entropy(qf, gamma);
+                }
                 double tn = pure_local
-                                ? mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma)
-                                : mortar_node_factor(q, dc, rmin[i], pmin[i], 0, 0.0, 0.0, gamma);
+                                ? mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], sfv, gamma)
+                                : mortar_node_factor(q, dc, rmin[i], pmin[i], 0, 0.0, 0.0, 0.0, gamma);
                 if (tn < t) t = tn;
                 if (comb) {
-                    double tnl = mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], gamma);
+                    double tnl = mortar_node_factor(q, dc, rlo[i], pmin[i], 1, rhi[i], smin[i], sfv, gamma);
                     if (tnl < tl) tl = tnl;
                 }
             }

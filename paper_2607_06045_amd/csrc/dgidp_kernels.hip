@@ -517,7 +517,8 @@ __device__ double theta_s(const double* u0, const double* dc, double lst, double
 // entropy floor lsm); the last two on Gamma = 4-scaled increments.
 template <bool LOCB>
 __device__ __forceinline__ double volume_factor(const double* uFV, const double (&cf)[4][4], double rfl,
-                                                double pfl, double rce, double lsm, double g, double ig1)
+                                                double pfl, double rce, double lsm, double lsi, double g,
+                                                double ig1)
 {
     const double rt = rfl * kMargin, pt = pfl * kMargin;
     // Zalesak: the sum of the negative (positive) density increments may use at
@@ -544,9 +545,13 @@ __device__ __forceinline__ double volume_factor(const double* uFV, const double 
         const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
         th = fmin(th, theta_p(uFV, dc, pt, ig1));
     }
-    // specific entropy: per face on [0, th]
+    // specific entropy: per face on [0, th].  The target ln(s_min (1 + 2^-40))
+    // is capped at lsi lowered by 2^-41: with bounds from the low-order solution
+    // lsi is the node's own low-order log entropy (where the node itself is the
+    // minimum of its neighbourhood, the raised bound would lie above the state
+    // the limiter starts from); with bar states lsi = +inf (no cap)
     if (LOCB) {
-        const double lst = lsm + 0x1p-40;  // ln(s_min (1 + 2^-40))
+        const double lst = fmin(lsm + 0x1p-40, lsi - 0x1p-41);
 #pragma unroll 1
         for (int j = 0; j < 4; ++j) {
             const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
@@ -562,7 +567,7 @@ __device__ __forceinline__ double volume_factor(const double* uFV, const double 
 // the volume margin.
 template <bool LOCB>
 __device__ __forceinline__ double mortar_factor(const double* uvol, const double* dc, double rfl, double pfl,
-                                                double rce, double lsm, double g, double ig1)
+                                                double rce, double lsm, double lsi, double g, double ig1)
 {
     const double rt = rfl * kMarginMortar, pt = pfl * kMarginMortar;
     double ts = 1.0;
@@ -570,7 +575,7 @@ __device__ __forceinline__ double mortar_factor(const double* uvol, const double
     if (dc[0] < 0.0 && !negl) ts = fmin(ts, fmax((rt - uvol[0]) / dc[0], 0.0));
     if (LOCB && dc[0] > 0.0 && !negl) ts = fmin(ts, fmax((rce * kMarginMortarHi - uvol[0]) / dc[0], 0.0));
     ts = fmin(ts, theta_p(uvol, dc, pt, ig1));
-    if (LOCB) ts = theta_s(uvol, dc, lsm + 0x1p-41, g, ts);
+    if (LOCB) ts = theta_s(uvol, dc, fmin(lsm + 0x1p-41, lsi - 0x1p-40), g, ts);
     return ts;
 }
 
@@ -763,8 +768,11 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     int fcode_f = -1, fnb = 0, fnb2 = -1, bk = 0;
     double onb[4];  // conforming neighbour state (boundary: exterior state) across face ff at fk
     double us1[4];  // large side: the second small element's trace at position fk
-    double un4[4] = {0, 0, 0, 0};  // u^n of this node for the SSP combination
-    double u0[4] = {0, 0, 0, 0};   // this node's state (uin)
+    // u^n of this node for the SSP combination, loaded where it is needed (so
+    // that it occupies no registers through the flux phases), and this node's
+    // state (uin)
+    double un4[4] = {0, 0, 0, 0};
+    double u0[4] = {0, 0, 0, 0};
     // the low-order surface term of this lane's face node, kept in registers
     // until phase 5 frees sU, which then carries it to the node's own thread
     double fterm[4] = {0, 0, 0, 0};
@@ -789,7 +797,6 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             fnb = A.fnbr[e * 4 + ff];
             fnb2 = A.fnbr2[e * 4 + ff];
         }
-        if (MODE == MODE_STAGE && A.a != 0.0) load_u<N>(A.un, e, q, un4);
         NodeP me;
         load_node<N>(A.uin, e, q, me, g);
         hx = A.h[2 * e];
@@ -1227,6 +1234,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     __syncthreads();
 
     // ---- phase 6: low-order residual, bounds, node factors ----
+    if (act && MODE == MODE_STAGE && A.a != 0.0) load_u<N>(A.un, e, q, un4);
     const int fxl = b * N + a - 1, fxr = b * N + a;                  // x faces left / right
     const int fyb = N * n + a * N + b - 1, fyt = N * n + a * N + b;  // y faces below / above
     const bool onf[4] = {a == 0, a == N, b == 0, b == N};
@@ -1293,6 +1301,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // local bounds: density floor (the larger of the local and the positivity
     // floor), ceiling, log entropy floor; thl the local node factor of the blend
     double rlf = 0.0, rhi = 0.0, lsm = 0.0, thl = 1.0;
+    double lsi = 0.0;  // local bounds: the node's own low-order log entropy (cap of the entropy target)
     unsigned long long inad = 0;
     if (act) {
 #pragma unroll
@@ -1309,10 +1318,13 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             double rlo = fmin(A.lob[bi], uFV[0]);
             rhi = fmax(A.lob[bi + NN], uFV[0]);
             lsm = A.lob[bi + 2 * NN];
-            if (uFV[0] > 0.0 && pFV > 0.0) lsm = fmin(lsm, log(pFV) - g * log(uFV[0]));
+            lsi = uFV[0] > 0.0 && pFV > 0.0 ? log(pFV) - g * log(uFV[0]) : -__builtin_inf();
+            lsm = fmin(lsm, lsi);
             rlf = fmax(rmin, rlo);
         } else if (need_loc) {
             // bounds over the node and the bar states of its low-order neighbours
+            // (the node's own bar state is its input state: no cap)
+            lsi = __builtin_inf();
             double rlo = u0[0];
             rhi = u0[0];
             lsm = ls_own;
@@ -1362,10 +1374,10 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         }
         if (A.limiter != DGIDP_LIMIT_NONE) {
             if (PURE) {
-                th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
+                th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, lsi, g, ig1);
             } else {
-                th = volume_factor<false>(uFV, cf, rmin, pmin, 0.0, 0.0, g, ig1);
-                if (COMB && need_loc) thl = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, g, ig1);
+                th = volume_factor<false>(uFV, cf, rmin, pmin, 0.0, 0.0, 0.0, g, ig1);
+                if (COMB && need_loc) thl = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, lsi, g, ig1);
             }
         }
     }
@@ -1446,10 +1458,10 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
                     if (!fin) {
                         ts = tsl = 0.0;
                     } else if (PURE) {
-                        ts = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, g, ig1);
+                        ts = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, lsi, g, ig1);
                     } else {
-                        ts = mortar_factor<false>(uvol, dc, rmin, pmin, 0.0, 0.0, g, ig1);
-                        if (COMB) tsl = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, g, ig1);
+                        ts = mortar_factor<false>(uvol, dc, rmin, pmin, 0.0, 0.0, 0.0, g, ig1);
+                        if (COMB) tsl = mortar_factor<true>(uvol, dc, rlf, pmin, rhi, lsm, lsi, g, ig1);
                     }
                 }
                 double* S = A.slot + (size_t)(j == 0 ? slot0 : slot1) * kSlotW;

@@ -142,3 +142,48 @@ def test_lowsol_step(oracle):
     uc = states.constant(x, rho=0.8, v1=0.4, v2=-0.3, p=1.2)
     oc, _ = M.fe_step(uc, M.max_dt(uc, 0.4, mode=oracle.DT_LOWORDER), limiter=oracle.LIM_LOCAL_LO)
     assert np.abs(oc - uc).max() < 1e-13
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_entropy_target_capped_at_own_low_order_state(oracle, N):
+    """Bounds from the low-order solution contain the node's own low-order
+    state, so the node that is the entropy minimum of its neighbourhood starts
+    the limiter exactly on its bound.  With the target capped at that node's
+    own entropy (lowered by 2^-41) its factor no longer depends on the sign of a
+    rounding error: a relative 1e-16 perturbation of the input of a top-hat
+    blast stage moves the limited state by less than 1e-8 (state metric; the
+    remaining sensitivity is the entropy root in the ambient gas, where the
+    increments are isentropic to about 1e-12), and every node keeps
+    s >= min(s_min, s(u^FV)) within the 1e-12 slack of the bound check."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from parity import state_err
+    spec = random_mesh(10, 8, 2, 0.45, L=4.0, x0=-2.0, y0=-2.0)
+    M = oracle.Mesh(N, *spec.args())
+    x, y, m = M.geometry()
+    u = states.sedov_tophat(x, y, r0=0.5)
+    dt = M.max_dt(u, 0.4, mode=oracle.DT_LOWORDER)
+    w, st = M.fe_step(u, dt, limiter=oracle.LIM_LOCAL_LO)
+    assert st["violations"] == 0
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        pert = u * (1 + 1e-16 * rng.standard_normal(u.shape))
+        assert state_err(M.fe_step(pert, dt, limiter=oracle.LIM_LOCAL_LO)[0], w) < 1e-8
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_near_constant_state_is_not_limited_to_low_order(oracle, N):
+    """A state constant up to a relative 1e-12: every node is (up to rounding)
+    the entropy minimum of its neighbourhood.  With the target raised above the
+    node's own low-order entropy, every factor was 0 (the whole step low order);
+    with the cap at that entropy the factors follow the density bounds alone,
+    and no bound is violated."""
+    spec = random_mesh(3, 4, 3, 0.4)
+    M = oracle.Mesh(N, *spec.args())
+    x, y, m = M.geometry()
+    rho = 1.0 + 1e-12 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    u = states.conservative(rho, 0.3 + 0 * x, -0.2 + 0 * x, 1.0 + 0 * x, 1.4)
+    dt = M.max_dt(u, 0.4, mode=oracle.DT_LOWORDER)
+    w, st = M.fe_step(u, dt, limiter=oracle.LIM_LOCAL_LO)
+    assert st["violations"] == 0
+    assert st["alpha_vol_mean"] < 0.6 and st["alpha_mort_mean"] < 0.6
