@@ -342,12 +342,17 @@ int dgidp_features(dgidp_ctx* ctx, float* f, int on_device);
  * want a cheaper or trained AMR indicator.  Parameters, FP32, in this order:
  * W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3 (W[j][k]: unit j, input
  * k), DGIDP_MLP_NPARAM values.  The context keeps FP32 master weights and a
- * BF16 copy (round to nearest even) that every pass uses; arithmetic FP32.
- * set_weights copies host weights and resets the Adam state; get_weights
- * returns the masters (host). */
+ * BF16 copy (round to nearest even) that every pass uses.  Inference
+ * (dgidp_mlp_forward, DGIDP_IND_MLP) multiplies BF16 operands with FP32
+ * accumulation: the inputs and the first hidden layer are rounded to BF16
+ * (nearest even) before their products; biases, ReLU and the output layer are
+ * FP32.  Training (grad, train_step) runs in FP32 arithmetic on the BF16
+ * weights.  set_weights copies host weights and resets the Adam state;
+ * get_weights returns the masters (host). */
 int dgidp_mlp_set_weights(dgidp_ctx* ctx, const float* w);
 int dgidp_mlp_get_weights(dgidp_ctx* ctx, float* w);
-/* y[B] = network(x[B][16]). */
+/* y[B] = network(x[B][16]), 0 <= B <= 2^30.  Device inputs (on_device) must be
+ * 16-byte aligned, else DGIDP_E_INVALID_ARG. */
 int dgidp_mlp_forward(dgidp_ctx* ctx, const float* x, int64_t B, float* y, int on_device);
 /* Gradient of loss = (1/B) sum_s (y_s - t_s)^2 at the BF16 weights, into
  * grad[DGIDP_MLP_NPARAM] (host or device as on_device); *loss (host, may be

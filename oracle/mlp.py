@@ -17,7 +17,9 @@ Adam (Kingma and Ba 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8:
 The network is not in the paper (the learned indicator is an extension).
 Pins: the backward pass against central finite differences, the forward pass
 against a hand-set network, the first Adam step against its closed form
-(a step of lr sign(g) when |g| >> eps), BF16 rounding against exact cases.
+(a step of lr sign(g) when |g| >> eps), BF16 rounding against exact cases, the
+BF16-operand inference pass against the plain one where every operand is
+exactly representable in BF16, and against the rounding it adds elsewhere.
 """
 import numpy as np
 
@@ -66,6 +68,18 @@ def init(seed):
 def forward(w, x):
     """y[B] and the activations, with BF16-rounded weights, FP64 arithmetic."""
     return forward_params(unpack(bf16(w)), x)
+
+
+def forward_bf16(w, x):
+    """y[B] of the library's inference pass: the operands of both matrix
+    products are BF16 (the weights, the inputs and the first hidden layer,
+    rounded from its FP32 value), everything else FP64 here (FP32 there)."""
+    p = unpack(bf16(w))
+    xb = bf16(np.asarray(x, dtype=np.float32))
+    z1 = xb @ p["W1"].T + p["b1"]
+    h1 = bf16(np.maximum(z1, 0.0).astype(np.float32))
+    z2 = h1 @ p["W2"].T + p["b2"]
+    return np.maximum(z2, 0.0) @ p["W3"] + p["b3"][0]
 
 
 def forward_params(p, x):

@@ -2,6 +2,7 @@
 // and the C-ABI entry points declared in include/dgidp.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -1277,11 +1278,9 @@ int dgidp_indicator(dgidp_ctx* ctx, int kind, float* alpha, int on_device)
         MlpState* m = get_mlp(ctx);
         if (!m) return fail(ctx, DGIDP_E_DEVICE, "network buffers");
         if (!mlp_has_weights(m)) return fail(ctx, DGIDP_E_INVALID_ARG, "network weights not set");
-        float* feat = ind_staging(ctx, E * 17);
-        if (!feat) return fail(ctx, DGIDP_E_DEVICE, "staging buffer");
-        if (!on_device) out = feat + E * 16;
-        if (launch_indicator(ctx->p.N, (int)E, ctx->U, ctx->dm.perm, ctx->p.gamma, nullptr, feat, ctx->stream) ||
-            mlp_forward(m, feat, (int64_t)E, out, ctx->stream))
+        if (!on_device && !(out = ind_staging(ctx, E))) return fail(ctx, DGIDP_E_DEVICE, "staging buffer");
+        if (launch_learned_indicator(ctx->p.N, (int)E, ctx->U, ctx->dm.perm, ctx->p.gamma, mlp_weights_bf16(m), out,
+                                     ctx->stream))
             return fail(ctx, DGIDP_E_DEVICE, "indicator kernel launch failed");
     }
     if (!on_device) {
@@ -1318,6 +1317,8 @@ int dgidp_mlp_forward(dgidp_ctx* ctx, const float* x, int64_t B, float* y, int o
     if (!m) return fail(ctx, DGIDP_E_DEVICE, "network buffers");
     if (!mlp_has_weights(m)) return fail(ctx, DGIDP_E_INVALID_ARG, "network weights not set");
     if (B == 0) return 0;
+    if (on_device && (reinterpret_cast<uintptr_t>(x) & 15))
+        return fail(ctx, DGIDP_E_INVALID_ARG, "device inputs not 16-byte aligned");
     const float* dx = x;
     float* dy = y;
     if (!on_device) {

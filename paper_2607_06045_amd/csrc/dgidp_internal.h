@@ -117,6 +117,10 @@ int launch_zhang_shu(int N, int G, const int* zgrp, const double* uold, double* 
 // modal indicator alpha[E] and features feat[E][16], external order (either may be null)
 int launch_indicator(int N, int E, const double* u, const int* perm, double gamma, float* alpha,
                      float* feat, hipStream_t s);
+// learned indicator alpha[E] (external order): features and network in one kernel;
+// wb the network's BF16 parameters
+int launch_learned_indicator(int N, int E, const double* u, const int* perm, double gamma, const uint16_t* wb,
+                             float* alpha, hipStream_t s);
 
 // learned indicator network (dgidp_mlp.hip); device pointers on stream st
 struct MlpState;
@@ -127,6 +131,7 @@ bool mlp_has_weights(const MlpState* s);
 float* mlp_scratch(MlpState* s, int which, size_t floats);  // which in 0..3, grown on demand
 int mlp_set_weights(MlpState* s, const float* host_w, hipStream_t st);
 int mlp_get_weights(MlpState* s, float* host_w, hipStream_t st);
+const uint16_t* mlp_weights_bf16(const MlpState* s);  // device, DGIDP_MLP_NPARAM values and a zero tail to 5,320
 int mlp_forward(MlpState* s, const float* x, int64_t B, float* y, hipStream_t st);
 // gradient (to grad, if not null) and loss (to *loss_host, if not null); an
 // Adam step when lr > 0

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dgidp_internal.h"
+#include "dgidp_mlp_dev.h"
 
 namespace dgidp {
 
@@ -1883,25 +1884,48 @@ __global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// modal indicator and features: one thread per node stages rho p, rho and p,
-// one thread per mode (i, j) forms its squared orthonormal-Legendre
-// coefficient, and one thread per element reduces the shells.
+// modal indicator (k_indicator), features and the learned indicator
+// (k_features).  Squared orthonormal-Legendre coefficients of a staged nodal
+// quantity q[b'][a'], one thread per mode (i, j) = (a, b) of an element, in
+// two sum-factorised passes through LDS:
+//   r[b'][i] = sum_a' Vinv[i][a'] q[b'][a'],   m[j][i] = sum_b' Vinv[j][b'] r[b'][i]
+// (n reads per thread and pass instead of n^2).
 //  Hennemann indicator on rho p: energy = max of the energy fractions of the
 //  highest and the second-highest mode shells, alpha = logistic with threshold
 //  T = 0.5 10^(-1.8 (N+1)^(1/4)) and sharpness ln(9999), zero below 1e-3,
 //  capped at 0.5.
 //  Features: x- and y-shell energy fractions of rho and of p for the shells
-//  N-3 .. N (16 values).
+//  N-3 .. N (16 values), one lane per feature.
 // Outputs (FP32) go to the external element order through perm.
 // ---------------------------------------------------------------------------
 template <int N>
+__device__ __forceinline__ double modal_x(const Tab<N>& tb, const double* Q, int a, int b)
+{
+    constexpr int n = N + 1;
+    double r = 0.0;
+#pragma unroll
+    for (int aa = 0; aa < n; ++aa) r += tb.Vinv[a][aa] * Q[b * n + aa];
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ double modal_y_sq(const Tab<N>& tb, const double* Rx, int a, int b)
+{
+    constexpr int n = N + 1;
+    double m = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < n; ++bb) m += tb.Vinv[b][bb] * Rx[bb * n + a];
+    return m * m;
+}
+
+template <int N>
 __global__ __launch_bounds__(128) void k_indicator(const double* __restrict__ u, int E,
                                                    const int* __restrict__ perm, double gamma,
-                                                   float* alpha, float* feat)
+                                                   float* __restrict__ alpha)
 {
     constexpr int n = N + 1, NN = n * n, EPB = 128 / NN;
-    __shared__ double sQ[3][EPB][NN];
-    __shared__ double sM[3][EPB][NN];
+    __shared__ double sQ[EPB][NN];
+    __shared__ double sR[EPB][NN];
     const Tab<N>& tb = T<N>();
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
@@ -1911,72 +1935,168 @@ __global__ __launch_bounds__(128) void k_indicator(const double* __restrict__ u,
         double w[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) w[v] = u[((size_t)e * 4 + v) * NN + q];
-        const double p = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
-        sQ[0][le][q] = w[0] * p;
-        sQ[1][le][q] = w[0];
-        sQ[2][le][q] = p;
+        sQ[le][q] = w[0] * (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
     }
     __syncthreads();
-    if (act) {
-        // mode (i, j) = (a, b): m = sum_b' Vinv[j][b'] sum_a' Vinv[i][a'] q[b'][a']
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double m = 0.0;
-#pragma unroll
-            for (int bb = 0; bb < n; ++bb) {
-                double r = 0.0;
-#pragma unroll
-                for (int aa = 0; aa < n; ++aa) r += tb.Vinv[a][aa] * sQ[k][le][bb * n + aa];
-                m += tb.Vinv[b][bb] * r;
-            }
-            sM[k][le][q] = m * m;
-        }
-    }
+    if (act) sR[le][q] = modal_x<N>(tb, sQ[le], a, b);
+    __syncthreads();
+    if (act) sQ[le][q] = modal_y_sq<N>(tb, sR[le], a, b);  // sQ now holds m^2
     __syncthreads();
     if (!act || q != 0) return;
-    const int x = perm[e];
-    if (alpha) {
-        double all = 0.0, low1 = 0.0, low2 = 0.0;
-        for (int j = 0; j < n; ++j)
-            for (int i = 0; i < n; ++i) {
-                const double m2 = sM[0][le][j * n + i];
-                all += m2;
-                if (i < N && j < N) low1 += m2;
-                if (i < N - 1 && j < N - 1) low2 += m2;
-            }
-        const double en = fmax((all - low1) / all, (low1 - low2) / low1);
-        const double T = 0.5 * pow(10.0, -1.8 * sqrt(sqrt((double)(N + 1))));
-        const double s = log((1.0 - 1e-4) / 1e-4);
-        double al = 1.0 / (1.0 + exp(-(s / T) * (en - T)));
-        if (al < 1e-3) al = 0.0;
-        alpha[x] = (float)fmin(al, 0.5);
-    }
-    if (feat) {
-        for (int k = 1; k < 3; ++k) {
-            double tot = 0.0;
-            for (int i = 0; i < NN; ++i) tot += sM[k][le][i];
-            for (int sh = 0; sh < 4; ++sh) {
-                const int kk = N - 3 + sh;
-                double xs = 0.0, ys = 0.0;
-                for (int j = 0; j < n; ++j) {
-                    xs += sM[k][le][j * n + kk];  // x mode kk, all y modes j
-                    ys += sM[k][le][kk * n + j];  // y mode kk, all x modes j
-                }
-                feat[(size_t)x * 16 + (k - 1) * 8 + sh] = (float)(xs / tot);
-                feat[(size_t)x * 16 + (k - 1) * 8 + 4 + sh] = (float)(ys / tot);
-            }
+    double all = 0.0, low1 = 0.0, low2 = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            const double m2 = sQ[le][j * n + i];
+            all += m2;
+            if (i < N && j < N) low1 += m2;
+            if (i < N - 1 && j < N - 1) low2 += m2;
+        }
+    const double en = fmax((all - low1) / all, (low1 - low2) / low1);
+    const double T = 0.5 * pow(10.0, -1.8 * sqrt(sqrt((double)(N + 1))));
+    const double s = log((1.0 - 1e-4) / 1e-4);
+    double al = 1.0 / (1.0 + exp(-(s / T) * (en - T)));
+    if (al < 1e-3) al = 0.0;
+    alpha[perm[e]] = (float)fmin(al, 0.5);
+}
+
+// Features of a tile of TE elements per 256-thread block, in rounds of
+// 256 / (N+1)^2 elements (one thread per node); the tile's state is loaded
+// before its first round.  Each feature takes one lane: its shell sum of n
+// squared modes; the 16 lanes of an element are consecutive lanes of one wave
+// and form the total energy of each quantity from the x-shell sums with three
+// butterfly steps.  NET = false writes the features; NET = true keeps them in
+// LDS and wave 0 runs the network on the tile (the matrix-core pass of
+// mlp::forward32: features rounded to FP32, then to BF16; weights staged once
+// per block in LDS).
+template <int N>
+struct FeatGeom {
+    static constexpr int NN = (N + 1) * (N + 1), CH = 256 / NN;
+    static constexpr int R = (32 / CH) < 1 ? 1 : 32 / CH;  // rounds: 3 at N = 4, 2 at N = 3
+    static constexpr int TE = R * CH;                       // 30 at N = 4, 32 at N = 3
+};
+
+template <int N, bool NET>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7), amdgpu_num_vgpr(64))) void k_features(
+    const double* __restrict__ u, int E, const int* __restrict__ perm, double gamma,
+    const uint16_t* __restrict__ wb, float* __restrict__ out)
+{
+    using G = FeatGeom<N>;
+    constexpr int n = N + 1, NN = G::NN, CH = G::CH, R = G::R, TE = G::TE;
+    static_assert(TE <= 32 && N >= 3, "one wave of the network pass per tile; shells N-3 .. N");
+    __shared__ double sQ[2][CH][NN];  // nodal values, then squared modes
+    __shared__ double sR[2][CH][NN];  // x pass
+    __shared__ __align__(16) float sX[NET ? 32 : 1][mlp::kNin + 4];
+    __shared__ __align__(16) mlp::LdsWeights sW[1];  // not allocated when NET is false (unused)
+    const Tab<N>& tb = T<N>();
+    const int tid = threadIdx.x;
+    const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
+    const int fe = tid >> 4, f = tid & 15;
+    // feature f of element fe: quantity f / 8 (rho, p), direction (f / 4) % 2
+    // (x shells: sums over the y modes, y shells: over the x modes), shell N - 3 + f % 4
+    const int fk = f >> 3, kk = N - 3 + (f & 3);
+    const bool ydir = (f >> 2) & 1;
+    const int e0 = blockIdx.x * TE;
+    // the weights are staged first (their loads are issued before the state's);
+    // the rounds' barriers order the staging before the network pass
+    if (NET) mlp::stage_weights(sW[0], wb, tid, 256);
+    double w[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = e0 + r * CH + le;
+        if (tid < CH * NN && e < E) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) w[r][v] = u[((size_t)e * 4 + v) * NN + q];
         }
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool act = tid < CH * NN && e0 + r * CH + le < E;
+        if (act) {
+            const double p = (gamma - 1.0) * (w[r][3] - 0.5 * (w[r][1] * w[r][1] + w[r][2] * w[r][2]) / w[r][0]);
+            sQ[0][le][q] = w[r][0];
+            sQ[1][le][q] = p;
+        }
+        __syncthreads();
+        if (act) {
+            sR[0][le][q] = modal_x<N>(tb, sQ[0][le], a, b);
+            sR[1][le][q] = modal_x<N>(tb, sQ[1][le], a, b);
+        }
+        __syncthreads();
+        if (act) {  // sQ now holds m^2
+            sQ[0][le][q] = modal_y_sq<N>(tb, sR[0][le], a, b);
+            sQ[1][le][q] = modal_y_sq<N>(tb, sR[1][le], a, b);
+        }
+        __syncthreads();
+        if (fe < CH) {  // whole 16-lane groups
+            const int e = e0 + r * CH + fe;
+            const bool ok = e < E;
+            double sh = 0.0, part = 0.0;
+            if (ok) {
+                const double* m2 = sQ[fk][fe];
+#pragma unroll
+                for (int j = 0; j < n; ++j) sh += ydir ? m2[kk * n + j] : m2[j * n + kk];
+                if (!ydir) {
+                    part = sh;
+                    // the x shells below N - 3 (one at N = 4) enter the total by lane N - 3
+                    if ((f & 3) == 0)
+#pragma unroll
+                        for (int c0 = 0; c0 < N - 3; ++c0)
+#pragma unroll
+                            for (int j = 0; j < n; ++j) part += m2[j * n + c0];
+                }
+            }
+            part += __shfl_xor(part, 1, 64);
+            part += __shfl_xor(part, 2, 64);
+            part += __shfl_xor(part, 4, 64);
+            const float v = ok ? (float)(sh / part) : 0.0f;
+            if (!NET && ok) out[(size_t)perm[e] * 16 + f] = v;
+            if (NET) sX[r * CH + fe][f] = v;
+        }
+        // the next round's staging overwrites sQ (and the network pass reads sX):
+        // the reads and writes above are done
+        if (NET || r + 1 < R) __syncthreads();
+    }
+    if (!NET || tid >= 64) return;
+    const int c = tid & 31, hf = tid >> 5;
+    float xv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xv[t] = c < TE ? sX[c][hf * 8 + t] : 0.0f;
+    const float y = mlp::forward32(sW[0], mlp::pack_bf16x8(xv), tid);
+    if (hf == 0 && c < TE && e0 + c < E) out[perm[e0 + c]] = y;
+}
+
+template <int N, bool NET>
+static void launch_features(int E, const double* u, const int* perm, double gamma, const uint16_t* wb, float* out,
+                            hipStream_t s)
+{
+    const int ntiles = (E + FeatGeom<N>::TE - 1) / FeatGeom<N>::TE;
+    hipLaunchKernelGGL((k_features<N, NET>), dim3(ntiles), dim3(256), 0, s, u, E, perm, gamma, wb, out);
 }
 
 int launch_indicator(int N, int E, const double* u, const int* perm, double gamma, float* alpha,
                      float* feat, hipStream_t s)
 {
     if (E <= 0) return 0;
-    const int EPB = 128 / ((N + 1) * (N + 1));
-    const int grid = (E + EPB - 1) / EPB;
-    if (N == 3) hipLaunchKernelGGL(k_indicator<3>, dim3(grid), dim3(128), 0, s, u, E, perm, gamma, alpha, feat);
-    else if (N == 4) hipLaunchKernelGGL(k_indicator<4>, dim3(grid), dim3(128), 0, s, u, E, perm, gamma, alpha, feat);
+    if (N != 3 && N != 4) return -1;
+    if (alpha) {
+        const int EPB = 128 / ((N + 1) * (N + 1));
+        const int grid = (E + EPB - 1) / EPB;
+        if (N == 3) hipLaunchKernelGGL(k_indicator<3>, dim3(grid), dim3(128), 0, s, u, E, perm, gamma, alpha);
+        else hipLaunchKernelGGL(k_indicator<4>, dim3(grid), dim3(128), 0, s, u, E, perm, gamma, alpha);
+    }
+    if (feat) {
+        if (N == 3) launch_features<3, false>(E, u, perm, gamma, nullptr, feat, s);
+        else launch_features<4, false>(E, u, perm, gamma, nullptr, feat, s);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_learned_indicator(int N, int E, const double* u, const int* perm, double gamma, const uint16_t* wb,
+                             float* alpha, hipStream_t s)
+{
+    if (E <= 0) return 0;
+    if (N == 3) launch_features<3, true>(E, u, perm, gamma, wb, alpha, s);
+    else if (N == 4) launch_features<4, true>(E, u, perm, gamma, wb, alpha, s);
     else return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1985,7 +2105,8 @@ int launch_indicator(int N, int E, const double* u, const int* perm, double gamm
 // shock indicator of combined limiting (Sec. 3.5): the Hennemann indicator on
 // the pressure, not capped, FP64, one value per element in internal order.
 // One thread per node stages p, one thread per mode (i, j) forms its squared
-// orthonormal-Legendre coefficient, thread 0 of the element reduces.
+// orthonormal-Legendre coefficient (the two passes of modal_x and modal_y_sq),
+// thread 0 of the element reduces.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(128) void k_shock_indicator(const double* __restrict__ u, int E, double gamma,
@@ -1993,7 +2114,7 @@ __global__ __launch_bounds__(128) void k_shock_indicator(const double* __restric
 {
     constexpr int n = N + 1, NN = n * n, EPB = 128 / NN;
     __shared__ double sP[EPB][NN];
-    __shared__ double sM2[EPB][NN];
+    __shared__ double sR[EPB][NN];
     const Tab<N>& tb = T<N>();
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
@@ -2006,23 +2127,15 @@ __global__ __launch_bounds__(128) void k_shock_indicator(const double* __restric
         sP[le][q] = (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
     }
     __syncthreads();
-    if (act) {
-        double m = 0.0;
-#pragma unroll
-        for (int bb = 0; bb < n; ++bb) {
-            double r = 0.0;
-#pragma unroll
-            for (int aa = 0; aa < n; ++aa) r += tb.Vinv[a][aa] * sP[le][bb * n + aa];
-            m += tb.Vinv[b][bb] * r;
-        }
-        sM2[le][q] = m * m;
-    }
+    if (act) sR[le][q] = modal_x<N>(tb, sP[le], a, b);
+    __syncthreads();
+    if (act) sP[le][q] = modal_y_sq<N>(tb, sR[le], a, b);  // sP now holds m^2
     __syncthreads();
     if (!act || q != 0) return;
     double all = 0.0, low1 = 0.0, low2 = 0.0;
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) {
-            const double m2 = sM2[le][j * n + i];
+            const double m2 = sP[le][j * n + i];
             all += m2;
             if (i < N && j < N) low1 += m2;
             if (i < N - 1 && j < N - 1) low2 += m2;

@@ -1,6 +1,8 @@
 // Learned troubled-cell / AMR indicator for gfx950: a 16 -> 64 -> 64 -> 1 ReLU
-// network with BF16 weights (FP32 arithmetic), MSE loss and Adam on FP32
-// master weights.
+// network with BF16 weights, MSE loss and Adam on FP32 master weights.
+// Inference multiplies BF16 operands (weights, inputs, first hidden layer) on
+// the matrix cores with FP32 accumulation; training runs in FP32 arithmetic on
+// the BF16 weights.
 //
 // Parameter vector (5313 floats): W1[64][16], b1[64], W2[64][64], b2[64],
 // W3[64], b3 (W[j][k]: output unit j, input k).  The device keeps the FP32
@@ -8,8 +10,8 @@
 // forward and backward passes read; the gradient is taken at the BF16 weights
 // and applied to the masters.
 //
-//  k_mlp_forward   one thread per sample, weights staged once per block in LDS
-//                  (every lane of a wave reads the same weight: broadcast)
+//  k_mlp_forward   inference on the matrix cores (BF16 products, FP32
+//                  accumulation), 32 samples per wave
 //  k_mlp_grad      64 samples per pass, 256 threads: forward and backward
 //                  vectors of the samples in LDS (four threads per sample, 16
 //                  hidden units each), then each thread owns every 256th
@@ -25,26 +27,17 @@
 #include <string>
 
 #include "dgidp_internal.h"
+#include "dgidp_mlp_dev.h"
 
 namespace dgidp {
 
 namespace {
 
-constexpr int kNin = 16, kNh = 64;
-constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 5248, kOffB3 = 5312;
-constexpr int kNP = 5313;
+using namespace mlp;
+
 constexpr int kRow = kNP + 1;   // partial row: gradient, then the loss sum
 constexpr int kGS = 64;         // samples per pass of the gradient kernel
 constexpr int kMaxGradBlocks = 1024;
-
-__device__ __forceinline__ uint16_t bf16_rne(float f)
-{
-    uint32_t b = __float_as_uint(f);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
-
-__device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __global__ __launch_bounds__(256) void k_mlp_round(const float* __restrict__ master,
                                                    uint16_t* __restrict__ wb)
@@ -53,33 +46,40 @@ __global__ __launch_bounds__(256) void k_mlp_round(const float* __restrict__ mas
     if (p < kNP) wb[p] = bf16_rne(master[p]);
 }
 
+// inference: 32 samples per wave (the matrix-core pass of forward32), four
+// waves per block sharing one LDS copy of the weights; each wave loops over
+// its tiles
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ x, int B,
                                                      const uint16_t* __restrict__ wb,
                                                      float* __restrict__ y)
 {
-    __shared__ float sw[kNP];
-    for (int p = threadIdx.x; p < kNP; p += blockDim.x) sw[p] = bf16_f(wb[p]);
+    __shared__ __align__(16) LdsWeights sW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = lane & 31, hf = lane >> 5;
+    stage_weights(sW, wb, threadIdx.x, 256);
     __syncthreads();
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= B) return;
-    float xi[kNin], h1[kNh];
+    const int ntiles = (B + 31) / 32;
+#pragma unroll 1
+    for (int tile = blockIdx.x * 4 + wv; tile < ntiles; tile += gridDim.x * 4) {
+        const int s = tile * 32 + c;
+        float v[8];
+        if (s < B) {
+            const float4 p0 = *(const float4*)(x + (size_t)s * kNin + hf * 8);
+            const float4 p1 = *(const float4*)(x + (size_t)s * kNin + hf * 8 + 4);
+            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+        } else {
 #pragma unroll
-    for (int k = 0; k < kNin; ++k) xi[k] = x[(size_t)s * kNin + k];
-#pragma unroll
-    for (int j = 0; j < kNh; ++j) {
-        float z = sw[kOffB1 + j];
-#pragma unroll
-        for (int k = 0; k < kNin; ++k) z = fmaf(sw[kOffW1 + j * kNin + k], xi[k], z);
-        h1[j] = fmaxf(z, 0.0f);
+            for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+        }
+        // an opaque zero offset keeps the weight reads inside the loop (hoisted,
+        // they would hold some 140 registers)
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        const LdsWeights& L = *reinterpret_cast<const LdsWeights*>(reinterpret_cast<const char*>(&sW) + z);
+        const float o = forward32(L, pack_bf16x8(v), lane);
+        if (hf == 0 && s < B) y[s] = o;
     }
-    float out = sw[kOffB3];
-    for (int j = 0; j < kNh; ++j) {
-        float z = sw[kOffB2 + j];
-#pragma unroll
-        for (int k = 0; k < kNh; ++k) z = fmaf(sw[kOffW2 + j * kNh + k], h1[k], z);
-        out = fmaf(sw[kOffW3 + j], fmaxf(z, 0.0f), out);
-    }
-    y[s] = out;
 }
 
 // gradient of loss = (1/B) sum (y - t)^2 at the BF16 weights; block b handles
@@ -234,9 +234,10 @@ MlpState* mlp_create()
     if (hipMalloc((void**)&s->master, kNP * sizeof(float)) != hipSuccess ||
         hipMalloc((void**)&s->m, kNP * sizeof(float)) != hipSuccess ||
         hipMalloc((void**)&s->v, kNP * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&s->wb, kNP * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void**)&s->wb, kNPpad * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc((void**)&s->partial, (size_t)kMaxGradBlocks * kRow * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&s->loss, sizeof(float)) != hipSuccess) {
+        hipMalloc((void**)&s->loss, sizeof(float)) != hipSuccess ||
+        hipMemset(s->wb, 0, kNPpad * sizeof(uint16_t)) != hipSuccess) {
         mlp_destroy(s);
         return nullptr;
     }
@@ -291,11 +292,15 @@ int mlp_get_weights(MlpState* s, float* host_w, hipStream_t st)
     return 0;
 }
 
+const uint16_t* mlp_weights_bf16(const MlpState* s) { return s->wb; }  // kNPpad values, 16-B aligned
+
 int mlp_forward(MlpState* s, const float* x, int64_t B, float* y, hipStream_t st)
 {
     if (B <= 0) return 0;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, x, (int)B,
-                       s->wb, y);
+    // four waves (128 samples) per block and round; at most 1,024 blocks
+    const int64_t tiles = (B + 31) / 32;
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1024);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(256), 0, st, x, (int)B, s->wb, y);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -3,11 +3,16 @@ the oracle (oracle/indicator.py, oracle/mlp.py), through the C-ABI.
 
 Tolerances: outputs are FP32.  Indicator and features are computed in FP64
 and rounded once: 2^-24 relative plus FP64 round-off; the indicator's cut at
-alpha = 1e-3 is a decision, compared only away from it.  The network runs in
-FP32 with BF16 weights: a 16 + 64 + 64 term chain of FP32 sums, so outputs
-agree within 2 * 144 * 2^-24 of the absolute-value propagation of the same
-network (|W| |x| + |b| layer by layer).  Gradients are FP32 sums over the
-batch (64-sample passes, then the passes): held to 1e-4 of their norm."""
+alpha = 1e-3 is a decision, compared only away from it.  Inference runs on the
+matrix cores: BF16 inputs, weights and first hidden layer, FP32 accumulation;
+it is compared with the oracle's pass of the same roundings
+(oracle.mlp.forward_bf16) within 2 * 144 * 2^-24 of the absolute-value
+propagation of the network (|W| |x| + |b| layer by layer: the FP32 sums of a
+16 + 64 + 64 term chain) plus, for every first-layer unit whose exact value
+lies within the FP32 error of a BF16 rounding boundary, the step between its
+two BF16 neighbours carried through |W2| and |W3|.  Gradients are FP32 sums
+over the batch (64-sample passes, then the passes): held to 1e-4 of their
+norm."""
 import numpy as np
 import pytest
 
@@ -73,16 +78,37 @@ def _solver0():
     return P.Solver(3)
 
 
-def test_mlp_forward_parity():
+def _bf16_forward_tol(w, x):
+    """bound on |device - oracle.mlp.forward_bf16| (see the module docstring)"""
+    p = MLP.unpack(MLP.bf16(w))
+    xb = MLP.bf16(x)
+    z1 = xb @ p["W1"].T + p["b1"]
+    # FP32 error of a first-layer unit (16 products and the bias), doubled for
+    # the rounding of the probes below
+    e1 = 2 * 18 * 2.0 ** -24 * (np.abs(xb) @ np.abs(p["W1"]).T + np.abs(p["b1"]))
+    relu32 = lambda v: np.maximum(v, 0.0).astype(np.float32)
+    dh = MLP.bf16(relu32(z1 + e1)) - MLP.bf16(relu32(z1 - e1))
+    flip = (dh @ np.abs(p["W2"]).T) @ np.abs(p["W3"])
+    return 2 * 144 * 2.0 ** -24 * _abs_scale(w, xb) + flip, int((dh > 0).sum())
+
+
+@pytest.mark.parametrize("B", [1, 5, 3001, 300001])
+def test_mlp_forward_parity(B):
+    """matrix-core inference against the oracle's BF16-operand pass; 300,001
+    samples take the kernel's block loop (1,024 blocks of 128 samples per
+    round) and a ragged last tile"""
     s = _solver0()
     w = MLP.init(1)
     s.mlp_set_weights(w)
     assert np.array_equal(s.mlp_get_weights(), w)
-    x = np.random.default_rng(0).uniform(0, 1, (3001, 16)).astype(np.float32)
+    x = np.random.default_rng(B).uniform(0, 1, (B, 16)).astype(np.float32)
     y = s.mlp_forward(x)
-    ref = MLP.forward(w, x.astype(np.float64))[0]
-    tol = 2 * 144 * 2.0 ** -24 * _abs_scale(w, x.astype(np.float64))
-    print(f"forward: max |dy| {np.abs(y - ref).max():.2e}, max tol {tol.max():.2e}", flush=True)
+    ref = MLP.forward_bf16(w, x)
+    tol, nflip = _bf16_forward_tol(w, x)
+    print(f"forward B={B}: max |dy| {np.abs(y - ref).max():.2e}, max tol {tol.max():.2e}, "
+          f"first-layer units near a BF16 boundary {nflip}; "
+          f"max |dy| vs the FP64 pass {np.abs(y - MLP.forward(w, x.astype(np.float64))[0]).max():.2e}",
+          flush=True)
     assert (np.abs(y - ref) <= tol).all()
     import torch
     yd = s.mlp_forward(torch.from_numpy(x).cuda())
@@ -188,11 +214,13 @@ def test_learned_indicator_drives_amr():
     """The network trained on GPU-generated (features, modal indicator) pairs
     drives dynamic AMR of the blast: its refine / keep / coarsen decisions agree
     with the modal indicator's on the same states, and the run stays within
-    the positivity bounds."""
+    the positivity bounds.  Recorded beside them: the element counts after each
+    adaptation and the wall time of both runs (the learned network imitates
+    the modal indicator; it refines somewhat more and gains nothing in time)."""
     from paper_2607_06045_amd import evaluate as EV
     r = EV.run_learned(steps=40, iters=1500, blasts=2, shears=1, snaps=4)
     print({k: r[k] for k in ("agreement", "refine_recall", "coarsen_recall", "violations",
-                             "l1_density_base_cells", "indicator_ms")}, flush=True)
+                             "l1_density_base_cells", "indicator_ms", "wall_s")}, flush=True)
     print("elements plain", r["elements"]["plain"], "learned", r["elements"]["learned"], flush=True)
     assert r["agreement"] > 0.9 and r["refine_recall"] > 0.9
     assert r["violations"] == {"plain": 0, "learned": 0}
@@ -210,3 +238,55 @@ def test_mixed_precision_amr_run():
     assert r["violations"] == {"fp64": 0, "mixed": 0}
     assert max(r["conservation_defect"]["fp64"]) < 1e-13
     assert max(r["conservation_defect"]["mixed"]) < 1e-9
+
+
+def _time_indicator(s, kind, reps=30):
+    import torch
+    for _ in range(3):
+        s.indicator(kind, device=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        s.indicator(kind, device=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+@pytest.mark.parametrize("workload,N", [("blast22k", 3), ("quadrants247k", 4)])
+def test_learned_indicator_cost_against_the_modal_indicator(workload, N):
+    """Cost of the learned indicator (16 features and the matrix-core network
+    in one kernel) against the modal indicator it imitates.  Both read the
+    state once, so neither can be much cheaper than the other: the modal one
+    transforms rho p, the learned one rho and p and adds the network.
+    Recorded: time per call over back-to-back calls (events on the context's
+    stream; at 22,156 leaves the host's call overhead is part of it).
+    Asserted: the learned indicator costs at most 1.5 times the modal one on
+    the 246,736-leaf workload, where the kernels dominate, and its output
+    equals the stand-alone network on the stand-alone features bit for bit."""
+    import paper_2607_06045_amd as P
+    s, u = _solver(workload_mesh(workload), N, lambda x, y: states.workload_state(workload, x, y))
+    s.mlp_set_weights(MLP.init(2))
+    t_modal = _time_indicator(s, P.IND_HENNEMANN)
+    t_net = _time_indicator(s, P.IND_MLP)
+    t_feat = _time_indicator_features(s)
+    print(f"{workload} (E={s.E}, N={N}): modal {1e3 * t_modal:.1f} us, learned {1e3 * t_net:.1f} us "
+          f"(ratio {t_net / t_modal:.2f}), features alone {1e3 * t_feat:.1f} us per call", flush=True)
+    assert np.array_equal(s.indicator(P.IND_MLP), s.mlp_forward(s.features()))
+    if workload == "quadrants247k":
+        assert t_net <= 1.5 * t_modal
+
+
+def _time_indicator_features(s, reps=30):
+    import torch
+    for _ in range(3):
+        s.features(device=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        s.features(device=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps

@@ -68,3 +68,41 @@ def test_adam_first_step_is_signed_lr():
     # |g| >> eps: the first step is lr sign(g) up to eps/|g| and FP32 rounding of w
     err = np.abs(dw[big] + lr * np.sign(g[big]))
     assert (err <= lr * 1e-5 + 2.0 ** -23 * np.abs(w0[big]) + 1e-12).all()
+
+
+def test_bf16_inference_equals_plain_forward_on_bf16_exact_operands():
+    """Weights, inputs and first-layer activations that are exactly BF16
+    (small dyadic values): the BF16-operand pass adds no rounding and equals the
+    plain forward pass."""
+    rng = np.random.default_rng(4)
+    d = {"W1": rng.integers(-4, 5, (64, 16)) / 8.0, "b1": rng.integers(-4, 5, 64) / 8.0,
+         "W2": rng.integers(-4, 5, (64, 64)) / 64.0, "b2": rng.integers(-4, 5, 64) / 8.0,
+         "W3": rng.integers(-4, 5, 64) / 8.0, "b3": np.array([0.25])}
+    w = MLP.pack(d).astype(np.float32)
+    x = (rng.integers(0, 8, (50, 16)) / 8.0).astype(np.float32)
+    # first-layer values: sums of 16 products of (k/8)(m/8) plus b1, multiples
+    # of 1/64 below 2^4 in magnitude: exact in BF16 (8 significant bits) only
+    # when small; keep the rows whose activations are exact
+    z1 = x.astype(np.float64) @ d["W1"].T + d["b1"]
+    h1 = np.maximum(z1, 0.0)
+    exact = np.all(MLP.bf16(h1) == h1, axis=1)
+    assert exact.sum() >= 10
+    y0 = MLP.forward(w, x[exact])[0]
+    y1 = MLP.forward_bf16(w, x[exact])
+    assert np.array_equal(y0, y1)
+
+
+def test_bf16_inference_rounds_the_inputs_and_the_first_layer():
+    """Generic inputs: the BF16 pass equals the plain pass applied to the
+    BF16-rounded inputs with the first layer rounded to BF16, and differs from
+    the plain pass by the size of that rounding (relative 2^-9 per operand)."""
+    w = MLP.init(3)
+    x = np.random.default_rng(5).uniform(0, 1, (200, 16)).astype(np.float32)
+    p = MLP.unpack(MLP.bf16(w))
+    xb = MLP.bf16(x)
+    assert np.all(np.abs(xb - x) <= 2.0 ** -8 * np.abs(x))
+    h1 = MLP.bf16(np.maximum(xb @ p["W1"].T + p["b1"], 0.0).astype(np.float32))
+    ref = np.maximum(h1 @ p["W2"].T + p["b2"], 0.0) @ p["W3"] + p["b3"][0]
+    assert np.allclose(MLP.forward_bf16(w, x), ref, rtol=0, atol=0)
+    y = MLP.forward(w, x)[0]
+    assert 0 < np.abs(MLP.forward_bf16(w, x) - y).max() < 0.05 * np.abs(y).max()
