@@ -1072,7 +1072,11 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const unsigned c = pcode[i];
-            const int ql = c & 31, qk = (c >> 5) & 31, d = (c >> 10) & 1;
+            // pair p = q + i NN: the x pairs are slots below n NPL; where NN divides
+            // that count (N = 4) the direction of iteration i is a constant
+            constexpr bool DSTAT = (n * NPL) % NN == 0;
+            const int ql = c & 31, qk = (c >> 5) & 31;
+            const int d = DSTAT ? (i * NN >= n * NPL ? 1 : 0) : (int)((c >> 10) & 1);
             const int p = q + i * NN;
             const int rn = 1 + d, rt = 2 - d;
             const double scale = sS[(c >> 11) & 7][(c >> 14) & 7] * (d ? hh[1] : hh[0]);
@@ -1131,31 +1135,34 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     }
     __syncthreads();
 
-    // ---- phase 5a: telescoped high-order subcell fluxes, one lane per line ----
-    // Lanes q < 2n of an element own line q (x lines q < n, y lines after):
-    // the flux through the subcell face after position pos is the sum of the
-    // line's pair fluxes (l, k) with l <= pos < k.  With the position a loop
-    // constant, every index is static.  The N sums replace the line's first N
-    // pair slots, which no other lane reads.
-    if (act && q < 2 * n) {
-        const int base = q * NPL;  // x lines, then y lines, NPL pairs each
-        double hof[N][4];
+    // ---- phase 5a: telescoped high-order subcell fluxes ----
+    // One task per line and variable (x lines first, then y lines; 8n tasks,
+    // task t = q + j NN for j = 0, 1): the flux through the subcell face after
+    // position pos is the sum of the line's pair fluxes (l, k) with
+    // l <= pos < k.  With the position a loop constant, every pair index is
+    // static.  The N sums replace the line's first N pair slots of that
+    // variable, which no other task reads.
+    static_assert(8 * n <= 2 * NN, "two telescoping tasks per lane at most");
+    if (act) {
 #pragma unroll
-        for (int pos = 0; pos < N; ++pos)
+        for (int j = 0; j < 2; ++j) {
+            const int t = q + j * NN;
+            if (t < 8 * n) {
+                double* P = &sPair[le][t & 3][(t >> 2) * NPL];
+                double hof[N];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double acc = 0.0;
+                for (int pos = 0; pos < N; ++pos) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int l = 0; l <= pos; ++l)
+                    for (int l = 0; l <= pos; ++l)
 #pragma unroll
-                    for (int k = pos + 1; k < n; ++k)
-                        acc += sPair[le][v][base + l * (2 * n - l - 1) / 2 + (k - l - 1)];
-                hof[pos][v] = acc;
+                        for (int k = pos + 1; k < n; ++k) acc += P[l * (2 * n - l - 1) / 2 + (k - l - 1)];
+                    hof[pos] = acc;
+                }
+#pragma unroll
+                for (int pos = 0; pos < N; ++pos) P[pos] = hof[pos];
             }
-#pragma unroll
-        for (int pos = 0; pos < N; ++pos)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sPair[le][v][base + pos] = hof[pos][v];
+        }
     }
     // ---- phase 5b: low-order subcell fluxes of the faces owned by this node,
     // x (a|a+1) and y (b|b+1), and the antidiffusive fluxes ----
