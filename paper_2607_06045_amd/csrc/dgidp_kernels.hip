@@ -272,28 +272,28 @@ __device__ __forceinline__ void mortar_flux(int d, bool large_low, const NodeP& 
 }
 
 // logarithmic mean x^ln = (x - y) / (ln x - ln y) from the logarithms lx, ly.
-// Where ((x - y)/(x + y))^2 = f^2 < 1e-4 the series of 2 atanh truncated after
-// f^6 (Ismail & Roe 2009): (x + y) / (2 (1 + e)), e = f^2/3 + f^4/5 + f^6/7,
-// with 1/(1 + e) expanded to third order (e < 3.5e-5: remainder below 2e-18).
-// Branch free: one reciprocal serves whichever form applies.
+// Where |f| = |x - y| / (x + y) < 1e-2 (f^2 < 1e-4) the series
+// x^ln = (x + y)/2 f / atanh f = (x + y)/2 (1 - f^2/3 - 4 f^4/45 - 44 f^6/945 - ...)
+// (from the series of 2 atanh, as in Ismail & Roe 2009), whose next term is
+// below 4e-18 relative there.  Branch free: one reciprocal serves whichever
+// form applies.
 __device__ __forceinline__ double lnmean(double x, double y, double lx, double ly)
 {
     const double s = x + y, d = x - y;
-    const bool ser = d * d < 1e-4 * (s * s);
+    const bool ser = fabs(d) < 1e-2 * s;
     const double r = frcp(ser ? s : lx - ly);
-    const double f2 = d * d * (r * r);
-    const double e = f2 * (1.0 / 3.0 + f2 * (1.0 / 5.0 + f2 * (1.0 / 7.0)));
-    const double sv = 0.5 * s * (1.0 - e * (1.0 - e * (1.0 - e)));
-    return ser ? sv : d * r;
+    const double f = d * r, f2 = f * f;
+    const double sv = 0.5 * s * (1.0 - f2 * (1.0 / 3.0 + f2 * (4.0 / 45.0 + f2 * (44.0 / 945.0))));
+    return ser ? sv : f;
 }
 
 // 1 / x^ln = (ln x - ln y) / (x - y); series (2 + f^2 (2/3 + f^2 (2/5 + f^2 2/7))) / (x + y)
 __device__ __forceinline__ double inv_lnmean(double x, double y, double lx, double ly)
 {
     const double s = x + y, d = x - y;
-    const bool ser = d * d < 1e-4 * (s * s);
+    const bool ser = fabs(d) < 1e-2 * s;
     const double r = frcp(ser ? s : d);
-    const double f2 = d * d * (r * r);
+    const double f = d * r, f2 = f * f;
     const double sv = (2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0)))) * r;
     return ser ? sv : (lx - ly) * r;
 }
@@ -680,8 +680,10 @@ template <int N>
 __device__ __forceinline__ void load_u(const double* u, int e, int q, double* w)
 {
     constexpr int NN = (N + 1) * (N + 1);
+    // one address per node; the variables at constant offsets (index < 2^30, mesh limit)
+    const double* p = u + ((unsigned)e * 4u * NN + (unsigned)q);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) w[v] = u[((unsigned)e * 4u + v) * NN + q];  // < 2^30 (mesh limit)
+    for (int v = 0; v < 4; ++v) w[v] = p[v * NN];
 }
 
 template <int N>
@@ -1430,12 +1432,12 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             thmin = fmin(thmin, tf[3]);
             ++nf;
         }
+        double* po = A.uout + ((unsigned)e * 4u * NN + (unsigned)q);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const unsigned idx = ((unsigned)e * 4u + v) * NN + q;
             double r = A.b * uvol[v];
             if (A.a != 0.0) r += A.a * un4[v];
-            A.uout[idx] = r;
+            po[v * NN] = r;
         }
         if (nmf == 0) {
             if (PURE) {
