@@ -15,7 +15,7 @@ constexpr int kMaxN = 4;
 constexpr int kSlotW = 16;  // doubles per mortar slot record
 // elements per block of the stage kernel (the host orders elements per the
 // kernel's block-to-XCD mapping)
-constexpr int stage_block_elems(int N) { return N == 3 ? 4 : 7; }
+constexpr int stage_block_elems(int N) { return N == 3 ? 4 : 5; }
 
 // Face codes: fmort[e*4+f] = -1 for a conforming face, otherwise
 // (mortar << 2) | (small << 1) | half, small = 1 if e is a small side.

@@ -2,7 +2,7 @@
 //
 // One SSP-RK3 stage (Sec. 2.3 and Sec. 3 intro of the paper) is two kernels:
 //   k_stage   one thread per LGL node; a block holds 4 elements in one wave
-//             (N = 3) or 7 elements in three waves (N = 4).  It stages the element in LDS,
+//             (N = 3) or 5 elements in two waves (N = 4).  It stages the element in LDS,
 //             evaluates the surface fluxes with one lane per face node
 //             (conforming LLF, Kopriva's L2 mortar, the sparse IDP mortar flux
 //             of eq. interfaceflux_local), the Ranocha two-point fluxes once per
@@ -20,6 +20,8 @@
 // one 64-bit atomic max per block into one of kDtSpread accumulators; the first
 // stage kernel of the step reduces those and takes dt = cfl / max.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "dgidp_internal.h"
 #include "dgidp_mlp_dev.h"
@@ -55,15 +57,17 @@ __device__ __forceinline__ int xcd_batch(int bid, int nb)
 
 // launch geometry per degree: one-wave blocks of 4 elements at N = 3 (the
 // phase barriers stay inside a wave and a late block holds less work),
-// three-wave blocks of 7 elements at N = 4 (25 nodes do not pack a wave; 175
-// of 192 lanes busy, and four blocks of 40 KB of LDS fill a compute unit to
-// the three waves per SIMD that the registers allow, where two-wave blocks of
-// 5 elements reached only ten waves: 6% faster, measured)
+// two-wave blocks of 5 elements at N = 4 (125 of 128 lanes busy; with the
+// pairs evaluated in two passes a block needs 25.8 KB of LDS, so six blocks,
+// twelve waves, fill a compute unit to the three waves per SIMD that the
+// registers allow).  Three-wave blocks of 7 elements (175 of 192 lanes, 40 KB
+// of LDS with all pairs stored at once, four blocks per CU) took 410.9
+// against 385.4 us per launch on the 246,736-leaf workload.
 template <int N>
 struct Geo {
     static constexpr int n = N + 1, NN = n * n;
-    static constexpr int BS = N == 3 ? 64 : 192;   // block size
-    static constexpr int EPB = BS / NN;            // 4 for N = 3, 7 for N = 4
+    static constexpr int BS = N == 3 ? 64 : 128;   // block size
+    static constexpr int EPB = BS / NN;            // 4 for N = 3, 5 for N = 4
     static_assert(EPB == stage_block_elems(N), "host element order assumes this block size");
     static constexpr int NT = EPB * NN;            // active threads
     static constexpr int NFN = 4 * n;              // face nodes per element
@@ -78,7 +82,12 @@ struct Geo {
     // saved.
     static constexpr int PU = N == 3 ? NN : NN + 1;        // sU variable stride
     static constexpr int PR = N == 3 ? NN : NN + 1;        // sR variable stride
-    static constexpr int PP = NP;                          // sPair variable stride
+    // x and y pairs in two passes where the x pairs fill whole thread rounds
+    // (N = 4); the pair buffer then needs the larger of the subcell-face
+    // fluxes (2 NF), the mortar staging (12 n) and half the pairs with the x
+    // lines' telescoped fluxes
+    static constexpr bool SPLIT = (n * NPL) % NN == 0;
+    static constexpr int PP = SPLIT ? (2 * NF > 12 * n ? 2 * NF : 12 * n) : NP;  // sPair variable stride
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
@@ -726,7 +735,7 @@ template <int N, int MODE, bool MIXED, int LIMK>
 // at least three waves per SIMD: the local-limiting variant would otherwise
 // take 172 registers and run two (63.3 against 67.7 us on the 22,156-leaf
 // blast with a few spilled registers; the other variants fit anyway)
-__global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
+__global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3))) void k_stage(StageArgs A)
 {
     using G = Geo<N>;
     // LOC: local bounds enforced; COMB: blended with positivity; BAR: the bounds
@@ -737,6 +746,9 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
     constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN;
     static_assert(NP % NN == 0, "pair split");
+    constexpr bool DSTAT = (n * NPL) % NN == 0, SPLIT = G::SPLIT;
+    constexpr int XH = n * NPL;  // SPLIT: the x lines' telescoped fluxes follow the pair slots
+    static_assert(!SPLIT || (DSTAT && XH + n * N <= G::PP), "two-pass pair buffer");
     static_assert(G::PP >= 2 * NF, "subcell face buffers reuse the pair buffer");
     static_assert(G::PP >= 12 * n, "mortar buffers reuse the pair buffer");
     static_assert(G::PU >= NFN, "surface terms reuse the state buffer");
@@ -1069,19 +1081,23 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
     // velocity is read from LDS row 1 + d and the tangential one from row 2 - d,
     // and the two momentum components are stored back to rows 1 + d and 2 - d,
     // so that lanes holding x and y pairs run the same instructions.
-    if (act) {
-        const double hh[2] = {0.5 * hy, 0.5 * hx};
+    // pair p = q + i NN: the x pairs are slots below n NPL.  Where NN divides that
+    // count (N = 4) the direction of round i is a constant, and the x and y pairs
+    // are evaluated in two passes (SPLIT): the x lines are telescoped into the
+    // slots after the x pairs, then the y pairs take the x pairs' slots, so the
+    // pair buffer holds half the pairs at a time.
+    const double hhx = 0.5 * hy, hhy = 0.5 * hx;  // pair scale of x and y lines
+    auto pair_rounds = [&](auto i0c, auto i1c, int slot_off) {
+        constexpr int i0 = decltype(i0c)::value, i1 = decltype(i1c)::value;
+        if (!act) return;
 #pragma unroll
-        for (int i = 0; i < PPT; ++i) {
+        for (int i = i0; i < i1; ++i) {
             const unsigned c = pcode[i];
-            // pair p = q + i NN: the x pairs are slots below n NPL; where NN divides
-            // that count (N = 4) the direction of iteration i is a constant
-            constexpr bool DSTAT = (n * NPL) % NN == 0;
             const int ql = c & 31, qk = (c >> 5) & 31;
             const int d = DSTAT ? (i * NN >= n * NPL ? 1 : 0) : (int)((c >> 10) & 1);
-            const int p = q + i * NN;
+            const int p = q + i * NN - slot_off;
             const int rn = 1 + d, rt = 2 - d;
-            const double scale = sS[(c >> 11) & 7][(c >> 14) & 7] * (d ? hh[1] : hh[0]);
+            const double scale = sS[(c >> 11) & 7][(c >> 14) & 7] * (d ? hhy : hhx);
             const double Ln = sR[le][rn][ql], Lt = sR[le][rt][ql];
             const double Rn = sR[le][rn][qk], Rt = sR[le][rt][qk];
             double f0, fn, ft, f3;
@@ -1134,35 +1150,54 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
             sPair[le][rt][p] = scale * ft;
             sPair[le][3][p] = scale * f3;
         }
-    }
-    __syncthreads();
+    };
+    // telescoped high-order subcell fluxes of one line and variable: the flux
+    // through the subcell face after position pos is the sum of the line's pair
+    // fluxes (l, k) with l <= pos < k; with the position a loop constant every
+    // pair index is static.  P: the line's pair slots; the N sums go to H.
+    auto telescope = [&](const double* P, double* H) {
+        double hof[N];
+#pragma unroll
+        for (int pos = 0; pos < N; ++pos) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l <= pos; ++l)
+#pragma unroll
+                for (int k = pos + 1; k < n; ++k) acc += P[l * (2 * n - l - 1) / 2 + (k - l - 1)];
+            hof[pos] = acc;
+        }
+#pragma unroll
+        for (int pos = 0; pos < N; ++pos) H[pos] = hof[pos];
+    };
+    if constexpr (SPLIT) {
+        // ---- phase 4 and 5a in two passes: one task per line and variable ----
+        pair_rounds(std::integral_constant<int, 0>(), std::integral_constant<int, PPT / 2>(), 0);
+        __syncthreads();
+        if (act && q < 4 * n) telescope(&sPair[le][q & 3][(q >> 2) * NPL], &sPair[le][q & 3][XH + (q >> 2) * N]);
+        __syncthreads();
+        pair_rounds(std::integral_constant<int, PPT / 2>(), std::integral_constant<int, PPT>(), n * NPL);
+        __syncthreads();
+        if (act && q < 4 * n) {
+            double* P = &sPair[le][q & 3][(q >> 2) * NPL];
+            telescope(P, P);
+        }
+    } else {
+        pair_rounds(std::integral_constant<int, 0>(), std::integral_constant<int, PPT>(), 0);
+        __syncthreads();
 
-    // ---- phase 5a: telescoped high-order subcell fluxes ----
-    // One task per line and variable (x lines first, then y lines; 8n tasks,
-    // task t = q + j NN for j = 0, 1): the flux through the subcell face after
-    // position pos is the sum of the line's pair fluxes (l, k) with
-    // l <= pos < k.  With the position a loop constant, every pair index is
-    // static.  The N sums replace the line's first N pair slots of that
-    // variable, which no other task reads.
-    static_assert(8 * n <= 2 * NN, "two telescoping tasks per lane at most");
-    if (act) {
+        // ---- phase 5a: telescoped high-order subcell fluxes ----
+        // One task per line and variable (x lines first, then y lines; 8n tasks,
+        // task t = q + j NN for j = 0, 1).  The N sums replace the line's first N
+        // pair slots of that variable, which no other task reads.
+        static_assert(8 * n <= 2 * NN, "two telescoping tasks per lane at most");
+        if (act) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int t = q + j * NN;
-            if (t < 8 * n) {
-                double* P = &sPair[le][t & 3][(t >> 2) * NPL];
-                double hof[N];
-#pragma unroll
-                for (int pos = 0; pos < N; ++pos) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int l = 0; l <= pos; ++l)
-#pragma unroll
-                        for (int k = pos + 1; k < n; ++k) acc += P[l * (2 * n - l - 1) / 2 + (k - l - 1)];
-                    hof[pos] = acc;
+            for (int j = 0; j < 2; ++j) {
+                const int t = q + j * NN;
+                if (t < 8 * n) {
+                    double* P = &sPair[le][t & 3][(t >> 2) * NPL];
+                    telescope(P, P);
                 }
-#pragma unroll
-                for (int pos = 0; pos < N; ++pos) P[pos] = hof[pos];
             }
         }
     }
@@ -1193,7 +1228,7 @@ __global__ __launch_bounds__(Geo<N>::BS, 3) void k_stage(StageArgs A)
         for (int d = 0; d < 2; ++d) {
             const int pos = d == 0 ? a : b, line = d == 0 ? b : a;
             if (pos >= N) continue;
-            const int slot = (d * n + line) * NPL + pos;
+            const int slot = SPLIT ? (d == 0 ? XH + line * N + pos : line * NPL + pos) : (d * n + line) * NPL + pos;
             const double wl = sTw[0][line];
 #pragma unroll
             for (int v = 0; v < 4; ++v) Ao[d][v] = wl * (sPair[le][v][slot] - FVo[d][v]);
