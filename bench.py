@@ -39,6 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # MI355X: 256 compute units of 4 SIMDs; a wave64 VALU instruction occupies its
 # SIMD for 4 cycles; peak engine clock 2.4 GHz
 SIMDS = 1024
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 CLOCK_HZ = 2.4e9
 # algorithmic HBM bytes of the element stage kernel per node and launch: the
 # first stage reads u and writes u^(1) (64 B); the other two also read u^n
@@ -218,6 +219,15 @@ def main():
             "issue_floor_ms": vw * 4.0 / (SIMDS * CLOCK_HZ) * 1e3,
             "frac": vw * 4.0 / (SIMDS * CLOCK_HZ) / (km["stage"] * 1e-3),
             "source": f"profiles/counters_k_stage_{name}.json"}
+        sq = cnt.get("sq_per_launch", {})
+        if all(k in sq for k in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64")):
+            # FP64 arithmetic of the counted instructions (64 lanes each, an FMA
+            # counting two) against the live duration and the FP64 vector peak
+            flop = 64.0 * (sq["SQ_INSTS_VALU_ADD_F64"] + sq["SQ_INSTS_VALU_MUL_F64"] +
+                           2.0 * sq["SQ_INSTS_VALU_FMA_F64"])
+            tf = flop / (km["stage"] * 1e-3) / 1e12
+            roof["valu"].update({"f64_tflops": tf, "f64_peak_tflops": FP64_PEAK_TFLOPS,
+                                 "f64_frac": tf / FP64_PEAK_TFLOPS})
     copy_gbs = copy_bandwidth()
     roof["copy_gbs_measured"] = copy_gbs
     roof["frac_of_measured_copy"] = achieved / copy_gbs
