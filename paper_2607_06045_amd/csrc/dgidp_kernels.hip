@@ -74,20 +74,22 @@ struct Geo {
     static constexpr int NPL = n * (n - 1) / 2;    // node pairs per line
     static constexpr int NP = 2 * n * NPL;         // node pairs per element
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
-    // padded LDS strides: a half wave covers two N = 3 elements; an element's
-    // stride of 16 (mod 32) doubles puts the second one on the other 32 banks.
-    // At N = 3 the arrays stay unpadded: a block then needs 12544 bytes and
-    // twelve blocks fit a compute unit (measured: with 15616 bytes only nine
-    // do); the extra waves are worth more than the bank conflicts the padding
-    // saved.
-    static constexpr int PU = N == 3 ? NN : NN + 1;        // sU variable stride
-    static constexpr int PR = N == 3 ? NN : NN + 1;        // sR variable stride
+    // LDS variable strides of the state and primitive arrays: unpadded.  At
+    // N = 3 padding to an odd element stride cost three of twelve blocks per
+    // compute unit (15616 against 12544 bytes per block), more than the bank
+    // conflicts it saved; at N = 4 a pad of one made no difference (378.3
+    // against 378.1 us per launch on the 246,736-leaf workload).
+    static constexpr int PU = NN;  // sU variable stride
+    static constexpr int PR = NN;  // sR variable stride
     // x and y pairs in two passes where the x pairs fill whole thread rounds
     // (N = 4); the pair buffer then needs the larger of the subcell-face
     // fluxes (2 NF), the mortar staging (12 n) and half the pairs with the x
     // lines' telescoped fluxes
     static constexpr bool SPLIT = (n * NPL) % NN == 0;
-    static constexpr int PP = SPLIT ? (2 * NF > 12 * n ? 2 * NF : 12 * n) : NP;  // sPair variable stride
+    // (one pad slot at N = 4: 80 slots per variable would give elements a
+    // 2,560-byte stride, a multiple of the 256-byte bank period, so that the
+    // elements sharing a wave would meet in the same banks)
+    static constexpr int PP = SPLIT ? (2 * NF > 12 * n ? 2 * NF : 12 * n) + 1 : NP;  // sPair variable stride
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
