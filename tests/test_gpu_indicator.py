@@ -290,3 +290,48 @@ def _time_indicator_features(s, reps=30):
     ev1.record()
     torch.cuda.synchronize()
     return ev0.elapsed_time(ev1) / reps
+
+
+@pytest.mark.parametrize("N", [3, 4])
+@pytest.mark.parametrize("nx", [1, 2, 7])
+def test_indicators_on_small_and_ragged_meshes(N, nx):
+    """Meshes of 1, 4 and 49 elements: fewer elements than one tile of the
+    feature kernel (30 at N = 4, 32 at N = 3) and a ragged last tile.  The modal
+    indicator and the features against the oracle, the learned indicator bit for
+    bit against the stand-alone network on the stand-alone features."""
+    import paper_2607_06045_amd as P
+    from workloads.meshes import uniform_mesh
+    s, u = _solver(uniform_mesh(nx, nx), N, lambda x, y: states.random_admissible(x, 11 + nx))
+    a = s.indicator(P.IND_HENNEMANN)
+    ref = IND.hennemann(u, N)
+    en = IND.hennemann_energy(u, N)
+    T = IND.threshold(N)
+    raw = 1.0 / (1.0 + np.exp(-(np.log(9999.0) / T) * (en - T)))
+    away = np.abs(raw - IND.ALPHA_MIN) > 1e-9
+    assert a.shape == (nx * nx,)
+    assert np.abs(a - ref)[away].max(initial=0.0) <= 2.0 ** -24 * 0.5 + 1e-12
+    f = s.features()
+    assert f.shape == (nx * nx, 16)
+    assert np.abs(f - IND.features(u, N)).max() <= 2.0 ** -24 + 1e-12
+    s.mlp_set_weights(MLP.init(5))
+    y = s.indicator(P.IND_MLP)
+    assert np.array_equal(y, s.mlp_forward(f))
+    tol, _ = _bf16_forward_tol(MLP.init(5), f)
+    assert (np.abs(y - MLP.forward_bf16(MLP.init(5), f)) <= tol).all()
+
+
+def test_mlp_forward_rejects_misaligned_device_input():
+    """device inputs must be 16-byte aligned (the kernel reads them as 16-byte
+    vectors); an offset view is refused, an aligned one accepted"""
+    import paper_2607_06045_amd as P
+    import torch
+    s = _solver0()
+    s.mlp_set_weights(MLP.init(0))
+    base = torch.rand(65, 16, dtype=torch.float32, device="cuda")
+    flat = base.reshape(-1)
+    bad = flat[1:1 + 64 * 16].reshape(64, 16)   # 4-byte offset
+    with pytest.raises(P.DgidpError, match="INVALID_ARG"):
+        s.mlp_forward(bad)
+    good = base[1:]                               # 64-byte offset
+    y = s.mlp_forward(good)
+    assert np.array_equal(y.cpu().numpy(), s.mlp_forward(good.cpu().numpy()))
