@@ -1096,7 +1096,9 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
         for (int i = i0; i < i1; ++i) {
             const unsigned c = pcode[i];
             const int ql = c & 31, qk = (c >> 5) & 31;
-            const int d = DSTAT ? (i * NN >= n * NPL ? 1 : 0) : (int)((c >> 10) & 1);
+            // a round wholly below or above the x pairs' n NPL slots has a constant
+            // direction; only a round that straddles them (N = 3: the second) decodes it
+            const int d = (i + 1) * NN <= n * NPL ? 0 : (i * NN >= n * NPL ? 1 : (int)((c >> 10) & 1));
             const int p = q + i * NN - slot_off;
             const int rn = 1 + d, rt = 2 - d;
             const double scale = sS[(c >> 11) & 7][(c >> 14) & 7] * (d ? hhy : hhx);
