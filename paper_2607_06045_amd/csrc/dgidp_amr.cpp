@@ -20,6 +20,7 @@
 
 #include "dgidp_internal.h"
 #include "dgidp_leaves.h"
+#include "dgidp_par.h"
 
 namespace dgidp {
 
@@ -131,37 +132,58 @@ int adapt_leaves(int64_t E, const int8_t* lev, const int32_t* ix, const int32_t*
         for (int c = 0; c < 4; ++c) grp[sib[c]] = first;
         ++ncoarse;
     }
-    // rule 4
+    // rule 4: each old leaf's place in the new list by a prefix count (a kept
+    // leaf 1, a refined one 4, a merged group 1 at its first member), then the
+    // entries written in parallel
     plan = AdaptPlan();
     plan.n_balance = nbal;
     plan.n_coarsened = ncoarse;
+    std::vector<int64_t> at((size_t)E + 1, 0);
     for (int64_t e = 0; e < E; ++e) {
-        if (grp[e] >= 0) {
-            if (grp[e] != e) continue;
-            const int l = lev[e];
-            const int64_t pi = ix[e] >> 1, pj = iy[e] >> 1;
-            plan.level.push_back((int8_t)(l - 1));
-            plan.ix.push_back((int32_t)pi);
-            plan.iy.push_back((int32_t)pj);
-            plan.kind.push_back(2);
-            for (int c = 0; c < 4; ++c) plan.src.push_back(L.get(l, 2 * pi + (c & 1), 2 * pj + (c >> 1)));
-        } else if (ref[e]) {
-            ++plan.n_refined;
-            for (int c = 0; c < 4; ++c) {
-                plan.level.push_back((int8_t)(lev[e] + 1));
-                plan.ix.push_back(2 * ix[e] + (c & 1));
-                plan.iy.push_back(2 * iy[e] + (c >> 1));
-                plan.kind.push_back(1);
-                plan.src.insert(plan.src.end(), {e, (int64_t)c, -1, -1});
-            }
-        } else {
-            plan.level.push_back(lev[e]);
-            plan.ix.push_back(ix[e]);
-            plan.iy.push_back(iy[e]);
-            plan.kind.push_back(0);
-            plan.src.insert(plan.src.end(), {e, -1, -1, -1});
-        }
+        const int64_t c = grp[e] >= 0 ? (grp[e] == e ? 1 : 0) : (ref[e] ? 4 : 1);
+        at[e + 1] = at[e] + c;
+        if (grp[e] < 0 && ref[e]) ++plan.n_refined;
     }
+    const int64_t En = at[E];
+    plan.level.resize(En);
+    plan.ix.resize(En);
+    plan.iy.resize(En);
+    plan.kind.resize(En);
+    plan.src.resize(En * 4);
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e) {
+            const int64_t o = at[e];
+            if (grp[e] >= 0) {
+                if (grp[e] != e) continue;
+                const int l = lev[e];
+                const int64_t pi = ix[e] >> 1, pj = iy[e] >> 1;
+                plan.level[o] = (int8_t)(l - 1);
+                plan.ix[o] = (int32_t)pi;
+                plan.iy[o] = (int32_t)pj;
+                plan.kind[o] = 2;
+                for (int c = 0; c < 4; ++c) plan.src[o * 4 + c] = L.get(l, 2 * pi + (c & 1), 2 * pj + (c >> 1));
+            } else if (ref[e]) {
+                for (int c = 0; c < 4; ++c) {
+                    plan.level[o + c] = (int8_t)(lev[e] + 1);
+                    plan.ix[o + c] = 2 * ix[e] + (c & 1);
+                    plan.iy[o + c] = 2 * iy[e] + (c >> 1);
+                    plan.kind[o + c] = 1;
+                    int64_t* sp = &plan.src[(o + c) * 4];
+                    sp[0] = e;
+                    sp[1] = c;
+                    sp[2] = sp[3] = -1;
+                }
+            } else {
+                plan.level[o] = lev[e];
+                plan.ix[o] = ix[e];
+                plan.iy[o] = iy[e];
+                plan.kind[o] = 0;
+                int64_t* sp = &plan.src[o * 4];
+                sp[0] = e;
+                sp[1] = sp[2] = sp[3] = -1;
+            }
+        }
+    });
     return 0;
 }
 

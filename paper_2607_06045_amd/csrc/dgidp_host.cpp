@@ -11,6 +11,7 @@
 
 #include "dgidp_internal.h"
 #include "dgidp_leaves.h"
+#include "dgidp_par.h"
 
 namespace dgidp {
 int build_and_upload_tables(int N, std::vector<double>* nodes);
@@ -228,17 +229,35 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         err = "invalid mesh arguments";
         return DGIDP_E_INVALID_ARG;
     }
+    // the loops over leaves and faces run on the host pool; each reports the
+    // first offending index, as a serial loop would
+    std::mutex red;
+    constexpr int64_t kNone = INT64_MAX;
     double area = 0.0;
     int lmax = 0;
-    for (int64_t e = 0; e < E; ++e) {
-        const int l = level[e];
-        if (l < 0 || l > 20 || ix[e] < 0 || iy[e] < 0 || ix[e] >= ((int64_t)nx0 << l) ||
-            iy[e] >= ((int64_t)ny0 << l)) {
-            err = "leaf " + std::to_string(e) + " outside the root grid";
-            return DGIDP_E_MESH_GAP_OR_OVERLAP;
+    int64_t bad = kNone;
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        double a = 0.0;
+        int lm = 0;
+        int64_t b = kNone;
+        for (int64_t e = lo; e < hi; ++e) {
+            const int l = level[e];
+            if (l < 0 || l > 20 || ix[e] < 0 || iy[e] < 0 || ix[e] >= ((int64_t)nx0 << l) ||
+                iy[e] >= ((int64_t)ny0 << l)) {
+                b = e;
+                break;
+            }
+            a += std::ldexp(1.0, -2 * l);
+            lm = std::max(lm, l);
         }
-        area += std::ldexp(1.0, -2 * l);
-        lmax = std::max(lmax, l);
+        std::lock_guard<std::mutex> g(red);
+        area += a;  // (the tiling test below allows for the summation order)
+        lmax = std::max(lmax, lm);
+        bad = std::min(bad, b);
+    });
+    if (bad != kNone) {
+        err = "leaf " + std::to_string(bad) + " outside the root grid";
+        return DGIDP_E_MESH_GAP_OR_OVERLAP;
     }
     LeafLookup find;
     const int64_t dup = find.build(E, level, ix, iy, nx0, ny0);
@@ -246,16 +265,25 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
         err = "duplicate leaf " + std::to_string(dup);
         return DGIDP_E_MESH_GAP_OR_OVERLAP;
     }
-    for (int64_t e = 0; e < E; ++e) {
-        int64_t cx = ix[e], cy = iy[e];
-        for (int l = level[e] - 1; l >= 0; --l) {
-            cx >>= 1;
-            cy >>= 1;
-            if (find.get(l, cx, cy) >= 0) {
-                err = "leaf " + std::to_string(e) + " overlaps a coarser leaf";
-                return DGIDP_E_MESH_GAP_OR_OVERLAP;
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        int64_t b = kNone;
+        for (int64_t e = lo; e < hi && b == kNone; ++e) {
+            int64_t cx = ix[e], cy = iy[e];
+            for (int l = level[e] - 1; l >= 0; --l) {
+                cx >>= 1;
+                cy >>= 1;
+                if (find.get(l, cx, cy) >= 0) {
+                    b = e;
+                    break;
+                }
             }
         }
+        std::lock_guard<std::mutex> g(red);
+        bad = std::min(bad, b);
+    });
+    if (bad != kNone) {
+        err = "leaf " + std::to_string(bad) + " overlaps a coarser leaf";
+        return DGIDP_E_MESH_GAP_OR_OVERLAP;
     }
     if (std::fabs(area - (double)nx0 * ny0) > 1e-9 * nx0 * ny0) {
         err = "leaves do not tile the domain";
@@ -281,12 +309,14 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
     // the same-level leaf across each face (-1: none, the face is nonconforming;
     // unused on boundary faces), looked up once for the ordering and pass 1
     std::vector<int> same((size_t)E * 4, -1);
-    for (int64_t e = 0; e < E; ++e)
-        for (int f = 0; f < 4; ++f) {
-            if (bface[e * 4 + f] >= 0) continue;
-            const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
-            same[e * 4 + f] = lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy);
-        }
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e)
+            for (int f = 0; f < 4; ++f) {
+                if (bface[e * 4 + f] >= 0) continue;
+                const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
+                same[e * 4 + f] = lookup(level[e], (int64_t)ix[e] + dx, (int64_t)iy[e] + dy);
+            }
+    });
     // internal order: Morton order of the leaves on the finest grid, cut into
     // the eight contiguous ranges that the stage kernel hands to the eight
     // XCDs; inside each range the leaves with a nonconforming face come first.
@@ -294,96 +324,147 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
     // work) or none, and the longer waves start first on each XCD instead of
     // ending the launch late.
     std::vector<std::pair<uint64_t, int>> ord((size_t)E);
-    for (int64_t e = 0; e < E; ++e) {
-        const int s = lmax - level[e];
-        ord[e] = {morton((uint64_t)ix[e] << s, (uint64_t)iy[e] << s), (int)e};
-    }
-    std::sort(ord.begin(), ord.end());
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e) {
+            const int s = lmax - level[e];
+            ord[e] = {morton((uint64_t)ix[e] << s, (uint64_t)iy[e] << s), (int)e};
+        }
+    });
+    // (the keys are distinct: chunk sorts merged give the serial order)
+    par_sort(ord);
     {
         const int64_t epb = stage_block_elems(N);
         const int64_t nb = (E + epb - 1) / epb, q = nb >> 3, r = nb & 7;
-        int64_t g0 = 0;
-        for (int x = 0; x < 8; ++x) {
-            const int64_t gn = q + (x < r ? 1 : 0);
-            const int64_t lo = std::min<int64_t>(E, g0 * epb), hi = std::min<int64_t>(E, (g0 + gn) * epb);
-            std::stable_partition(ord.begin() + lo, ord.begin() + hi, [&](const std::pair<uint64_t, int>& o) {
-                const int e = o.second;
-                for (int f = 0; f < 4; ++f)
-                    if (bface[e * 4 + f] < 0 && same[e * 4 + f] < 0) return true;
-                return false;
-            });
-            g0 += gn;
-        }
+        par_for(8, [&](int64_t x0, int64_t x1) {
+            for (int64_t x = x0; x < x1; ++x) {
+                const int64_t g0 = x * q + std::min<int64_t>(x, r), gn = q + (x < r ? 1 : 0);
+                const int64_t lo = std::min<int64_t>(E, g0 * epb), hi = std::min<int64_t>(E, (g0 + gn) * epb);
+                std::stable_partition(ord.begin() + lo, ord.begin() + hi, [&](const std::pair<uint64_t, int>& o) {
+                    const int e = o.second;
+                    for (int f = 0; f < 4; ++f)
+                        if (bface[e * 4 + f] < 0 && same[e * 4 + f] < 0) return true;
+                    return false;
+                });
+            }
+        }, 1);
     }
     std::vector<int> inv(E);
     hm.perm.assign(E, 0);
-    for (int64_t i = 0; i < E; ++i) {
-        hm.perm[i] = ord[i].second;
-        inv[ord[i].second] = (int)i;
-    }
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            hm.perm[i] = ord[i].second;
+            inv[ord[i].second] = (int)i;
+        }
+    });
     hm.fnbr.assign(E * 4, -1);
     hm.fnbr2.assign(E * 4, -1);
     hm.fmort.assign(E * 4, -1);
     hm.mort.clear();
     int M = 0;
-    // pass 1: conforming faces and large sides (mortars numbered by internal large element)
-    for (int64_t i = 0; i < E; ++i) {
-        const int e = hm.perm[i], l = level[e];
-        for (int f = 0; f < 4; ++f) {
-            if (bface[e * 4 + f] >= 0) {
-                hm.fnbr[i * 4 + f] = (int)i;
-                hm.fmort[i * 4 + f] = -2 - bface[e * 4 + f];
-                continue;
+    // pass 1: conforming and boundary faces, and the large sides of mortars
+    // (their two small neighbours; numbered below in internal order)
+    std::vector<char> large((size_t)E * 4, 0);
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        int64_t b = kNone;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int e = hm.perm[i], l = level[e];
+            for (int f = 0; f < 4; ++f) {
+                if (bface[e * 4 + f] >= 0) {
+                    hm.fnbr[i * 4 + f] = (int)i;
+                    hm.fmort[i * 4 + f] = -2 - bface[e * 4 + f];
+                    continue;
+                }
+                const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
+                const int64_t cx = ix[e] + dx, cy = iy[e] + dy;
+                const int g = same[e * 4 + f];
+                if (g >= 0) {
+                    hm.fnbr[i * 4 + f] = inv[g];
+                    continue;
+                }
+                const int64_t nx = (int64_t)nx0 << l, ny = (int64_t)ny0 << l;
+                const int64_t wx = ((cx % nx) + nx) % nx, wy = ((cy % ny) + ny) % ny;
+                if (lookup(l - 1, wx >> 1, wy >> 1) >= 0) continue;  // small side: pass 2
+                int s0, s1;
+                if (f < 2) {
+                    const int64_t sx = 2 * wx + (f == 0 ? 1 : 0);
+                    s0 = lookup(l + 1, sx, 2 * wy);
+                    s1 = lookup(l + 1, sx, 2 * wy + 1);
+                } else {
+                    const int64_t sy = 2 * wy + (f == 2 ? 1 : 0);
+                    s0 = lookup(l + 1, 2 * wx, sy);
+                    s1 = lookup(l + 1, 2 * wx + 1, sy);
+                }
+                if (s0 < 0 || s1 < 0) {
+                    b = std::min<int64_t>(b, i * 4 + f);
+                    continue;
+                }
+                hm.fnbr[i * 4 + f] = inv[s0];
+                hm.fnbr2[i * 4 + f] = inv[s1];
+                large[i * 4 + f] = 1;
             }
-            const int dx = f == 0 ? -1 : (f == 1 ? 1 : 0), dy = f == 2 ? -1 : (f == 3 ? 1 : 0);
-            const int64_t cx = ix[e] + dx, cy = iy[e] + dy;
-            const int g = same[e * 4 + f];
-            if (g >= 0) {
-                hm.fnbr[i * 4 + f] = inv[g];
-                continue;
-            }
-            const int64_t nx = (int64_t)nx0 << l, ny = (int64_t)ny0 << l;
-            const int64_t wx = ((cx % nx) + nx) % nx, wy = ((cy % ny) + ny) % ny;
-            if (lookup(l - 1, wx >> 1, wy >> 1) >= 0) continue;  // small side: pass 2
-            int s0, s1;
-            if (f < 2) {
-                const int64_t sx = 2 * wx + (f == 0 ? 1 : 0);
-                s0 = lookup(l + 1, sx, 2 * wy);
-                s1 = lookup(l + 1, sx, 2 * wy + 1);
-            } else {
-                const int64_t sy = 2 * wy + (f == 2 ? 1 : 0);
-                s0 = lookup(l + 1, 2 * wx, sy);
-                s1 = lookup(l + 1, 2 * wx + 1, sy);
-            }
-            if (s0 < 0 || s1 < 0) {
-                err = "leaf " + std::to_string(e) + " face " + std::to_string(f) + " is not 2:1 balanced";
-                return DGIDP_E_MESH_NOT_BALANCED;
-            }
-            hm.fnbr[i * 4 + f] = inv[s0];
-            hm.fnbr2[i * 4 + f] = inv[s1];
-            hm.fmort[i * 4 + f] = (M << 2);
-            hm.mort.push_back((int)i);
-            hm.mort.push_back(f);
-            hm.mort.push_back(inv[s0]);
-            hm.mort.push_back(inv[s1]);
-            ++M;
         }
+        std::lock_guard<std::mutex> g(red);
+        bad = std::min(bad, b);
+    });
+    if (bad != kNone) {
+        err = "leaf " + std::to_string(hm.perm[bad / 4]) + " face " + std::to_string(bad % 4) +
+              " is not 2:1 balanced";
+        return DGIDP_E_MESH_NOT_BALANCED;
+    }
+    // mortars numbered by their large side in internal order: counts per chunk
+    // of faces, their offsets, then the entries
+    {
+        const int64_t nk = E * 4, nc = 64;
+        std::vector<int64_t> at(nc + 1, 0);
+        par_for(nc, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c)
+                for (int64_t k = nk * c / nc; k < nk * (c + 1) / nc; ++k) at[c + 1] += large[k];
+        }, 1);
+        for (int64_t c = 0; c < nc; ++c) at[c + 1] += at[c];
+        M = (int)at[nc];
+        hm.mort.resize((size_t)M * 4);
+        par_for(nc, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                int64_t S = at[c];
+                for (int64_t k = nk * c / nc; k < nk * (c + 1) / nc; ++k)
+                    if (large[k]) {
+                        hm.fmort[k] = (int)(S << 2);
+                        int* m = &hm.mort[S * 4];
+                        m[0] = (int)(k / 4);
+                        m[1] = (int)(k % 4);
+                        m[2] = hm.fnbr[k];
+                        m[3] = hm.fnbr2[k];
+                        ++S;
+                    }
+            }
+        }, 1);
     }
     // pass 2: small sides point at the large element and carry their half
-    for (int S = 0; S < M; ++S) {
-        const int L = hm.mort[S * 4], f = hm.mort[S * 4 + 1];
-        for (int h = 0; h < 2; ++h) {
-            const int s = hm.mort[S * 4 + 2 + h];
-            hm.fnbr[s * 4 + (f ^ 1)] = L;
-            hm.fmort[s * 4 + (f ^ 1)] = (S << 2) | 2 | h;
+    par_for(M, [&](int64_t lo, int64_t hi) {
+        for (int64_t S = lo; S < hi; ++S) {
+            const int L = hm.mort[S * 4], f = hm.mort[S * 4 + 1];
+            for (int h = 0; h < 2; ++h) {
+                const int s = hm.mort[S * 4 + 2 + h];
+                hm.fnbr[s * 4 + (f ^ 1)] = L;
+                hm.fmort[s * 4 + (f ^ 1)] = ((int)S << 2) | 2 | h;
+            }
         }
+    });
+    par_for(E * 4, [&](int64_t lo, int64_t hi) {
+        int64_t b = kNone;
+        for (int64_t i = lo; i < hi; ++i)
+            if (hm.fnbr[i] < 0) {
+                b = i;
+                break;
+            }
+        std::lock_guard<std::mutex> g(red);
+        bad = std::min(bad, b);
+    });
+    if (bad != kNone) {
+        err = "face " + std::to_string(bad % 4) + " of leaf " + std::to_string(hm.perm[bad / 4]) +
+              " has no 2:1 partner";
+        return DGIDP_E_MESH_NOT_BALANCED;
     }
-    for (int64_t i = 0; i < E * 4; ++i)
-        if (hm.fnbr[i] < 0) {
-            err = "face " + std::to_string(i % 4) + " of leaf " + std::to_string(hm.perm[i / 4]) +
-                  " has no 2:1 partner";
-            return DGIDP_E_MESH_NOT_BALANCED;
-        }
     // mortar slots: node ids, and partners of nodes that lie on two mortars
     const int NS = 3 * n;
     hm.snode.assign((size_t)M * NS, 0);
