@@ -1,6 +1,6 @@
 """Pins of the oracle's non-periodic boundaries: slip walls and characteristic
 inflow/outflow, the conditions of the double Mach reflection and the jet
-(Sec. 3.6).
+(Sec. 3.5, 3.6).
 
 - A slip wall is a mirror: a walled run equals, to rounding, the periodic run on
   the domain doubled across the wall with the data reflected (normal velocity
@@ -12,14 +12,22 @@ inflow/outflow, the conditions of the double Mach reflection and the jet
   that hits its walls, and keeps a state at rest.
 - Every condition keeps a uniform flow whose exterior state is that flow
   (free-stream preservation), for sub- and supersonic speeds.
-The subsonic characteristic branches are pinned by free-stream preservation
-only; their values are checked against the rule they follow."""
+- The subsonic characteristic branches against characteristic theory:
+  a uniform-velocity, uniform-pressure flow stays so to rounding under every
+  flux, mortar and limiter of the scheme (momentum and energy are linear in the
+  density at fixed velocity and pressure), so a contact entering through a
+  subsonic inflow and one leaving through a subsonic outflow keep velocity and
+  pressure exact whatever the ignored exterior values are; at the matching
+  pressure the subsonic outflow is the plain outflow; a subsonic inflow that
+  imposes a lower speed sends in a rarefaction that keeps the outgoing
+  invariant u - 2c/(gamma-1); a subsonic outflow that imposes a lower pressure
+  sends in one that keeps u + 2c/(gamma-1) and the entropy."""
 import numpy as np
 import pytest
 
 from parity import state_err
 from workloads import states
-from workloads.meshes import MeshSpec, random_mesh, refined_box_mesh
+from workloads.meshes import MeshSpec, random_mesh, refined_box_mesh, uniform_mesh
 
 G = 1.4
 
@@ -172,6 +180,118 @@ def test_free_stream(oracle, kind, speed):
     for _ in range(3):
         u, st = M.ssprk3(u, 0.9, limiter=oracle.LIM_LOCAL)
     assert state_err(u, u0) < 1e-13
+
+
+def _channel_run(oracle, axis, sign, ext_lo, ext_hi, rho0, T, limiter=None, bc_hi=None):
+    """A channel of 64 x 4 square elements (N=3) along the axis, periodic across
+    it, characteristic on both ends (bc_hi overrides the upper end); the flow
+    runs along the axis at speed sign * 0.5 with pressure 1 and density rho0(s)
+    (s the coordinate along the axis).  ext_lo / ext_hi are the exterior
+    states of the two ends as (rho, velocity along, velocity across, p).
+    Returns s and the primitive variables (rho, along, across, p) at T."""
+    lim = oracle.LIM_POSITIVITY if limiter is None else limiter
+    spec = uniform_mesh(64, 4, Lx=1.0, Ly=1 / 16) if axis == 0 else uniform_mesh(4, 64, Lx=1 / 16, Ly=1.0)
+
+    def cons(r, un, ut, p):
+        v = (un, ut) if axis == 0 else (ut, un)
+        return states.conservative(*[np.array([q]) for q in (r, v[0], v[1], p)], G)[0]
+
+    lo, hi = (0, 1) if axis == 0 else (2, 3)
+    ext = np.zeros((4, 4))
+    ext[lo], ext[hi] = cons(*ext_lo), cons(*ext_hi)
+    bc = [0, 0, 0, 0]
+    bc[lo] = oracle.BC_CHARACTERISTIC
+    bc[hi] = oracle.BC_CHARACTERISTIC if bc_hi is None else bc_hi
+    M = oracle.Mesh(3, *spec.args(), bc=bc, ext=ext)
+    x, y, _ = M.geometry()
+    s = x if axis == 0 else y
+    un, ut = sign * 0.5 + 0 * s, 0 * s
+    v = (un, ut) if axis == 0 else (ut, un)
+    u = states.conservative(rho0(s), v[0], v[1], 1.0 + 0 * s, G)
+    t = 0.0
+    while t < T * (1 - 1e-12):
+        dt = min(M.max_dt(u, 0.5), T - t)
+        u, st = M.ssprk3_dt(u, dt, limiter=lim)
+        assert st["violations"] == 0 and st["fv_inadmissible"] == 0
+        t += dt
+    r = u[:, 0]
+    v1, v2 = u[:, 1] / r, u[:, 2] / r
+    p = (G - 1) * (u[:, 3] - 0.5 * r * (v1 ** 2 + v2 ** 2))
+    return (s, r, v1, v2, p) if axis == 0 else (s, r, v2, v1, p)
+
+
+@pytest.mark.parametrize("limiter", ["positivity", "local"])
+@pytest.mark.parametrize("axis,sign", [(0, 1), (0, -1), (1, 1), (1, -1)])
+def test_subsonic_contact_passes_both_ends(oracle, axis, sign, limiter):
+    """Density 2 enters through the subsonic inflow, whose exterior pressure (3)
+    must be ignored; a density bump leaves through the subsonic outflow, whose
+    exterior density and velocity (5; -0.3 and 0.7) must be ignored.  Velocity
+    and pressure stay exact; the density at the inflow end approaches 2."""
+    lim = oracle.LIM_POSITIVITY if limiter == "positivity" else oracle.LIM_LOCAL
+    inflow = (2.0, sign * 0.5, 0.0, 3.0)
+    outflow = (5.0, -0.3 * sign, 0.7, 1.0)
+    s_out = 0.95 if sign > 0 else 0.05
+    s, r, un, ut, p = _channel_run(oracle, axis, sign, *((inflow, outflow) if sign > 0 else (outflow, inflow)),
+                                   lambda s: 1.0 + 0.3 * np.exp(-((s - s_out) / 0.05) ** 2), 0.05, lim)
+    errs = np.abs(un - sign * 0.5).max(), np.abs(ut).max(), np.abs(p - 1.0).max()
+    near_in = s < 0.015 if sign > 0 else s > 0.985
+    print(f"contact axis {axis} sign {sign} {limiter}: |un - U| {errs[0]:.1e}, |ut| {errs[1]:.1e}, "
+          f"|p - 1| {errs[2]:.1e}; density at the inflow {r[near_in].mean():.4f}")
+    assert max(errs) < 1e-13
+    assert r[near_in].mean() > 1.9
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_subsonic_outflow_at_matching_pressure_is_plain_outflow(oracle, axis):
+    """At the interior pressure the subsonic outflow's ghost is the interior
+    state (up to the rounding of its energy), so the run equals the run with a
+    plain outflow there."""
+    inflow, outflow = (2.0, 0.5, 0.0, 3.0), (5.0, -0.3, 0.7, 1.0)
+    bump = lambda s: 1.0 + 0.3 * np.exp(-((s - 0.95) / 0.05) ** 2)
+    a = _channel_run(oracle, axis, 1, inflow, outflow, bump, 0.03)
+    b = _channel_run(oracle, axis, 1, inflow, outflow, bump, 0.03, bc_hi=oracle.BC_OUTFLOW)
+    err = max(np.abs(qa - qb).max() for qa, qb in zip(a[1:], b[1:]))
+    print(f"axis {axis}: characteristic outflow vs plain outflow {err:.1e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_subsonic_inflow_rarefaction(oracle, axis):
+    """The inflow end imposes density 1 and speed 0.45 (exterior pressure 7,
+    ignored) on the flow (1, 0.5, p = 1).  A rarefaction runs in; the outgoing
+    characteristics keep u - 2c/(gamma-1), so behind it, next to the end,
+    u = 0.45, rho = 1 and c = c0 + (gamma-1)/2 (0.45 - 0.5), p = (c/c0)^(2 gamma/(gamma-1))."""
+    Ue = 0.45
+    s, r, un, ut, p = _channel_run(oracle, axis, 1, (1.0, Ue, 0.0, 7.0), (1.0, 0.5, 0.0, 1.0),
+                                   lambda s: 1.0 + 0 * s, 0.2)
+    c0 = np.sqrt(G)
+    cm = c0 + 0.5 * (G - 1) * (Ue - 0.5)
+    pm = (cm / c0) ** (2 * G / (G - 1))
+    reg = s < 0.03  # the contact is at 0.09
+    e = np.abs(un[reg] - Ue).max(), np.abs(p[reg] - pm).max(), np.abs(r[reg] - 1.0).max()
+    print(f"inflow rarefaction axis {axis}: u {e[0]:.1e}, p {e[1]:.1e} (jump {1 - pm:.3f}), rho {e[2]:.1e}")
+    # the wave changes u by 0.05 and p by 0.058; the discretisation error at
+    # this resolution is about 1e-4
+    assert max(e) < 1e-3
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_subsonic_outflow_rarefaction(oracle, axis):
+    """The outflow end imposes pressure 0.95 (exterior density 3 and velocity
+    (-1, 0.4) ignored) on the flow (1, 0.5, p = 1).  A rarefaction runs in; the
+    outgoing characteristics keep u + 2c/(gamma-1) and the entropy, so next to
+    the end p = 0.95, rho = 0.95^(1/gamma) and u = 0.5 + 2 (c0 - c)/(gamma-1)."""
+    pe = 0.95
+    s, r, un, ut, p = _channel_run(oracle, axis, 1, (1.0, 0.5, 0.0, 1.0), (3.0, -1.0, 0.4, pe),
+                                   lambda s: 1.0 + 0 * s, 0.2)
+    rb = pe ** (1 / G)
+    cb = np.sqrt(G * pe / rb)
+    ub = 0.5 + 2 * (np.sqrt(G) - cb) / (G - 1)
+    reg = s > 0.95  # the rarefaction's tail is at 0.87
+    e = np.abs(un[reg] - ub).max(), np.abs(p[reg] - pe).max(), np.abs(r[reg] - rb).max(), np.abs(ut).max()
+    print(f"outflow rarefaction axis {axis}: u {e[0]:.1e} (jump {ub - 0.5:.3f}), p {e[1]:.1e}, rho {e[2]:.1e}, "
+          f"|ut| {e[3]:.1e}")
+    assert max(e[:3]) < 1e-3 and e[3] < 1e-13
 
 
 def test_ghost_rules(oracle):
