@@ -26,7 +26,7 @@ using namespace dgidp;
 // every array each time.  The state alternates between two slots so that an
 // adaptation can read the old state while it writes the new one.
 enum PoolSlot {
-    P_FNBR, P_FNBR2, P_FMORT, P_MORT, P_H, P_SNODE, P_SPART, P_PERM, P_BKIND, P_BEXT, P_SLOT,
+    P_FNBR, P_FNBR2, P_FMORT, P_MORT, P_H, P_SNODE, P_SPART, P_PERM, P_BKIND, P_BEXT, P_SLOT, P_BLIST,
     P_SHOCK, P_DLO, P_LOB, P_LSV, P_U0, P_U1, P_W1, P_W2, P_TKIND, P_TSRC, P_TGRP, P_TCOUNT,
     P_COUNT
 };
@@ -646,6 +646,7 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
         }
     }
     const int M = hm.M;
+    int nbm = 0;
     std::vector<double> hh(E * 2);
     for (int64_t i = 0; i < E; ++i) {
         const int e = hm.perm[i], l = level[e];
@@ -663,8 +664,21 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     ctx->Ly = Ly;
     ctx->nx0 = nx0;
     ctx->ny0 = ny0;
+    // stage-kernel batches with a mortar element first (their own launch)
+    const int64_t epb = stage_block_elems(N), nbat = (E + epb - 1) / epb;
+    std::vector<int> blist;
+    blist.reserve((size_t)nbat);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t bt = 0; bt < nbat; ++bt) {
+            bool mort = false;
+            for (int64_t i = bt * epb; i < std::min(E, (bt + 1) * epb) && !mort; ++i)
+                for (int f = 0; f < 4; ++f) mort = mort || hm.fmort[i * 4 + f] >= 0;
+            if (mort == (pass == 0)) blist.push_back((int)bt);
+            if (pass == 0 && mort) ++nbm;
+        }
     int rc = 0;
     if ((rc = upload(ctx, P_FNBR, ctx->dm.fnbr, hm.fnbr)) || (rc = upload(ctx, P_FNBR2, ctx->dm.fnbr2, hm.fnbr2)) ||
+        (rc = upload(ctx, P_BLIST, ctx->dm.blist, blist)) ||
         (rc = upload(ctx, P_FMORT, ctx->dm.fmort, hm.fmort)) ||
         (rc = upload(ctx, P_MORT, ctx->dm.mort, hm.mort)) || (rc = upload(ctx, P_H, ctx->dm.h, hh)) ||
         (rc = upload(ctx, P_SNODE, ctx->dm.slot_node, hm.snode)) ||
@@ -693,6 +707,7 @@ int dgidp_mesh_upload(dgidp_ctx* ctx, int64_t E, const int8_t* level, const int3
     ctx->M = M;
     ctx->dm.E = (int)E;
     ctx->dm.M = M;
+    ctx->dm.nbm = nbm;
     return 0;
 }
 

@@ -65,6 +65,11 @@ struct DevMesh {
     double* dlo = nullptr;      // [E*4*NN] R_LO / m of a stage's input (low-order-solution bounds)
     double* lob = nullptr;      // [E*3*NN] rho min, rho max, ln s min from the low-order solution
     double* lsv = nullptr;      // [E*2*NN] low-order density and ln s per node
+    // [ceil(E / stage_block_elems(N))] stage-kernel element batches: the nbm
+    // batches holding an element with a mortar face first, then the others,
+    // each part in ascending order
+    int* blist = nullptr;
+    int nbm = 0;
     int8_t* bkind = nullptr;    // [NB] condition of each boundary node (external numbering)
     double* bext = nullptr;     // [NB*4] exterior state of each boundary node
 };

@@ -82,14 +82,26 @@ struct Geo {
     static constexpr int PU = NN;  // sU variable stride
     static constexpr int PR = NN;  // sR variable stride
     // x and y pairs in two passes where the x pairs fill whole thread rounds
-    // (N = 4); the pair buffer then needs the larger of the subcell-face
-    // fluxes (2 NF), the mortar staging (12 n) and half the pairs with the x
-    // lines' telescoped fluxes
+    // (N = 4); the pair buffer then needs the larger of the mortar staging
+    // (12 n) and half the pairs with the x lines' telescoped fluxes.  The
+    // low-order subcell fluxes go to the primitive rows once those are read,
+    // so the pair buffer no longer holds them.
     static constexpr bool SPLIT = (n * NPL) % NN == 0;
-    // (one pad slot at N = 4: 80 slots per variable would give elements a
-    // 2,560-byte stride, a multiple of the 256-byte bank period, so that the
-    // elements sharing a wave would meet in the same banks)
-    static constexpr int PP = SPLIT ? (2 * NF > 12 * n ? 2 * NF : 12 * n) + 1 : NP;  // sPair variable stride
+    static constexpr int XH = n * NPL;  // SPLIT: the x lines' telescoped fluxes follow the pair slots
+    // (one pad slot at N = 4: an odd stride keeps the elements sharing a wave
+    // out of step with the 256-byte bank period)
+    static constexpr int PP = SPLIT ? (XH + n * N > 12 * n ? XH + n * N : 12 * n) + 1 : NP;  // sPair variable stride
+    // free pair slots after the telescoping (the slots N..NPL-1 of every line
+    // whose first N slots hold its telescoped fluxes) carry the surface terms
+    // of the face nodes: face f, position k in line f L + k / FR, slot N + k % FR
+    static constexpr int FR = NPL - N;
+    static constexpr int FL = (n + FR - 1) / FR;
+    static_assert(FR >= 1 && FL <= 2 && 4 * FL <= (SPLIT ? n : 2 * n), "surface-term slots");
+    static __device__ __forceinline__ int fslot(int f, int k)
+    {
+        if constexpr (FL == 1) return f * NPL + N + k;
+        else return (f * 2 + (k >= FR ? 1 : 0)) * NPL + N + (k >= FR ? k - FR : k);
+    }
 };
 
 // (l, k) of the node pairs l < k of a line, 6 bits per pair in line order
@@ -617,26 +629,28 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // accumulation of per-thread statistics, one atomic per wave; every lane of
-// the wave must call it
+// the wave must call it.  Counts are taken from lane masks (per lane: inad and
+// viol 0 or 1, nf 0, 1 or 2); the two floating-point reductions run only in
+// waves where some lane has a value to contribute.
 __device__ __forceinline__ void push_stats(DevStats* st, unsigned long long inad,
                                            unsigned long long viol, double thmin, double asum,
                                            unsigned long long nf, bool mortar)
 {
-    inad = wave_sum(inad);
-    viol = wave_sum(viol);
-    asum = wave_sum(asum);
-    nf = wave_sum(nf);
-    thmin = wave_min(thmin);
+    const unsigned long long ninad = __popcll(__ballot(inad != 0));
+    const unsigned long long nviol = __popcll(__ballot(viol != 0));
+    const unsigned long long nfs = __popcll(__ballot(nf >= 1)) + __popcll(__ballot(nf >= 2));
+    if (__ballot(asum != 0.0)) asum = wave_sum(asum);
+    if (__ballot(thmin < 1.0)) thmin = wave_min(thmin);
     if ((threadIdx.x & 63) == 0) {
-        if (inad) atomicAdd(&st->fv_inadmissible, inad);
-        if (viol) atomicAdd(&st->violations, viol);
-        if (nf) {
+        if (ninad) atomicAdd(&st->fv_inadmissible, ninad);
+        if (nviol) atomicAdd(&st->violations, nviol);
+        if (nfs) {
             if (mortar) {
                 atomicAdd(&st->alpha_mort_sum, asum);
-                atomicAdd(&st->nmortars, nf);
+                atomicAdd(&st->nmortars, nfs);
             } else {
                 atomicAdd(&st->alpha_vol_sum, asum);
-                atomicAdd(&st->nfaces, nf);
+                atomicAdd(&st->nfaces, nfs);
             }
         }
         if (thmin < 1.0) {
@@ -672,8 +686,13 @@ struct StageArgs {
     double* slot;
     const int8_t* bkind;  // boundary nodes: condition and exterior state
     const double* bext;
+    // element batches of this launch: blist[boff + i], i < gridDim.x (the
+    // batches holding a mortar element and the others are separate launches)
+    const int* blist;
+    int boff;
     int E;
     double gamma, beta;
+    double ig1;  // 1 / (gamma - 1)
     int limiter;
     int vflux;  // two-point volume flux: DGIDP_FLUX_RANOCHA or DGIDP_FLUX_CHANDRASHEKAR
     DevStats* st;
@@ -718,26 +737,38 @@ __device__ __forceinline__ void pair_lk(int i, int& l, int& k)
     k = l + 1 + r;
 }
 
-// node qq of the block's element le from its LDS copies
-#define LDS_NODE(X, qq)                                   \
-    do {                                                  \
-        for (int v_ = 0; v_ < 4; ++v_) X.u[v_] = sU[le][v_][qq]; \
-        X.r = sR[le][0][qq];                              \
-        X.v1 = sR[le][1][qq];                             \
-        X.v2 = sR[le][2][qq];                             \
-        X.p = sR[le][3][qq];                              \
-        X.c = sR[le][4][qq];                              \
+// node qq of the block's element le from its LDS primitives; the conserved
+// state is formed again from them (rho v = rho * v, E = p / (gamma - 1) +
+// (rho v . v) / 2: within a few ulp of the stored state, the same for every
+// reader of a node, so that equal states still meet in a zero flux difference)
+#define LDS_NODE(X, qq)                                                    \
+    do {                                                                   \
+        X.r = sR[le][0][qq];                                               \
+        X.v1 = sR[le][1][qq];                                              \
+        X.v2 = sR[le][2][qq];                                              \
+        X.p = sR[le][3][qq];                                               \
+        X.c = sR[le][4][qq];                                               \
+        X.u[0] = X.r;                                                      \
+        X.u[1] = X.r * X.v1;                                               \
+        X.u[2] = X.r * X.v2;                                               \
+        X.u[3] = fma(X.p, ig1, 0.5 * (X.u[1] * X.v1 + X.u[2] * X.v2));     \
     } while (0)
 
 // LIMK: 0 positivity (or none, at run time), 1 local bounds from bar states,
 // 2 the blend of positivity and bar-state local factors by the per-element
 // shock indicator A.ind (eq. combination_posLim_local), 3 local bounds from the
 // low-order solution (eq. Bounds_LowOrder), read from A.lob
-template <int N, int MODE, bool MIXED, int LIMK>
+// MORT: the launch over the element batches that hold a mortar element (the
+// surface phase with Kopriva's mortar and the sparse low-order mortar flux,
+// mortar slot records); the batches without one run the MORT = false variant,
+// which has no mortar code, fewer registers and four waves per SIMD.
+template <int N, int MODE, bool MIXED, int LIMK, bool MORT>
 // at least three waves per SIMD: the local-limiting variant would otherwise
 // take 172 registers and run two (63.3 against 67.7 us on the 22,156-leaf
-// blast with a few spilled registers; the other variants fit anyway)
-__global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3))) void k_stage(StageArgs A)
+// blast with a few spilled registers; the other variants fit anyway); the
+// conforming positivity variant fits 128 registers, four waves
+__global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu((!MORT && LIMK == 0) ? 4 : 3)))
+void k_stage(StageArgs A)
 {
     using G = Geo<N>;
     // LOC: local bounds enforced; COMB: blended with positivity; BAR: the bounds
@@ -751,25 +782,32 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
     constexpr bool DSTAT = (n * NPL) % NN == 0, SPLIT = G::SPLIT;
     constexpr int XH = n * NPL;  // SPLIT: the x lines' telescoped fluxes follow the pair slots
     static_assert(!SPLIT || (DSTAT && XH + n * N <= G::PP), "two-pass pair buffer");
-    static_assert(G::PP >= 2 * NF, "subcell face buffers reuse the pair buffer");
     static_assert(G::PP >= 12 * n, "mortar buffers reuse the pair buffer");
-    static_assert(G::PU >= NFN, "surface terms reuse the state buffer");
+    static_assert(G::PR == NN && 4 * NF + NN <= 8 * NN, "subcell fluxes and node factors reuse sR");
     constexpr int MB = 4 * n;  // offset of the mortar-node fluxes in the pair buffer
 
-    // variable-major, padded (see Geo)
-    __shared__ double sU[EPB][4][G::PU];
+    // variable-major (see Geo)
     __shared__ double sR[EPB][8][G::PR];     // rho, v1, v2, p, c, ln rho, z = rho/p, ln z
-    __shared__ double sPair[EPB][4][G::PP];  // pair fluxes; later FV and A of the subcell faces
+    __shared__ double sPair[EPB][4][G::PP];  // pair fluxes, then telescoped fluxes and surface terms
+    // bar states of local limiting: rows 0-3 the subcell faces owned by a node
+    // (x: density, log entropy; y: the same), rows 4-6 the face lanes' range
+    // across the element face; row 0 later the local node factors of the blend
+    __shared__ double sB[BAR ? EPB : 1][7][BAR ? NN : 1];
     __shared__ double sTw[2][n];              // LGL weights and their reciprocals, read per lane
     __shared__ double sS[n][n];               // Sbar, read per pair
-    // node factors of the volume limiter reuse the first row of sR (free after phase 5)
-#define sTh(qq) sR[le][0][qq]
+    // After phase 5b the primitive rows of sR are read no more: they take the
+    // low-order subcell fluxes, variable-major over the NF faces (x faces
+    // b N + a, y faces N n + a N + b), and after them the node factors.
+#define sFV(v, fi) sRe[(v) * NF + (fi)]
+#define sTh(qq) sRe[4 * NF + (qq)]
 
     const Tab<N>& tb = T<N>();
-    const double g = A.gamma, ig1 = 1.0 / (g - 1.0);
+    const double g = A.gamma, ig1 = A.ig1;
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
-    const int e = xcd_batch(blockIdx.x, gridDim.x) * EPB + le;
+    const int xb = xcd_batch(blockIdx.x, gridDim.x);
+    const int e = (A.blist ? A.blist[A.boff + xb] : xb) * EPB + le;
+    double* const sRe = &sR[0][0][0] + le * 8 * NN;  // element le's rows, flat
     const bool act = tid < NT && e < A.E;
     if (tid < n) {
         sTw[0][tid] = tb.w[tid];
@@ -820,10 +858,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
         hy = A.h[2 * e + 1];
         if (COMB) w_e = A.ind[e];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            sU[le][v][q] = me.u[v];
-            u0[v] = me.u[v];
-        }
+        for (int v = 0; v < 4; ++v) u0[v] = me.u[v];
         // the logarithms feed only the two-point volume fluxes: FP32 in the
         // mixed mode, where rows 5-7 hold the FP32 operands of those fluxes in
         // pairs (rho, p), (ln rho, z), (ln z, 0)
@@ -863,7 +898,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
                 bk = A.bkind[j];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) onb[v] = A.bext[(size_t)j * 4 + v];
-            } else if (!fm_small(fcode_f)) {
+            } else if (MORT && !fm_small(fcode_f)) {
                 // large side: both small traces at position fk, kept in
                 // registers for the mortar-node fluxes and staged for the
                 // sparse low-order pairs of the other positions
@@ -875,7 +910,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
                     sPair[le][v][MB + (ff * 2 + 1) * n + fk] = us1[v];
                 }
                 blk_mortar = true;
-            } else {
+            } else if (MORT) {
                 // small side: stage the large face trace for the interpolation
                 double w[4];
                 load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), w);
@@ -885,7 +920,10 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             }
         }
     }
-    const bool any_mortar = __syncthreads_or(blk_mortar);
+    // (every batch of the mortar launch holds a mortar element)
+    __syncthreads();
+    constexpr bool any_mortar = MORT;
+    (void)blk_mortar;
     double dt;
     if (A.dtmax) {
         const double m = wave_max(dtpart);
@@ -924,7 +962,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             const double W = sgf * sTw[0][fk] * hff * 0.5;
 #pragma unroll
             for (int v = 0; v < 4; ++v) fterm[v] = W * F[v];
-        } else if (!fm_small(fcode_f)) {
+        } else if (MORT && !fm_small(fcode_f)) {
             // large side: mortar-node fluxes at position fk of both halves
             // (kept in registers until every lane has read the staged small
             // traces), and the sparse low-order pairs of this node
@@ -933,20 +971,23 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
 #pragma unroll
                 for (int v = 0; v < 4; ++v) us.u[v] = hh == 0 ? onb[v] : us1[v];
                 make_node(us, g);
+                // the large face interpolated to half hh, from the face nodes'
+                // conserved states formed as LDS_NODE does
+                double ia[4] = {0, 0, 0, 0};
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    if (MIXED) {
-                        float acc = 0.0f;
+                for (int j = 0; j < n; ++j) {
+                    const int qj = face_q<N>(ff, j);
+                    const double r = sR[le][0][qj], v1 = sR[le][1][qj], v2 = sR[le][2][qj];
+                    const double m1 = r * v1, m2 = r * v2;
+                    const double uj[4] = {r, m1, m2, fma(sR[le][3][qj], ig1, 0.5 * (m1 * v1 + m2 * v2))};
 #pragma unroll
-                        for (int j = 0; j < n; ++j) acc += tb.If[hh][fk][j] * (float)sU[le][v][face_q<N>(ff, j)];
-                        ui.u[v] = acc;
-                    } else {
-                        double acc = 0.0;
-#pragma unroll
-                        for (int j = 0; j < n; ++j) acc += tb.I[hh][fk][j] * sU[le][v][face_q<N>(ff, j)];
-                        ui.u[v] = acc;
+                    for (int v = 0; v < 4; ++v) {
+                        if (MIXED) ia[v] = (float)ia[v] + tb.If[hh][fk][j] * (float)uj[v];
+                        else ia[v] += tb.I[hh][fk][j] * uj[v];
                     }
                 }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ui.u[v] = ia[v];
                 make_node(ui, g);
                 double F[4];
                 mortar_flux(dff, lowf, ui, us, F);
@@ -982,7 +1023,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
                 }
 #pragma unroll
             for (int v = 0; v < 4; ++v) fterm[v] = lo[v];
-        } else {
+        } else if (MORT) {
             // small side: interpolate the large face, LLF on the mortar = this face
             const int hh = fm_half(fcode_f);
             NodeP ui;
@@ -1036,7 +1077,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             }
         }
     }
-    if (any_mortar) {
+    if constexpr (any_mortar) {
         __syncthreads();
         // ---- phase 3: large sides publish and project the mortar fluxes ----
         const bool large = fnode && fcode_f >= 0 && !fm_small(fcode_f);
@@ -1206,18 +1247,19 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
         }
     }
     // ---- phase 5b: low-order subcell fluxes of the faces owned by this node,
-    // x (a|a+1) and y (b|b+1), and the antidiffusive fluxes ----
-    double FVo[2][4], Ao[2][4];
+    // x (a|a+1) and y (b|b+1) ----
+    double FVo[2][4];
     double brb[2] = {0.0, 0.0}, bls[2] = {0.0, 0.0};  // bar state of each owned subcell face
     if (act) {
+        NodeP me;
+        LDS_NODE(me, q);
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
             const int pos = d == 0 ? a : b;
             if (pos >= N) continue;
             const int qn = d == 0 ? q + 1 : q + n;
-            NodeP o, me;
+            NodeP o;
             LDS_NODE(o, qn);
-            LDS_NODE(me, q);
             double F[4];
             llf_face(d, true, me, o, F);
             if (BAR && need_loc) bar_bounds(d, true, me, o, g, brb[d], bls[d]);
@@ -1226,91 +1268,90 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             for (int v = 0; v < 4; ++v) FVo[d][v] = hs * F[v];
         }
     }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int d = 0; d < 2; ++d) {
-            const int pos = d == 0 ? a : b, line = d == 0 ? b : a;
-            if (pos >= N) continue;
-            const int slot = SPLIT ? (d == 0 ? XH + line * N + pos : line * NPL + pos) : (d * n + line) * NPL + pos;
-            const double wl = sTw[0][line];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Ao[d][v] = wl * (sPair[le][v][slot] - FVo[d][v]);
-        }
-    }
+    // every read of the primitives (and of the pairs, by the telescoping) is done
     __syncthreads();
     if (act) {
         if (a < N) {
-            const int fi = b * N + a;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                sPair[le][v][fi] = FVo[0][v];
-                sPair[le][v][NF + fi] = Ao[0][v];
-            }
+            for (int v = 0; v < 4; ++v) sFV(v, b * N + a) = FVo[0][v];
         }
         if (b < N) {
-            const int fi = N * n + a * N + b;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                sPair[le][v][fi] = FVo[1][v];
-                sPair[le][v][NF + fi] = Ao[1][v];
-            }
+            for (int v = 0; v < 4; ++v) sFV(v, N * n + a * N + b) = FVo[1][v];
         }
     }
-    // sU is no longer read: it now carries the surface terms of the face nodes
+    // the face lanes' surface terms go to the free pair slots
     if (fnode) {
+        const int fs = G::fslot(ff, fk);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sU[le][v][q] = fterm[v];
+        for (int v = 0; v < 4; ++v) sPair[le][v][fs] = fterm[v];
     }
-    // sR rows 1..7 are no longer read: rows 1-4 take the bar states of the
-    // subcell faces owned by this node (x: density, log entropy; y: the same),
-    // rows 5-7 the face lanes' bar-state range across the element face
     if (BAR && need_loc) {
         if (a < N) {
-            sR[le][1][q] = brb[0];
-            sR[le][2][q] = bls[0];
+            sB[le][0][q] = brb[0];
+            sB[le][1][q] = bls[0];
         }
         if (b < N) {
-            sR[le][3][q] = brb[1];
-            sR[le][4][q] = bls[1];
+            sB[le][2][q] = brb[1];
+            sB[le][3][q] = bls[1];
         }
         if (fnode) {
-            sR[le][5][q] = fb_lo;
-            sR[le][6][q] = fb_hi;
-            sR[le][7][q] = fb_ls;
+            sB[le][4][q] = fb_lo;
+            sB[le][5][q] = fb_hi;
+            sB[le][6][q] = fb_ls;
         }
     }
     __syncthreads();
 
     // ---- phase 6: low-order residual, bounds, node factors ----
     if (act && MODE == MODE_STAGE && A.a != 0.0) load_u<N>(A.un, e, q, un4);
-    const int fxl = b * N + a - 1, fxr = b * N + a;                  // x faces left / right
-    const int fyb = N * n + a * N + b - 1, fyt = N * n + a * N + b;  // y faces below / above
     const bool onf[4] = {a == 0, a == N, b == 0, b == N};
-    const int fnq[4] = {0 * n + b, 1 * n + b, 2 * n + a, 3 * n + a};  // face-node index per face
+    // the four subcell faces j of the node (left, right, below, above), each
+    // taken at a clamped in-range position of the node's own line; a missing
+    // face (on the element boundary) has weight 0.  Face index (x faces
+    // b N + pos, y faces N n + a N + pos), slot of the telescoped high-order
+    // flux (x faces on line b, y faces on line a) and signed weight (+w on the
+    // left / lower face, -w on the right / upper one), formed where used.
+    auto fpos = [&](int j) {
+        return j == 0 ? (a > 0 ? a - 1 : 0) : j == 1 ? (a < N ? a : N - 1) : j == 2 ? (b > 0 ? b - 1 : 0)
+                                                                             : (b < N ? b : N - 1);
+    };
+    auto fidx = [&](int j) { return j < 2 ? b * N + fpos(j) : N * n + a * N + fpos(j); };
+    auto hslot = [&](int j) {
+        if (SPLIT) return j < 2 ? XH + b * N + fpos(j) : a * NPL + fpos(j);
+        return j < 2 ? b * NPL + fpos(j) : (n + a) * NPL + fpos(j);
+    };
+    auto fweight = [&](int j) {
+        const double w = sTw[0][j < 2 ? b : a];
+        const bool has = j == 0 ? a > 0 : j == 1 ? a < N : j == 2 ? b > 0 : b < N;
+        return has ? ((j & 1) ? -w : w) : 0.0;
+    };
     double RLO[4], dS0[4] = {0, 0, 0, 0}, dS1[4] = {0, 0, 0, 0};
     int slot0 = -1, slot1 = -1, nmf = 0;
     double im = 1.0;  // 1 / m_i
+    // antidiffusive flux w (f^HO - f^FV) of face j, signed as its weight, variable v
+    auto antidiff = [&](int j, int v) { return fweight(j) * (sPair[le][v][hslot(j)] - sFV(v, fidx(j))); };
     if (act) {
         im = 4.0 * frcp(hx * hy) * sTw[1][a] * sTw[1][b];
-        const double wa = sTw[0][a], wb = sTw[0][b];
+        const double cw[4] = {fweight(0), fweight(1), fweight(2), fweight(3)};
+        const int fi[4] = {fidx(0), fidx(1), fidx(2), fidx(3)};
+        const double cs[4] = {onf[0] ? 1.0 : 0.0, onf[1] ? 1.0 : 0.0, onf[2] ? 1.0 : 0.0, onf[3] ? 1.0 : 0.0};
+        const int fs[4] = {G::fslot(0, b), G::fslot(1, b), G::fslot(2, a), G::fslot(3, a)};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double r = 0.0;
-            if (a > 0) r += wb * sPair[le][v][fxl];
-            if (a < N) r -= wb * sPair[le][v][fxr];
-            if (b > 0) r += wa * sPair[le][v][fyb];
-            if (b < N) r -= wa * sPair[le][v][fyt];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r = fma(cw[j], sFV(v, fi[j]), r);
+            // surface terms of the element faces the node lies on
+#pragma unroll
+            for (int f = 0; f < 4; ++f) r = fma(cs[f], sPair[le][v][fs[f]], r);
             RLO[v] = r;
         }
+        if constexpr (MORT) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (!onf[f]) continue;
-            const int fq = fnq[f];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) RLO[v] += sU[le][v][fq];
-            const int code = fcode[f];
-            if (code >= 0) {
+            for (int f = 0; f < 4; ++f) {
+                const int code = fcode[f];
+                if (!onf[f] || code < 0) continue;
                 const int S = fm_mortar(code), k = f < 2 ? b : a;
                 const int sid = fm_small(code) ? S * 3 * n + n + fm_half(code) * n + k : S * 3 * n + k;
                 if (nmf == 0) {
@@ -1332,10 +1373,7 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             for (int v = 0; v < 4; ++v) {
                 double r = RLO[v];
                 if (MODE == MODE_RHS_HIGH) {
-                    if (a > 0) r += sPair[le][v][NF + fxl];
-                    if (a < N) r -= sPair[le][v][NF + fxr];
-                    if (b > 0) r += sPair[le][v][NF + fyb];
-                    if (b < N) r -= sPair[le][v][NF + fyt];
+                    r += antidiff(0, v) + antidiff(1, v) + antidiff(2, v) + antidiff(3, v);
                     r += dS0[v] + dS1[v];
                 }
                 A.uout[((unsigned)e * 4u + v) * NN + q] = r * im;
@@ -1378,49 +1416,41 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             rhi = u0[0];
             lsm = ls_own;
             if (a > 0) {
-                rlo = fmin(rlo, sR[le][1][q - 1]);
-                rhi = fmax(rhi, sR[le][1][q - 1]);
-                lsm = fmin(lsm, sR[le][2][q - 1]);
+                rlo = fmin(rlo, sB[le][0][q - 1]);
+                rhi = fmax(rhi, sB[le][0][q - 1]);
+                lsm = fmin(lsm, sB[le][1][q - 1]);
             }
             if (a < N) {
-                rlo = fmin(rlo, sR[le][1][q]);
-                rhi = fmax(rhi, sR[le][1][q]);
-                lsm = fmin(lsm, sR[le][2][q]);
+                rlo = fmin(rlo, sB[le][0][q]);
+                rhi = fmax(rhi, sB[le][0][q]);
+                lsm = fmin(lsm, sB[le][1][q]);
             }
             if (b > 0) {
-                rlo = fmin(rlo, sR[le][3][q - n]);
-                rhi = fmax(rhi, sR[le][3][q - n]);
-                lsm = fmin(lsm, sR[le][4][q - n]);
+                rlo = fmin(rlo, sB[le][2][q - n]);
+                rhi = fmax(rhi, sB[le][2][q - n]);
+                lsm = fmin(lsm, sB[le][3][q - n]);
             }
             if (b < N) {
-                rlo = fmin(rlo, sR[le][3][q]);
-                rhi = fmax(rhi, sR[le][3][q]);
-                lsm = fmin(lsm, sR[le][4][q]);
+                rlo = fmin(rlo, sB[le][2][q]);
+                rhi = fmax(rhi, sB[le][2][q]);
+                lsm = fmin(lsm, sB[le][3][q]);
             }
+            const int fnq[4] = {0 * n + b, 1 * n + b, 2 * n + a, 3 * n + a};  // face lane of each face
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 if (!onf[f]) continue;
-                rlo = fmin(rlo, sR[le][5][fnq[f]]);
-                rhi = fmax(rhi, sR[le][6][fnq[f]]);
-                lsm = fmin(lsm, sR[le][7][fnq[f]]);
+                rlo = fmin(rlo, sB[le][4][fnq[f]]);
+                rhi = fmax(rhi, sB[le][5][fnq[f]]);
+                lsm = fmin(lsm, sB[le][6][fnq[f]]);
             }
             // the positivity floor stays: the density floor is the larger one
             rlf = fmax(rmin, rlo);
         }
-        // missing faces (on the element boundary) take a zero increment: their
-        // (clamped, in-range) table entry is multiplied by 0
-        {
-            const double m0 = a > 0 ? dtm : 0.0, m1 = a < N ? -dtm : 0.0;
-            const double m2 = b > 0 ? dtm : 0.0, m3 = b < N ? -dtm : 0.0;
-            const int i0 = NF + max(fxl, 0), i3 = NF + min(fyt, NF - 1);
+        // the faces' increments dt / m_i w (f^HO - f^FV), signed (zero for missing faces)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                cf[0][v] = m0 * sPair[le][v][i0];
-                cf[1][v] = m1 * sPair[le][v][NF + fxr];
-                cf[2][v] = m2 * sPair[le][v][NF + fyb];
-                cf[3][v] = m3 * sPair[le][v][i3];
-            }
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cf[j][v] = dtm * antidiff(j, v);
         if (A.limiter != DGIDP_LIMIT_NONE) {
             if (PURE) {
                 th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, lsi, g, ig1);
@@ -1430,11 +1460,12 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
             }
         }
     }
-    // the blend keeps the local node factors in row 1, read above for the bounds
+    // the blend keeps its local node factors in the first bar-state row, read
+    // above for the bounds
     if (COMB) __syncthreads();
     if (act) {
         sTh(q) = th;
-        if (COMB) sR[le][1][q] = thl;
+        if (COMB) sB[le][0][q] = thl;
     }
     __syncthreads();
 
@@ -1446,17 +1477,14 @@ __global__ __launch_bounds__(Geo<N>::BS) __attribute__((amdgpu_waves_per_eu(3)))
         double tf[4];
         // face factor: the smaller of its two node factors; blended:
         // (1 - w) theta_pos + w theta_local
-        const int qn4[4] = {q - 1, q + 1, q - n, q + n};
+        // (a missing face reads the node itself and takes 0)
         const bool has[4] = {a > 0, a < N, b > 0, b < N};
+        const int qn4[4] = {has[0] ? q - 1 : q, has[1] ? q + 1 : q, has[2] ? q - n : q, has[3] ? q + n : q};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (!has[j]) {
-                tf[j] = 0.0;
-            } else if (COMB) {
-                tf[j] = (1.0 - w_e) * fmin(th, sTh(qn4[j])) + w_e * fmin(thl, sR[le][1][qn4[j]]);
-            } else {
-                tf[j] = fmin(th, sTh(qn4[j]));
-            }
+            const double t = COMB ? (1.0 - w_e) * fmin(th, sTh(qn4[j])) + w_e * fmin(thl, sB[le][0][qn4[j]])
+                                  : fmin(th, sTh(qn4[j]));
+            tf[j] = has[j] ? t : 0.0;
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -2480,37 +2508,72 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.mort = m.mort;
     A.h = m.h;
     A.slot = m.slot;
+    A.blist = m.blist;
     A.E = m.E;
     A.gamma = kp.gamma;
+    A.ig1 = 1.0 / (kp.gamma - 1.0);
     A.beta = kp.beta;
     A.limiter = kp.limiter;
     A.vflux = kp.vflux;
     A.st = st;
-    const int grid = (m.E + G::EPB - 1) / G::EPB;
+    const int nb = (m.E + G::EPB - 1) / G::EPB;
     const bool mixed = kp.precision == DGIDP_MIXED;
-    const dim3 blk(G::BS);
     const int lk = kp.limiter == DGIDP_LIMIT_LOCAL ? 1
                    : kp.limiter == DGIDP_LIMIT_COMBINED ? 2
                    : kp.limiter == DGIDP_LIMIT_LOCAL_LOWORDER ? 3 : 0;
+    // Positivity limiting on a large mesh: the batches with a mortar element
+    // (the first m.nbm entries of the batch list) in one launch, the others in
+    // a second one without mortar code (four waves per SIMD instead of three).
+    // The mortar launch ends with a partly idle GPU, so a mesh of fewer than
+    // kSplitMin batches, or with a larger mortar share, runs as one launch of
+    // the mortar variant; so do the local-limiting modes, whose conforming
+    // variant keeps three waves per SIMD.  A mesh without mortars runs the
+    // conforming variant alone.
+    constexpr int kSplitMin = 16384;
+    const bool split = m.nbm == 0 || (lk == 0 && nb >= kSplitMin && 8LL * m.nbm <= nb);
+    auto go = [&](auto modec, auto mixc, auto lkc) {
+        constexpr int MD = decltype(modec)::value, LK = decltype(lkc)::value;
+        constexpr bool MX = decltype(mixc)::value;
+        if (!split) {
+            A.blist = nullptr;  // element batches in mesh order
+            A.boff = 0;
+            hipLaunchKernelGGL((k_stage<N, MD, MX, LK, true>), dim3(nb), dim3(G::BS), 0, s, A);
+            return;
+        }
+        A.blist = m.nbm > 0 ? m.blist : nullptr;
+        if (m.nbm > 0) {
+            A.boff = 0;
+            hipLaunchKernelGGL((k_stage<N, MD, MX, LK, true>), dim3(m.nbm), dim3(G::BS), 0, s, A);
+        }
+        if (nb > m.nbm) {
+            A.boff = m.nbm;
+            hipLaunchKernelGGL((k_stage<N, MD, MX, LK, false>), dim3(nb - m.nbm), dim3(G::BS), 0, s, A);
+        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using BT = std::true_type;
+    using BF = std::false_type;
     if (mode == MODE_STAGE) {
+        using MS = std::integral_constant<int, MODE_STAGE>;
         if (lk == 3) {
-            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 3>), dim3(grid), blk, 0, s, A);
-            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 3>), dim3(grid), blk, 0, s, A);
+            if (mixed) go(MS(), BT(), std::integral_constant<int, 3>());
+            else go(MS(), BF(), std::integral_constant<int, 3>());
         } else if (lk == 1) {
-            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 1>), dim3(grid), blk, 0, s, A);
-            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 1>), dim3(grid), blk, 0, s, A);
+            if (mixed) go(MS(), BT(), std::integral_constant<int, 1>());
+            else go(MS(), BF(), std::integral_constant<int, 1>());
         } else if (lk == 2) {
-            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 2>), dim3(grid), blk, 0, s, A);
-            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 2>), dim3(grid), blk, 0, s, A);
+            if (mixed) go(MS(), BT(), std::integral_constant<int, 2>());
+            else go(MS(), BF(), std::integral_constant<int, 2>());
         } else {
-            if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_STAGE, true, 0>), dim3(grid), blk, 0, s, A);
-            else hipLaunchKernelGGL((k_stage<N, MODE_STAGE, false, 0>), dim3(grid), blk, 0, s, A);
+            if (mixed) go(MS(), BT(), I0());
+            else go(MS(), BF(), I0());
         }
     } else if (mode == MODE_RHS_HIGH) {
-        if (mixed) hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, true, 0>), dim3(grid), blk, 0, s, A);
-        else hipLaunchKernelGGL((k_stage<N, MODE_RHS_HIGH, false, 0>), dim3(grid), blk, 0, s, A);
+        using MH = std::integral_constant<int, MODE_RHS_HIGH>;
+        if (mixed) go(MH(), BT(), I0());
+        else go(MH(), BF(), I0());
     } else {
-        hipLaunchKernelGGL((k_stage<N, MODE_RHS_LOW, false, 0>), dim3(grid), blk, 0, s, A);
+        go(std::integral_constant<int, MODE_RHS_LOW>(), BF(), I0());
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
