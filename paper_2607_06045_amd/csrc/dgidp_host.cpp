@@ -319,10 +319,24 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
     });
     // internal order: Morton order of the leaves on the finest grid, cut into
     // the eight contiguous ranges that the stage kernel hands to the eight
-    // XCDs; inside each range the leaves with a nonconforming face come first.
-    // A wave then holds either mortar elements (with their longer surface
-    // work) or none, and the longer waves start first on each XCD instead of
-    // ending the launch late.
+    // XCDs; inside each range the leaves that are the small side of a mortar
+    // come first, then those that are a large side, then the others.  A wave
+    // then holds either mortar elements (with their longer surface work) or
+    // none, mostly of one side, and the longer waves start first on each XCD
+    // instead of ending the launch late.
+    // role: 0 small side only, 1 large side, 2 no nonconforming face
+    std::vector<int8_t> role((size_t)E, 2);
+    par_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e)
+            for (int f = 0; f < 4; ++f) {
+                if (bface[e * 4 + f] >= 0 || same[e * 4 + f] >= 0) continue;
+                // two finer leaves across the face: a large side
+                const int64_t cx = f == 0 ? 2 * (int64_t)ix[e] - 1 : f == 1 ? 2 * (int64_t)ix[e] + 2 : 2 * (int64_t)ix[e];
+                const int64_t cy = f == 2 ? 2 * (int64_t)iy[e] - 1 : f == 3 ? 2 * (int64_t)iy[e] + 2 : 2 * (int64_t)iy[e];
+                if (lookup(level[e] + 1, cx, cy) >= 0) role[e] = 1;
+                else if (role[e] == 2) role[e] = 0;
+            }
+    });
     std::vector<std::pair<uint64_t, int>> ord((size_t)E);
     par_for(E, [&](int64_t lo, int64_t hi) {
         for (int64_t e = lo; e < hi; ++e) {
@@ -339,12 +353,10 @@ int build_host_mesh(int N, int64_t E, const int8_t* level, const int32_t* ix, co
             for (int64_t x = x0; x < x1; ++x) {
                 const int64_t g0 = x * q + std::min<int64_t>(x, r), gn = q + (x < r ? 1 : 0);
                 const int64_t lo = std::min<int64_t>(E, g0 * epb), hi = std::min<int64_t>(E, (g0 + gn) * epb);
-                std::stable_partition(ord.begin() + lo, ord.begin() + hi, [&](const std::pair<uint64_t, int>& o) {
-                    const int e = o.second;
-                    for (int f = 0; f < 4; ++f)
-                        if (bface[e * 4 + f] < 0 && same[e * 4 + f] < 0) return true;
-                    return false;
-                });
+                std::stable_sort(ord.begin() + lo, ord.begin() + hi,
+                                 [&](const std::pair<uint64_t, int>& p1, const std::pair<uint64_t, int>& p2) {
+                                     return role[p1.second] < role[p2.second];
+                                 });
             }
         }, 1);
     }

@@ -33,6 +33,11 @@ struct Tab {
     double I[2][n][n];            // mortar interpolation: half h, small node l, large node k
     double P[2][n][n];            // L2 projection: half h, large node k, small node l
     double Wt[n][2 * n];          // sparse mortar weights, reference measure on [-1, 1]
+    // their nonzero entries: per large-face node k the count and the columns
+    // h n + l in ascending order; per small-face node (h, l) the count and the
+    // large-face nodes k in ascending order
+    int lnc[n], lnz[n][2 * n];
+    int snc[2][n], snz[2][n][n];
     float wf[n], Sf[n][n], If[2][n][n], Pf[2][n][n];  // FP32 copies for the mixed mode
     double Vinv[n][n];            // nodal -> modal, orthonormal Legendre: m_i = sum_a Vinv[i][a] q_a
 };

@@ -997,30 +997,31 @@ void k_stage(StageArgs A)
                     else us1[v] = F[v];
                 }
             }
+            // (over this node's nonzero weights only: a wave runs as many
+            // rounds as its busiest lane)
             double lo[4] = {0, 0, 0, 0};
+            const int nz = tb.lnc[fk];
+#pragma unroll 1
+            for (int i = 0; i < nz; ++i) {
+                const int col = tb.lnz[fk][i];  // h n + l
+                const double wt = tb.Wt[fk][col];
+                NodeP us;
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-                for (int l = 0; l < n; ++l) {
-                    const double wt = tb.Wt[fk][hh * n + l];
-                    if (wt == 0.0) continue;
-                    NodeP us;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) us.u[v] = sPair[le][v][MB + (ff * 2 + hh) * n + l];
-                    make_node(us, g);
-                    double Gf[4];
-                    llf_face(dff, lowf, own, us, Gf);
-                    if (BAR && need_loc) {
-                        double rb, lb;
-                        bar_bounds(dff, lowf, own, us, g, rb, lb);
-                        fb_lo = fmin(fb_lo, rb);
-                        fb_hi = fmax(fb_hi, rb);
-                        fb_ls = fmin(fb_ls, lb);
-                    }
-                    const double W = sgf * wt * hff * 0.5;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
+                for (int v = 0; v < 4; ++v) us.u[v] = sPair[le][v][MB + ff * 2 * n + col];
+                make_node(us, g);
+                double Gf[4];
+                llf_face(dff, lowf, own, us, Gf);
+                if (BAR && need_loc) {
+                    double rb, lb;
+                    bar_bounds(dff, lowf, own, us, g, rb, lb);
+                    fb_lo = fmin(fb_lo, rb);
+                    fb_hi = fmax(fb_hi, rb);
+                    fb_ls = fmin(fb_ls, lb);
                 }
+                const double W = sgf * wt * hff * 0.5;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) lo[v] += W * Gf[v];
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) fterm[v] = lo[v];
         } else if (MORT) {
@@ -1046,10 +1047,11 @@ void k_stage(StageArgs A)
             mortar_flux(dff, !lowf, ui, own, F);
 #pragma unroll
             for (int v = 0; v < 4; ++v) ho[v] = sgf * sTw[0][fk] * hff * 0.5 * F[v];
-#pragma unroll
-            for (int j = 0; j < n; ++j) {
+            const int nz = tb.snc[hh][fk];
+#pragma unroll 1
+            for (int i = 0; i < nz; ++i) {
+                const int j = tb.snz[hh][fk][i];
                 const double wt = tb.Wt[j][hh * n + fk];
-                if (wt == 0.0) continue;
                 NodeP uj;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) uj.u[v] = sPair[le][v][ff * n + j];

@@ -252,6 +252,23 @@ void build(Tab<N>& t)
                 const ld hi = std::min(-1 + C[k + 1], -1 + h + C[l + 1] / 2);
                 t.Wt[k][h * n + l] = hi - lo > 1e-12L ? (double)(hi - lo) : 0.0;
             }
+    for (int k = 0; k < n; ++k) {
+        int c = 0;
+        for (int j = 0; j < 2 * n; ++j) {
+            t.lnz[k][j] = 0;
+            if (t.Wt[k][j] != 0.0) t.lnz[k][c++] = j;
+        }
+        t.lnc[k] = c;
+    }
+    for (int h = 0; h < 2; ++h)
+        for (int l = 0; l < n; ++l) {
+            int c = 0;
+            for (int k = 0; k < n; ++k) {
+                t.snz[h][l][k] = 0;
+                if (t.Wt[k][h * n + l] != 0.0) t.snz[h][l][c++] = k;
+            }
+            t.snc[h][l] = c;
+        }
     // modal transform: V[a][i] = sqrt((2i+1)/2) P_i(x_a), Vinv = V^-1
     {
         std::vector<std::vector<ld>> V(n, std::vector<ld>(n, 0)), R(n, std::vector<ld>(n, 0));

@@ -16,7 +16,10 @@ CMD="bash paper_2607_06045_amd/profile_bench.sh"
 BT="python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline --legs none"
 BC="python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --legs none"
 CP="python3 -m paper_2607_06045_amd.profiling copy --mib 512"
-KERNEL="k_stage<4, 0, false, 0>"
+# one stage is two launches of the element kernel: k_stage<4, 0, false, 0, true>
+# over the element batches with a mortar element, k_stage<4, 0, false, 0, false>
+# over the others; the summaries add the two per stage
+KERNEL="k_stage<4, 0, false, 0,"
 
 echo "== kernel trace: $BT"
 timeout -k 10 300 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o trace --output-format csv -- $BT \
@@ -34,16 +37,20 @@ pmc copyfetch FETCH_SIZE $CP || exit 1
 pmc copywrite WRITE_SIZE $CP || exit 1
 pmc sqa "SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VALU_INT32 SQ_BUSY_CYCLES" $BC || exit 1
 pmc sqb "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64" $BC || exit 1
+# issue and stall counters (optional: the summary goes without them if this pass fails)
+SQC=""
+pmc sqc "SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_ANY SQ_INSTS_LDS SQ_WAIT_ANY" $BC \
+    && SQC="$OUT/sqc"
 
 STATS=$(find "$OUT/trace" -name '*kernel_stats.csv' | head -1)
 python3 -m paper_2607_06045_amd.profiling stats --csv "$STATS" \
     --out "$OUT/summary/kernels_k_stage_quadrants247k.txt" \
-    --title "kernel durations, bench.py headline workload (four-quadrant states, 246,736 leaves, N=4, FP64; 20 steps + kernel timing; $KERNEL is the stage kernel)" \
+    --title "kernel durations, bench.py headline workload (four-quadrant states, 246,736 leaves, N=4, FP64; 20 steps + kernel timing; one stage = the two k_stage<4, 0, false, 0, *> launches)" \
     --command "$CMD" --trace-csv "$(find "$OUT/trace" -name '*kernel_trace.csv' | head -1)" \
     --kernel "$KERNEL" --tail 150 --bench-log "$OUT/trace.log" || exit 1
 python3 -m paper_2607_06045_amd.profiling counters --fetch "$OUT/fetch" --write "$OUT/write" \
     --copy-fetch "$OUT/copyfetch" --copy-write "$OUT/copywrite" --copy-mib 512 \
-    --sq "$OUT/sqa" "$OUT/sqb" --kernel "$KERNEL" \
+    --sq "$OUT/sqa" "$OUT/sqb" $SQC --kernel "$KERNEL" \
     --workload "four-quadrant states, 246,736 leaves, N=4, FP64; mean over the three stage configurations" \
     --dofs 6168400 --algorithmic-bytes-per-node 85.33333333333333 \
     --out "$OUT/summary/counters_k_stage_quadrants247k.json" --command "$CMD" || exit 1

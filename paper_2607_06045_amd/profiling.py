@@ -47,18 +47,25 @@ def _counter_rows(d):
     return rows
 
 
-def _mean_counter(rows, name_part, counter):
-    vals = [float(r["Counter_Value"]) for r in rows
-            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
-    if not vals:
-        raise SystemExit(f"no {counter} rows for kernels matching {name_part!r}")
-    return sum(vals) / len(vals), len(vals)
-
-
 def _mean_counter_opt(rows, name_part, counter):
-    vals = [float(r["Counter_Value"]) for r in rows
-            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
-    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+    """Counter per launch of the kernels whose names contain name_part: the
+    mean over the dispatches of each matching kernel, summed over the matching
+    kernels (one stage of the element kernel is a launch of each of its
+    variants that the mesh needs), and the number of dispatches per kernel."""
+    per = {}
+    for r in rows:
+        if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    if not per:
+        return None, 0
+    return sum(sum(v) / len(v) for v in per.values()), {k.split("(")[0]: len(v) for k, v in per.items()}
+
+
+def _mean_counter(rows, name_part, counter):
+    v, k = _mean_counter_opt(rows, name_part, counter)
+    if v is None:
+        raise SystemExit(f"no {counter} rows for kernels matching {name_part!r}")
+    return v, k
 
 
 def counters(a):
@@ -124,13 +131,30 @@ def timed_region(a):
     profiled bench.py run printed for that kernel."""
     with open(a.trace_csv) as fh:
         rows = [r for r in csv.DictReader(fh) if r["Kernel_Name"].startswith("void dgidp::" + a.kernel)]
-    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[-a.tail:]]
-    if not d:
+    if not rows:
         raise SystemExit(f"no dispatches of {a.kernel!r} in {a.trace_csv}")
-    mean = sum(d) / len(d)
-    out = [f"# {a.kernel}: mean over its last {len(d)} dispatches (bench.py's kernel-timing region): "
-           f"{mean:.2f} us"]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    # per kernel whose name starts so (the variants of one stage, launched
+    # side by side on two streams): the mean over its last --tail dispatches;
+    # one stage spans from the first start to the last end of its i-th
+    # dispatches
+    per = {}
+    for r in rows:
+        per.setdefault(r["Kernel_Name"].split("(")[0], []).append(
+            (int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out = []
+    for k, d in per.items():
+        d = d[-a.tail:]
+        m = sum((e - b) / 1e3 for b, e in d) / len(d)
+        out.append(f"# {k}: mean over its last {len(d)} dispatches (bench.py's kernel-timing region): "
+                   f"{m:.2f} us")
+    runs = [d[-a.tail:] for d in per.values()]
+    ns = min(len(d) for d in runs)
+    spans = [(max(d[i][1] for d in runs) - min(d[i][0] for d in runs)) / 1e3 for i in range(ns)]
+    mean = sum(spans) / ns
+    if len(per) > 1:
+        out.append(f"# one stage (first start to last end of {' and '.join(per)}): {mean:.2f} us "
+                   f"over {ns} stages")
     if a.bench_log:
         with open(a.bench_log) as fh:
             js = [json.loads(l) for l in fh if l.startswith('{"metric"')]
