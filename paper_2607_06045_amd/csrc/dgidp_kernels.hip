@@ -306,7 +306,10 @@ __device__ __forceinline__ double lnmean(double x, double y, double lx, double l
     const bool ser = fabs(d) < 1e-2 * s;
     const double r = frcp(ser ? s : lx - ly);
     const double f = d * r, f2 = f * f;
-    const double sv = 0.5 * s * (1.0 - f2 * (1.0 / 3.0 + f2 * (4.0 / 45.0 + f2 * (44.0 / 945.0))));
+    // 1/3 + f2 (4/45 + f2 44/945) = 44/945 (945/132 + f2 (21/11 + f2)): one
+    // literal per instruction
+    const double t = fma(f2, f2 + 21.0 / 11.0, 945.0 / 132.0) * f2;
+    const double sv = 0.5 * s * fma(-44.0 / 945.0, t, 1.0);
     return ser ? sv : f;
 }
 
@@ -317,7 +320,9 @@ __device__ __forceinline__ double inv_lnmean(double x, double y, double lx, doub
     const bool ser = fabs(d) < 1e-2 * s;
     const double r = frcp(ser ? s : d);
     const double f = d * r, f2 = f * f;
-    const double sv = (2.0 + f2 * (2.0 / 3.0 + f2 * (2.0 / 5.0 + f2 * (2.0 / 7.0)))) * r;
+    // 2/3 + f2 (2/5 + f2 2/7) = 2/7 (7/3 + f2 (7/5 + f2))
+    const double t = fma(f2, f2 + 7.0 / 5.0, 7.0 / 3.0) * f2;
+    const double sv = fma(2.0 / 7.0, t, 2.0) * r;
     return ser ? sv : (lx - ly) * r;
 }
 
@@ -1514,9 +1519,10 @@ void k_stage(StageArgs A)
                              pressure(uvol, g) < pmin ||
                              !(log(pressure(uvol, g)) - g * log(uvol[0]) >= lsm - kLocalTol)))
                     viol = 1;
-            } else if (A.limiter != DGIDP_LIMIT_NONE &&
-                       (uvol[0] < rmin || pressure(uvol, g) < pmin || uvol[0] != uvol[0])) {
-                viol = 1;
+            } else if (A.limiter != DGIDP_LIMIT_NONE) {
+                // p(uvol) >= pmin as 2 rho (E - pmin / (gamma - 1)) >= |m|^2 (rho >= rmin > 0)
+                const double gp = 2.0 * uvol[0] * (uvol[3] - pmin * ig1) - (uvol[1] * uvol[1] + uvol[2] * uvol[2]);
+                if (!(uvol[0] >= rmin) || !(gp >= 0.0)) viol = 1;
             }
         } else {
 #pragma unroll
