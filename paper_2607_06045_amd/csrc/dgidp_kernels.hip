@@ -381,18 +381,23 @@ __device__ __forceinline__ float inv_lnmeanf(float x, float y, float lx, float l
 // g(theta) = (E - pt/(gamma-1)) rho - |m|^2 / 2 >= 0, a quadratic in theta whose
 // admissible set along the ray is an interval [0, theta*] (p is concave).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double theta_p(const double* u0, const double* dc, double pt, double ig1)
+// The ray's direction is S c (S = Gamma = 4 for the volume faces' increments,
+// 1 otherwise): a power of two, so that S c is formed exactly inside the
+// fused multiply-adds.
+template <int S = 1>
+__device__ __forceinline__ double theta_p(const double* u0, const double* c, double pt, double ig1)
 {
     const double e0 = u0[3] - pt * ig1;
     const double g0 = u0[0] * e0 - 0.5 * (u0[1] * u0[1] + u0[2] * u0[2]);
     if (!(g0 > 0.0) || !(u0[0] > 0.0)) return 0.0;
     // full step admissible: the interval contains [0, 1]
-    const double r1 = u0[0] + dc[0];
+    const double r1 = fma((double)S, c[0], u0[0]);
     if (r1 > 0.0) {
-        const double m1 = u0[1] + dc[1], m2 = u0[2] + dc[2];
-        const double g1v = (u0[3] + dc[3] - pt * ig1) * r1 - 0.5 * (m1 * m1 + m2 * m2);
+        const double m1 = fma((double)S, c[1], u0[1]), m2 = fma((double)S, c[2], u0[2]);
+        const double g1v = fma((double)S, c[3], e0) * r1 - 0.5 * (m1 * m1 + m2 * m2);
         if (g1v >= 0.0) return 1.0;
     }
+    const double dc[4] = {S * c[0], S * c[1], S * c[2], S * c[3]};
     const double g1 = dc[0] * e0 + u0[0] * dc[3] - (u0[1] * dc[1] + u0[2] * dc[2]);
     const double g2 = dc[0] * dc[3] - 0.5 * (dc[1] * dc[1] + dc[2] * dc[2]);
     double root = 1.0;
@@ -570,10 +575,7 @@ __device__ __forceinline__ double volume_factor(const double* uFV, const double 
     // pressure: each face's increment scaled by Gamma = 2d = 4 (a zero
     // increment, as on a missing face, admits theta = 1 at an admissible uFV)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const double dc[4] = {4.0 * cf[j][0], 4.0 * cf[j][1], 4.0 * cf[j][2], 4.0 * cf[j][3]};
-        th = fmin(th, theta_p(uFV, dc, pt, ig1));
-    }
+    for (int j = 0; j < 4; ++j) th = fmin(th, theta_p<4>(uFV, cf[j], pt, ig1));
     // specific entropy: per face on [0, th].  The target ln(s_min (1 + 2^-40))
     // is capped at lsi lowered by 2^-41: with bounds from the low-order solution
     // lsi is the node's own low-order log entropy (where the node itself is the
