@@ -265,6 +265,44 @@ def test_full_size_quadrants247k_n4(oracle):
     assert abs(st["dt"] - sc["dt"]) <= 1e-14 * sc["dt"]
 
 
+def test_full_size_quadrants247k_rhs(oracle):
+    """The same workload's high- and low-order residuals on every node.  At this
+    size (49,348 element batches, 7% of them holding a mortar element) a stage
+    is two launches of the element kernel, one over the mortar batches and one
+    over the others, and so is the residual."""
+    spec = workload_mesh("quadrants247k")
+    s, M = pair(oracle, spec, 4)
+    x, y, m = M.geometry()
+    u = states.workload_state("quadrants247k", x, y)
+    s.upload(u)
+    w0 = oracle.basis(4)[1][0]
+    for which in (0, 1):
+        err = rate_err(s.rhs(which), M.rhs(u, which), u, x, y, w0)
+        print(f"quadrants247k N=4 rhs which={which} err={err:.2e}", flush=True)
+        assert err < TOL
+
+
+def test_full_size_quadrants247k_mixed(oracle):
+    """The two launches of a stage in the mixed mode: one SSP-RK3 step on every
+    node against the FP64 oracle, within the FP32 error bound of the mixed
+    path (2 (N+1) 20 2^-24 of the flux scale per unit time, 3 CFL of it per
+    step), no violations."""
+    import paper_2607_06045_amd as P
+    spec = workload_mesh("quadrants247k")
+    s, M = pair(oracle, spec, 4, precision=P.MIXED)
+    x, y, m = M.geometry()
+    u = states.workload_state("quadrants247k", x, y)
+    s.upload(u)
+    st = s.step(0.5)
+    c, sc = M.ssprk3(u, 0.5)
+    err = state_err(s.download(), c)
+    bound = 3 * 0.5 * 2 * 5 * 20 * 2.0 ** -24
+    print(f"quadrants247k N=4 mixed err={err:.2e} bound={bound:.2e}", flush=True)
+    assert 0.0 < err < bound
+    assert st["violations"] == 0
+    assert abs(st["dt"] - sc["dt"]) <= 1e-14 * sc["dt"]
+
+
 @pytest.mark.parametrize("on_device", [False, True])
 def test_state_upload_rejects_inadmissible(on_device):
     """Upload from host memory and from a device tensor: a NaN density, an
