@@ -1344,16 +1344,17 @@ void k_stage(StageArgs A)
         im = 4.0 * frcp(hx * hy) * sTw[1][a] * sTw[1][b];
         const double cw[4] = {fweight(0), fweight(1), fweight(2), fweight(3)};
         const int fi[4] = {fidx(0), fidx(1), fidx(2), fidx(3)};
-        const double cs[4] = {onf[0] ? 1.0 : 0.0, onf[1] ? 1.0 : 0.0, onf[2] ? 1.0 : 0.0, onf[3] ? 1.0 : 0.0};
-        const int fs[4] = {G::fslot(0, b), G::fslot(1, b), G::fslot(2, a), G::fslot(3, a)};
+        // the surface terms of the element faces the node lies on: at most one
+        // x face (0 or 1) and one y face (2 or 3), weight 0 where it lies on none
+        const double csx = onf[0] || onf[1] ? 1.0 : 0.0, csy = onf[2] || onf[3] ? 1.0 : 0.0;
+        const int fsx = G::fslot(a == 0 ? 0 : 1, b), fsy = G::fslot(b == 0 ? 2 : 3, a);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double r = 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) r = fma(cw[j], sFV(v, fi[j]), r);
-            // surface terms of the element faces the node lies on
-#pragma unroll
-            for (int f = 0; f < 4; ++f) r = fma(cs[f], sPair[le][v][fs[f]], r);
+            r = fma(csx, sPair[le][v][fsx], r);
+            r = fma(csy, sPair[le][v][fsy], r);
             RLO[v] = r;
         }
         if constexpr (MORT) {
@@ -1457,9 +1458,11 @@ void k_stage(StageArgs A)
         }
         // the faces' increments dt / m_i w (f^HO - f^FV), signed (zero for missing faces)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            const double wd = dtm * fweight(j);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) cf[j][v] = dtm * antidiff(j, v);
+            for (int v = 0; v < 4; ++v) cf[j][v] = wd * (sPair[le][v][hslot(j)] - sFV(v, fidx(j)));
+        }
         if (A.limiter != DGIDP_LIMIT_NONE) {
             if (PURE) {
                 th = volume_factor<true>(uFV, cf, rlf, pmin, rhi, lsm, lsi, g, ig1);
@@ -1486,15 +1489,12 @@ void k_stage(StageArgs A)
         double tf[4];
         // face factor: the smaller of its two node factors; blended:
         // (1 - w) theta_pos + w theta_local
-        // (a missing face reads the node itself and takes 0)
-        const bool has[4] = {a > 0, a < N, b > 0, b < N};
-        const int qn4[4] = {has[0] ? q - 1 : q, has[1] ? q + 1 : q, has[2] ? q - n : q, has[3] ? q + n : q};
+        // (a missing face reads the node itself; its increment is zero)
+        const int qn4[4] = {a > 0 ? q - 1 : q, a < N ? q + 1 : q, b > 0 ? q - n : q, b < N ? q + n : q};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double t = COMB ? (1.0 - w_e) * fmin(th, sTh(qn4[j])) + w_e * fmin(thl, sB[le][0][qn4[j]])
-                                  : fmin(th, sTh(qn4[j]));
-            tf[j] = has[j] ? t : 0.0;
-        }
+        for (int j = 0; j < 4; ++j)
+            tf[j] = COMB ? (1.0 - w_e) * fmin(th, sTh(qn4[j])) + w_e * fmin(thl, sB[le][0][qn4[j]])
+                         : fmin(th, sTh(qn4[j]));
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             uvol[v] = uFV[v] + tf[0] * cf[0][v] + tf[1] * cf[1][v] + tf[2] * cf[2][v] + tf[3] * cf[3][v];
