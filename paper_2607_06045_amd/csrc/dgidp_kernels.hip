@@ -1733,7 +1733,8 @@ __global__ __launch_bounds__(256) void k_lowbounds(LoBoundsArgs A)
 {
     constexpr int n = N + 1, NN = n * n;
     const Tab<N>& tb = T<N>();
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // (contiguous node ranges per XCD: the neighbours' values mostly in the same L2)
+    const size_t i = (size_t)xcd_batch(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= (size_t)A.E * NN) return;
     const int e = (int)(i / NN), q = (int)(i - (size_t)e * NN), a = q % n, b = q / n;
     double lo = __builtin_inf(), hi = -__builtin_inf(), ls = __builtin_inf();
@@ -1854,7 +1855,9 @@ __global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
     const double g = A.gamma;
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
-    const int e = blockIdx.x * EPB + le;
+    // (contiguous element ranges per XCD, as in the stage kernel: the face
+    // neighbours' traces are then mostly in the same L2)
+    const int e = xcd_batch(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = tid < NT && e < A.E;
     if (tid < n) {
         sTw[0][tid] = tb.w[tid];
