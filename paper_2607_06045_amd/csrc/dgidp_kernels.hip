@@ -57,12 +57,12 @@ __device__ __forceinline__ int xcd_batch(int bid, int nb)
 
 // launch geometry per degree: one-wave blocks of 4 elements at N = 3 (the
 // phase barriers stay inside a wave and a late block holds less work),
-// two-wave blocks of 5 elements at N = 4 (125 of 128 lanes busy; with the
-// pairs evaluated in two passes a block needs 25.8 KB of LDS, so six blocks,
-// twelve waves, fill a compute unit to the three waves per SIMD that the
-// registers allow).  Three-wave blocks of 7 elements (175 of 192 lanes, 40 KB
-// of LDS with all pairs stored at once, four blocks per CU) took 410.9
-// against 385.4 us per launch on the 246,736-leaf workload.
+// two-wave blocks of 5 elements at N = 4 (125 of 128 lanes busy; a block
+// needs 19.6 KB of LDS, so eight blocks, sixteen waves, fill a compute unit
+// to the four waves per SIMD that the conforming variant's registers allow).
+// Three-wave blocks of 7 elements (175 of 192 lanes, 40 KB of LDS with all
+// pairs stored at once, four blocks per CU) took 410.9 against 385.4 us per
+// launch on the 246,736-leaf workload.
 template <int N>
 struct Geo {
     static constexpr int n = N + 1, NN = n * n;
@@ -74,12 +74,10 @@ struct Geo {
     static constexpr int NPL = n * (n - 1) / 2;    // node pairs per line
     static constexpr int NP = 2 * n * NPL;         // node pairs per element
     static constexpr int NF = 2 * N * n;           // interior subcell faces per element
-    // LDS variable strides of the state and primitive arrays: unpadded.  At
-    // N = 3 padding to an odd element stride cost three of twelve blocks per
-    // compute unit (15616 against 12544 bytes per block), more than the bank
-    // conflicts it saved; at N = 4 a pad of one made no difference (378.3
-    // against 378.1 us per launch on the 246,736-leaf workload).
-    static constexpr int PU = NN;  // sU variable stride
+    // LDS variable stride of the primitive array: unpadded.  At N = 3 padding
+    // to an odd element stride cost blocks per compute unit, more than the
+    // bank conflicts it saved; at N = 4 a pad of one made no difference
+    // (288.7 against 289.8 us per stage on the 246,736-leaf workload).
     static constexpr int PR = NN;  // sR variable stride
     // x and y pairs in two passes where the x pairs fill whole thread rounds
     // (N = 4); the pair buffer then needs the larger of the mortar staging
@@ -836,9 +834,8 @@ void k_stage(StageArgs A)
     double un4[4] = {0, 0, 0, 0};
     double u0[4] = {0, 0, 0, 0};
     // the low-order surface term of this lane's face node, kept in registers
-    // until phase 5 frees sU, which then carries it to the node's own thread
+    // until phase 5 frees pair slots, which then carry it to the node's own thread
     double fterm[4] = {0, 0, 0, 0};
-    bool blk_mortar = false;
     // local bounds: own log entropy; for face lanes the density range and the
     // smallest log entropy of the bar states across this lane's face node
     double ls_own = 0.0;
@@ -916,21 +913,16 @@ void k_stage(StageArgs A)
                     sPair[le][v][MB + (ff * 2 + 0) * n + fk] = onb[v];
                     sPair[le][v][MB + (ff * 2 + 1) * n + fk] = us1[v];
                 }
-                blk_mortar = true;
             } else if (MORT) {
                 // small side: stage the large face trace for the interpolation
                 double w[4];
                 load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), w);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) sPair[le][v][ff * n + fk] = w[v];
-                blk_mortar = true;
             }
         }
     }
-    // (every batch of the mortar launch holds a mortar element)
     __syncthreads();
-    constexpr bool any_mortar = MORT;
-    (void)blk_mortar;
     double dt;
     if (A.dtmax) {
         const double m = wave_max(dtpart);
@@ -1086,7 +1078,7 @@ void k_stage(StageArgs A)
             }
         }
     }
-    if constexpr (any_mortar) {
+    if constexpr (MORT) {  // (every batch of the mortar launch holds a mortar element)
         __syncthreads();
         // ---- phase 3: large sides publish and project the mortar fluxes ----
         const bool large = fnode && fcode_f >= 0 && !fm_small(fcode_f);
