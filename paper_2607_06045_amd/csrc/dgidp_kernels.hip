@@ -2484,6 +2484,21 @@ __global__ void k_check_state(int total_nodes, int NN, double g, const double* u
     if (!ok) atomicMin(bad, (unsigned long long)i);
 }
 
+// dt = cfl / (the maximum over the dt kernel's accumulators), once per step:
+// one wave reads the kDtSpread accumulators; the stage kernels then read the
+// stored value (a per-wave reduction in every block of the first stage would
+// read the kDtSpread cache lines once per wave)
+__global__ __launch_bounds__(64) void k_dt_final(const unsigned long long* dtmax, double cfl, double* dt_out,
+                                                 DevStats* st)
+{
+    const double m = wave_max(__longlong_as_double((long long)dtmax[threadIdx.x * kDtStride]));
+    if (threadIdx.x == 0) {
+        const double dt = cfl / m;
+        *dt_out = dt;
+        if (st) st->dt = dt;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -2505,6 +2520,16 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.dtmax = dt.dtmax;
     A.cfl = dt.cfl;
     A.dt_out = dt.dt_out;
+    // on a large mesh dt is reduced once, by k_dt_final, and the stage reads
+    // it; on a small one (fewer than kFinalMin batches) the extra launch costs
+    // more than the stage's own per-wave reduction
+    constexpr int kFinalMin = 16384;
+    if (dt.dtmax && dt.dt_out && mode == MODE_STAGE && (m.E + G::EPB - 1) / G::EPB >= kFinalMin) {
+        static_assert(kDtSpread == 64, "one wave reduces the dt accumulators");
+        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(64), 0, s, dt.dtmax, dt.cfl, dt.dt_out, st);
+        A.dt = dt.dt_out;
+        A.dtmax = nullptr;
+    }
     A.fnbr = m.fnbr;
     A.fnbr2 = m.fnbr2;
     A.fmort = m.fmort;
