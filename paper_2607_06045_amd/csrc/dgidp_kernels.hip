@@ -708,7 +708,10 @@ template <int N>
 __device__ __forceinline__ int face_q(int f, int k)
 {
     constexpr int n = N + 1;
-    return f == 0 ? k * n : (f == 1 ? k * n + N : (f == 2 ? k : N * n + k));
+    // x faces (0, 1) run along a column, y faces (2, 3) along a row; the odd
+    // face of each pair is N columns or N rows further on
+    const int hi = f & 1;
+    return f < 2 ? k * n + hi * N : k + hi * (N * n);
 }
 
 template <int N>
@@ -818,13 +821,14 @@ void k_stage(StageArgs A)
         sTw[0][tid] = tb.w[tid];
         sTw[1][tid] = tb.winv[tid];
     }
-    if (tid < NN) sS[tid / n][tid % n] = tb.S[tid / n][tid % n];
+    if (tid < NN) (&sS[0][0])[tid] = (&tb.S[0][0])[tid];
 
     // ---- phase 1: own node into LDS; face-node role and its remote loads ----
     double hx = 1.0, hy = 1.0;
     int fcode[4] = {-1, -1, -1, -1};
     const bool fnode = act && q < NFN;       // this lane also evaluates one face node
     const int ff = q / n, fk = q - (q / n) * n;  // its face and position
+    const int qfo = face_q<N>(ff, fk), qfn = face_q<N>(ff ^ 1, fk);  // the face node, its neighbour's
     int fcode_f = -1, fnb = 0, fnb2 = -1, bk = 0;
     double onb[4];  // conforming neighbour state (boundary: exterior state) across face ff at fk
     double us1[4];  // large side: the second small element's trace at position fk
@@ -896,7 +900,7 @@ void k_stage(StageArgs A)
         if (fnode) {
             fcode_f = fcode[ff];
             if (fcode_f == -1) {
-                load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
+                load_u<N>(A.uin, fnb, qfn, onb);
             } else if (fcode_f < -1) {
                 const int j = (-2 - fcode_f) * n + fk;
                 bk = A.bkind[j];
@@ -906,8 +910,8 @@ void k_stage(StageArgs A)
                 // large side: both small traces at position fk, kept in
                 // registers for the mortar-node fluxes and staged for the
                 // sparse low-order pairs of the other positions
-                load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), onb);
-                load_u<N>(A.uin, fnb2, face_q<N>(ff ^ 1, fk), us1);
+                load_u<N>(A.uin, fnb, qfn, onb);
+                load_u<N>(A.uin, fnb2, qfn, us1);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     sPair[le][v][MB + (ff * 2 + 0) * n + fk] = onb[v];
@@ -916,7 +920,7 @@ void k_stage(StageArgs A)
             } else if (MORT) {
                 // small side: stage the large face trace for the interpolation
                 double w[4];
-                load_u<N>(A.uin, fnb, face_q<N>(ff ^ 1, fk), w);
+                load_u<N>(A.uin, fnb, qfn, w);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) sPair[le][v][ff * n + fk] = w[v];
             }
@@ -942,7 +946,7 @@ void k_stage(StageArgs A)
     const double hff = ff < 2 ? hy : hx;
     if (fnode) {
         NodeP own;  // the face node's state
-        LDS_NODE(own, face_q<N>(ff, fk));
+        LDS_NODE(own, qfo);
         if (fcode_f < 0) {
             NodeP o;
             if (fcode_f == -1) {
@@ -1503,9 +1507,8 @@ void k_stage(StageArgs A)
         double* po = A.uout + ((unsigned)e * 4u * NN + (unsigned)q);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            double r = A.b * uvol[v];
-            if (A.a != 0.0) r += A.a * un4[v];
-            po[v * NN] = r;
+            // (un4 is zero where a = 0: the first stage's input is u^n itself)
+            po[v * NN] = fma(A.a, un4[v], A.b * uvol[v]);
         }
         if (nmf == 0) {
             if (PURE) {
