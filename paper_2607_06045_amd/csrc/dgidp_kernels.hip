@@ -785,7 +785,7 @@ void k_stage(StageArgs A)
     constexpr bool LOC = LIMK >= 1, COMB = LIMK == 2, BAR = LIMK == 1 || LIMK == 2;
     constexpr bool PURE = LIMK == 1 || LIMK == 3;
     constexpr int n = G::n, NN = G::NN, EPB = G::EPB, NT = G::NT, NFN = G::NFN;
-    constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN;
+    constexpr int NPL = G::NPL, NP = G::NP, NF = G::NF, PPT = NP / NN, PP = G::PP;
     static_assert(NP % NN == 0, "pair split");
     constexpr bool DSTAT = (n * NPL) % NN == 0, SPLIT = G::SPLIT;
     constexpr int XH = n * NPL;  // SPLIT: the x lines' telescoped fluxes follow the pair slots
@@ -816,6 +816,7 @@ void k_stage(StageArgs A)
     const int xb = xcd_batch(blockIdx.x, gridDim.x);
     const int e = (A.blist ? A.blist[A.boff + xb] : xb) * EPB + le;
     double* const sRe = &sR[0][0][0] + le * 8 * NN;  // element le's rows, flat
+    double* const sPe = &sPair[0][0][0] + le * 4 * PP;  // element le's pair buffer, flat
     const bool act = tid < NT && e < A.E;
     if (tid < n) {
         sTw[0][tid] = tb.w[tid];
@@ -1335,7 +1336,7 @@ void k_stage(StageArgs A)
     int slot0 = -1, slot1 = -1, nmf = 0;
     double im = 1.0;  // 1 / m_i
     // antidiffusive flux w (f^HO - f^FV) of face j, signed as its weight, variable v
-    auto antidiff = [&](int j, int v) { return fweight(j) * (sPair[le][v][hslot(j)] - sFV(v, fidx(j))); };
+    auto antidiff = [&](int j, int v) { return fweight(j) * (sPe[v * PP + hslot(j)] - sFV(v, fidx(j))); };
     if (act) {
         im = 4.0 * frcp(hx * hy) * sTw[1][a] * sTw[1][b];
         const double cw[4] = {fweight(0), fweight(1), fweight(2), fweight(3)};
@@ -1349,28 +1350,30 @@ void k_stage(StageArgs A)
             double r = 0.0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) r = fma(cw[j], sFV(v, fi[j]), r);
-            r = fma(csx, sPair[le][v][fsx], r);
-            r = fma(csy, sPair[le][v][fsy], r);
+            r = fma(csx, sPe[v * PP + fsx], r);
+            r = fma(csy, sPe[v * PP + fsy], r);
             RLO[v] = r;
         }
         if constexpr (MORT) {
+            // a node lies on at most one x face (a = 0 or N) and one y face (b = 0 or
+            // N): slot 0 takes the mortar of its x face, slot 1 that of its y face
+            const int cx = onf[0] ? fcode[0] : (onf[1] ? fcode[1] : -1);
+            const int cy = onf[2] ? fcode[2] : (onf[3] ? fcode[3] : -1);
+            auto slot_of = [&](int code, int k) {
+                const int S3 = fm_mortar(code) * 3 * n;
+                return fm_small(code) ? S3 + n + fm_half(code) * n + k : S3 + k;
+            };
+            if (cx >= 0) {
+                slot0 = slot_of(cx, b);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const int code = fcode[f];
-                if (!onf[f] || code < 0) continue;
-                const int S = fm_mortar(code), k = f < 2 ? b : a;
-                const int sid = fm_small(code) ? S * 3 * n + n + fm_half(code) * n + k : S * 3 * n + k;
-                if (nmf == 0) {
-                    slot0 = sid;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) dS0[v] = A.slot[(size_t)sid * kSlotW + 4 + v];
-                } else {
-                    slot1 = sid;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) dS1[v] = A.slot[(size_t)sid * kSlotW + 4 + v];
-                }
-                ++nmf;
+                for (int v = 0; v < 4; ++v) dS0[v] = A.slot[(size_t)slot0 * kSlotW + 4 + v];
             }
+            if (cy >= 0) {
+                slot1 = slot_of(cy, a);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dS1[v] = A.slot[(size_t)slot1 * kSlotW + 4 + v];
+            }
+            nmf = (cx >= 0) + (cy >= 0);
         }
     }
     if (MODE == MODE_RHS_LOW || MODE == MODE_RHS_HIGH) {
@@ -1457,7 +1460,7 @@ void k_stage(StageArgs A)
         for (int j = 0; j < 4; ++j) {
             const double wd = dtm * fweight(j);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) cf[j][v] = wd * (sPair[le][v][hslot(j)] - sFV(v, fidx(j)));
+            for (int v = 0; v < 4; ++v) cf[j][v] = wd * (sPe[v * PP + hslot(j)] - sFV(v, fidx(j)));
         }
         if (A.limiter != DGIDP_LIMIT_NONE) {
             if (PURE) {
@@ -1524,7 +1527,7 @@ void k_stage(StageArgs A)
         } else {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (j >= nmf) break;
+                if ((j == 0 ? slot0 : slot1) < 0) continue;
                 const double* dS = j == 0 ? dS0 : dS1;
                 double c[4], dc[4];
                 bool fin = true;
