@@ -54,6 +54,16 @@ __device__ __forceinline__ int xcd_batch(int bid, int nb)
     const int x = bid & 7, j = bid >> 3;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
 }
+// the same ranges walked from their ends: a kernel that reads what the
+// previous one wrote takes the most recently written batches, the ones most
+// likely still held by the memory-side cache, first
+__device__ __forceinline__ int xcd_batch_rev(int bid, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = bid & 7, j = bid >> 3;
+    const int len = x < r ? q + 1 : q;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + len - 1 - j;
+}
 
 // launch geometry per degree: one-wave blocks of 4 elements at N = 3 (the
 // phase barriers stay inside a wave and a late block holds less work),
@@ -1854,8 +1864,9 @@ __global__ __launch_bounds__(kDtBlock) void k_dt(DtArgs A)
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
     // (contiguous element ranges per XCD, as in the stage kernel: the face
-    // neighbours' traces are then mostly in the same L2)
-    const int e = xcd_batch(blockIdx.x, gridDim.x) * EPB + le;
+    // neighbours' traces are then mostly in the same L2; each range from its
+    // end, where the stage before this kernel finished writing)
+    const int e = xcd_batch_rev(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = tid < NT && e < A.E;
     if (tid < n) {
         sTw[0][tid] = tb.w[tid];
