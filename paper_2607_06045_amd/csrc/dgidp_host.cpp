@@ -536,7 +536,7 @@ DtSource stored_dt(const dgidp_ctx* c)
 // one limited forward-Euler stage: uout = a un + b FE(uin), with the mesh
 // arrays and per-stage buffers of dm
 int stage_on(dgidp_ctx* ctx, const DevMesh& dm, const double* uin, const double* un, double* uout,
-             double a, double b, DevStats* st, const DtSource& dt)
+             double a, double b, DevStats* st, const DtSource& dt, bool rev = false)
 {
     const KernelParams kp = kparams(ctx);
     // combined limiting weighs its factors with the indicator of the stage's input
@@ -547,7 +547,7 @@ int stage_on(dgidp_ctx* ctx, const DevMesh& dm, const double* uin, const double*
         (launch_rhs(ctx->p.N, dm, kp, uin, DGIDP_RHS_LOW, dm.dlo, ctx->stream) ||
          launch_lowbounds(ctx->p.N, dm, kp.gamma, uin, dm.dlo, dt, dm.lsv, dm.lob, ctx->stream)))
         return fail(ctx, DGIDP_E_DEVICE, "low-order bounds launch failed");
-    if (launch_stage(ctx->p.N, dm, kp, uin, un, uout, a, b, dt, st, ctx->stream))
+    if (launch_stage(ctx->p.N, dm, kp, uin, un, uout, a, b, dt, st, ctx->stream, rev))
         return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");
     if (launch_mortar(ctx->p.N, dm, uout, b, st, ctx->stream, kp.gamma, kp.limiter))
         return fail(ctx, DGIDP_E_DEVICE, "mortar kernel launch failed");
@@ -555,9 +555,9 @@ int stage_on(dgidp_ctx* ctx, const DevMesh& dm, const double* uin, const double*
 }
 
 int stage(dgidp_ctx* ctx, const double* uin, const double* un, double* uout, double a, double b,
-          DevStats* st, const DtSource& dt)
+          DevStats* st, const DtSource& dt, bool rev = false)
 {
-    return stage_on(ctx, ctx->dm, uin, un, uout, a, b, st, dt);
+    return stage_on(ctx, ctx->dm, uin, un, uout, a, b, st, dt, rev);
 }
 
 }  // namespace
@@ -1028,7 +1028,7 @@ static int ssprk3(dgidp_ctx* ctx, dgidp_stats* s, const DtSource& first_dt)
     const DtSource dt = stored_dt(ctx);
     int rc;
     if ((rc = stage(ctx, ctx->U, nullptr, ctx->W1, 0.0, 1.0, st, first_dt))) return rc;
-    if ((rc = stage(ctx, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, st, dt))) return rc;
+    if ((rc = stage(ctx, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, st, dt, true))) return rc;
     if ((rc = stage(ctx, ctx->W2, ctx->U, ctx->U, 1.0 / 3.0, 2.0 / 3.0, st, dt))) return rc;
     return 0;
 }
@@ -1178,7 +1178,7 @@ int dgidp_step_noalloc(dgidp_ctx* ctx, double cfl)
     stored.dt = dtp;
     int rc;
     if ((rc = stage_on(ctx, dm, ctx->U, nullptr, W1, 0.0, 1.0, nullptr, first)) ||
-        (rc = stage_on(ctx, dm, W1, ctx->U, W2, 0.75, 0.25, nullptr, stored)) ||
+        (rc = stage_on(ctx, dm, W1, ctx->U, W2, 0.75, 0.25, nullptr, stored, true)) ||
         (rc = stage_on(ctx, dm, W2, ctx->U, ctx->U, 1.0 / 3.0, 2.0 / 3.0, nullptr, stored)))
         return rc;
     return 0;
@@ -1211,7 +1211,7 @@ int dgidp_time_kernels(dgidp_ctx* ctx, int reps, double* ms)
         if (launch_stage(ctx->p.N, ctx->dm, kp, ctx->U, nullptr, ctx->W1, 0.0, 1.0, stored_dt(ctx), nullptr,
                          ctx->stream) ||
             launch_stage(ctx->p.N, ctx->dm, kp, ctx->W1, ctx->U, ctx->W2, 0.75, 0.25, stored_dt(ctx), nullptr,
-                         ctx->stream) ||
+                         ctx->stream, true) ||
             launch_stage(ctx->p.N, ctx->dm, kp, ctx->W2, ctx->U, ctx->W1, 1.0 / 3.0, 2.0 / 3.0, stored_dt(ctx),
                          nullptr, ctx->stream))
             return fail(ctx, DGIDP_E_DEVICE, "stage kernel launch failed");

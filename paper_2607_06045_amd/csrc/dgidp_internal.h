@@ -149,9 +149,12 @@ int mlp_grad_step(MlpState* s, const float* x, const float* t, int64_t B, float 
                   float* loss_host, hipStream_t st);
 
 // launchers (dgidp_kernels.hip)
+// rev: the conforming launch of a split stage walks each XCD's batch range from
+// its end (the middle stage of SSP-RK3, so that every stage starts where the
+// kernel before it finished writing its input)
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
                  const double* un, double* uout, double a, double b, const DtSource& dt,
-                 DevStats* st, hipStream_t s);
+                 DevStats* st, hipStream_t s, bool rev = false);
 int launch_rhs(int N, const DevMesh& m, const KernelParams& kp, const double* u, int which,
                double* du, hipStream_t s);
 int launch_mortar(int N, const DevMesh& m, double* uout, double b, DevStats* st, hipStream_t s,

@@ -708,6 +708,7 @@ struct StageArgs {
     int E;
     double gamma, beta;
     double ig1;  // 1 / (gamma - 1)
+    int rev;     // walk the XCD batch ranges from their ends (conforming variant only)
     int limiter;
     int vflux;  // two-point volume flux: DGIDP_FLUX_RANOCHA or DGIDP_FLUX_CHANDRASHEKAR
     DevStats* st;
@@ -823,7 +824,7 @@ void k_stage(StageArgs A)
     const double g = A.gamma, ig1 = A.ig1;
     const int tid = threadIdx.x;
     const int le = tid / NN, q = tid - le * NN, a = q % n, b = q / n;
-    const int xb = xcd_batch(blockIdx.x, gridDim.x);
+    const int xb = !MORT && A.rev ? xcd_batch_rev(blockIdx.x, gridDim.x) : xcd_batch(blockIdx.x, gridDim.x);
     const int e = (A.blist ? A.blist[A.boff + xb] : xb) * EPB + le;
     double* const sRe = &sR[0][0][0] + le * 8 * NN;  // element le's rows, flat
     double* const sPe = &sPair[0][0][0] + le * 4 * PP;  // element le's pair buffer, flat
@@ -2522,7 +2523,7 @@ __global__ __launch_bounds__(64) void k_dt_final(const unsigned long long* dtmax
 template <int N>
 static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, const double* un,
                    double* uout, double a, double b, const DtSource& dt, DevStats* st, int mode,
-                   hipStream_t s)
+                   hipStream_t s, bool rev = false)
 {
     using G = Geo<N>;
     StageArgs A;
@@ -2559,6 +2560,7 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
     A.E = m.E;
     A.gamma = kp.gamma;
     A.ig1 = 1.0 / (kp.gamma - 1.0);
+    A.rev = 0;
     A.beta = kp.beta;
     A.limiter = kp.limiter;
     A.vflux = kp.vflux;
@@ -2593,7 +2595,11 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
             hipLaunchKernelGGL((k_stage<N, MD, MX, LK, true>), dim3(m.nbm), dim3(G::BS), 0, s, A);
         }
         if (nb > m.nbm) {
+            // (only this launch may walk its ranges backwards: its blocks cost
+            // alike, where the mortar launch and an unsplit stage start the
+            // costlier mortar batches first on purpose)
             A.boff = m.nbm;
+            A.rev = rev ? 1 : 0;
             hipLaunchKernelGGL((k_stage<N, MD, MX, LK, false>), dim3(nb - m.nbm), dim3(G::BS), 0, s, A);
         }
     };
@@ -2627,11 +2633,11 @@ static int stage_N(const DevMesh& m, const KernelParams& kp, const double* uin, 
 
 int launch_stage(int N, const DevMesh& m, const KernelParams& kp, const double* uin,
                  const double* un, double* uout, double a, double b, const DtSource& dt,
-                 DevStats* st, hipStream_t s)
+                 DevStats* st, hipStream_t s, bool rev)
 {
     if (m.E == 0) return 0;
-    if (N == 3) return stage_N<3>(m, kp, uin, un, uout, a, b, dt, st, MODE_STAGE, s);
-    if (N == 4) return stage_N<4>(m, kp, uin, un, uout, a, b, dt, st, MODE_STAGE, s);
+    if (N == 3) return stage_N<3>(m, kp, uin, un, uout, a, b, dt, st, MODE_STAGE, s, rev);
+    if (N == 4) return stage_N<4>(m, kp, uin, un, uout, a, b, dt, st, MODE_STAGE, s, rev);
     return -1;
 }
 
